@@ -1,0 +1,180 @@
+/*
+ * lofp.h -- C-ABI of the MI355X (gfx950) Feynman path-sum library.
+ *
+ * The library computes the exact amplitude <T|U_P|S> of a Fock input S and a
+ * photon-detection pattern T through layers of locally connected two-mode
+ * beam splitters (Sec. II of the paper).  A path is the sequence of
+ * intermediate Fock configurations between beam splitters; its weight is the
+ * product of single-beam-splitter transition amplitudes (Appendix) and the
+ * amplitude is the sum over valid paths (Eq. (1)).
+ *
+ * Conventions (all calls):
+ *   - Modes are numbered 0..m-1 from the top of the circuit.
+ *   - A beam splitter acts on the adjacent modes (a, a+1); mode a is its upper
+ *     port (index 1 in Eq. (bs_matrix)), theta and phi are the two angles of
+ *     Eq. (bs_matrix): [[cos t, -e^{-i p} sin t], [e^{i p} sin t, cos t]],
+ *     rows = output ports, columns = input ports.
+ *   - Layers are applied in the order given; inside a layer beam splitters
+ *     must act on disjoint modes.  Any angle values are accepted.
+ *   - S and T are int32 occupation vectors of length m.  If sum(S) != sum(T)
+ *     the amplitude is exactly 0 (photon number is conserved, Sec. II).
+ *   - Complex results are two doubles {re, im}.
+ *   - Every call returns a lofp_status; on anything but LOFP_OK a message is
+ *     available from lofp_last_error() (thread-local, valid until the next
+ *     call on the same thread).  On error no output is written.
+ *   - Results are bit-reproducible for a fixed (circuit, S, T, opts) and do
+ *     not depend on the other patterns of the batch.
+ *
+ * Limits: m <= 32 modes, total photon number n <= 64 and at most 15 photons
+ * in one mode of S or T (LOFP_ENOTSUP otherwise).  Non-adjacent pairs are
+ * rejected with LOFP_ENOTSUP.
+ */
+#ifndef LOFP_H
+#define LOFP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LOFP_OK = 0,
+    LOFP_EINVAL = 1,   /* malformed argument (null pointer, bad mode, ...) */
+    LOFP_ENOMEM = 2,   /* device or host allocation failed, or a state space
+                          exceeds the 32-bit index range                     */
+    LOFP_ENOTSUP = 3,  /* valid request outside the supported limits        */
+    LOFP_EDEVICE = 4   /* HIP runtime error (message names the call)        */
+} lofp_status;
+
+/* One beam splitter, Eq. (bs_matrix).  b must equal a + 1. */
+typedef struct {
+    int32_t a, b;
+    double theta, phi;
+} lofp_bs;
+
+typedef struct {
+    double re, im;
+} lofp_c128;
+
+/* Opaque circuit handle.  Owns a copy of the layer list, the light-cone
+ * (reach) tables and, once a device call has been made, the device copy of
+ * the beam-splitter transition tables.  Immutable after creation; calls on
+ * one handle from several threads are serialised internally. */
+typedef struct lofp_circuit_s *lofp_circuit;
+
+enum {
+    LOFP_METHOD_AUTO = 0,     /* path sum for every workload                 */
+    LOFP_METHOD_PATHSUM = 1,  /* frontier split + depth-first path sum       */
+    LOFP_METHOD_CONTRACT = 2  /* mode-axis layer-block contraction (Sec. II.C) */
+};
+
+enum {
+    LOFP_PREC_FP64 = 0,       /* products, tables and sums in FP64           */
+    LOFP_PREC_FP32 = 1        /* path products in FP32; tables and sums FP64 */
+};
+
+typedef struct {
+    int32_t method;        /* LOFP_METHOD_*                                    */
+    int32_t precision;     /* LOFP_PREC_*                                      */
+    int32_t fwd_layer;     /* frontier cut: forward frontier after this many
+                              layers (-1 = chosen by the planner)             */
+    int32_t bwd_layer;     /* backward frontier at this layer boundary
+                              (-1 = planner); fwd_layer <= bwd_layer          */
+    int32_t record_timing; /* 1: time each phase with HIP events (adds a
+                              stream synchronisation at the end of the call) */
+    int32_t reserved[3];
+} lofp_opts;
+
+/* Per-call statistics (filled when a non-null pointer is passed). */
+typedef struct {
+    int32_t batch;            /* patterns in the call                          */
+    int32_t fwd_layer;        /* layer boundaries actually used                */
+    int32_t bwd_layer;
+    int32_t dfs_levels;       /* beam splitters enumerated depth-first         */
+    int64_t frontier_states;  /* forward frontier entries over the batch       */
+    int64_t backward_states;  /* backward frontier entries over the batch      */
+    int64_t bfs_states;       /* states produced by all frontier expansions    */
+    int64_t dfs_leaves;       /* complete middle paths evaluated               */
+    int64_t dfs_edges;        /* depth-first tree edges taken (incl. leaves)   */
+    int64_t transitions;      /* contraction: cut-to-cut state transitions     */
+    double ms_plan;           /* record_timing: bounds + state-space tables    */
+    double ms_forward;        /*   forward frontier expansion                  */
+    double ms_backward;       /*   backward frontier expansion                 */
+    double ms_dfs;            /*   depth-first kernel                          */
+    double ms_reduce;         /*   final compensated reduction                 */
+    double ms_contract;       /*   contraction kernel                          */
+    double ms_total;          /*   whole call on the stream                    */
+} lofp_stats;
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char *lofp_last_error(void);
+
+/* Library version string. */
+const char *lofp_version(void);
+
+/* Build a circuit from n_layers layers; layer k holds layer_len[k] beam
+ * splitters, stored consecutively in bs (host memory, copied).
+ * Sec. II: the interferometer is a list of layers of two-mode beam splitters
+ * with parameters (theta, phi).  Does not touch the GPU.
+ * Errors: EINVAL for m < 2, negative lengths, a or b out of range, a >= b,
+ * or a mode used twice in one layer; ENOTSUP for b != a + 1 or m > 32. */
+lofp_status lofp_circuit_create(int32_t m, int32_t n_layers, const int32_t *layer_len,
+                                const lofp_bs *bs, lofp_circuit *out);
+
+lofp_status lofp_circuit_destroy(lofp_circuit c);
+
+/* Light cone of one waveguide (Sec. II.B, Fig. light_cones): the output
+ * waveguide of mode `mode` after `layer` layers (0 <= layer <= D) receives
+ * photons only from inputs [*past_lo, *past_hi] and sends them only to
+ * outputs [*fut_lo, *fut_hi] (0-based, inclusive).  Host only. */
+lofp_status lofp_light_cone(lofp_circuit c, int32_t layer, int32_t mode, int32_t *past_lo,
+                            int32_t *past_hi, int32_t *fut_lo, int32_t *fut_hi);
+
+/* Cut bounds for one (S, T) (Sec. II.B light cones, tightened by photon
+ * conservation): lo[t*(m-1)+r] <= #photons in modes 0..r after t layers
+ * <= hi[t*(m-1)+r], for t = 0..D, r = 0..m-2.  lo/hi: host arrays of
+ * (D+1)*(m-1) int32.  *feasible = 0 when no valid path exists.  Host only. */
+lofp_status lofp_bounds(lofp_circuit c, const int32_t *S, const int32_t *T, int32_t *lo,
+                        int32_t *hi, int32_t *feasible);
+
+/* Single-beam-splitter transition table (Appendix): out[x1*(N+1)+y1] =
+ * <y1, N-y1| BS_g |x1, N-x1> for beam splitter g (0-based, in application
+ * order) and photon number N, computed on the device in FP64 by the same
+ * kernel the path sum uses, copied to the host array out ((N+1)^2 entries). */
+lofp_status lofp_bs_table(lofp_circuit c, int32_t gate, int32_t N, lofp_c128 *out);
+
+/* Amplitudes <T_i|U_P|S> for a batch of patterns, device-resident form.
+ * S: host int32[m].  T_dev: device int32[batch*m] (row-major).  out_dev:
+ * device lofp_c128[batch].  stream: hipStream_t (NULL = default stream).
+ * Kernels run on `stream`; the call synchronises that stream once to size
+ * the frontier buffers, and returns with the results written in stream
+ * order.  opts may be NULL (defaults); stats may be NULL.
+ * Eq. (1) summed by the frontier split (forward and backward merged
+ * frontiers, Schroedinger-Feynman interpolation of Sec. I) and depth-first
+ * enumeration of the middle layers (method PATHSUM), or by the mode-axis
+ * contraction of Sec. II.C (method CONTRACT). */
+lofp_status lofp_amplitudes_device(lofp_circuit c, const int32_t *S, int32_t batch,
+                                   const int32_t *T_dev, lofp_c128 *out_dev,
+                                   const lofp_opts *opts, void *stream, lofp_stats *stats);
+
+/* Same, host-memory form: T is host int32[batch*m], out host lofp_c128[batch].
+ * Copies in and out and synchronises; for convenience, not for timing. */
+lofp_status lofp_amplitudes(lofp_circuit c, const int32_t *S, int32_t batch, const int32_t *T,
+                            lofp_c128 *out, const lofp_opts *opts, lofp_stats *stats);
+
+/* One amplitude, host memory, default options. */
+lofp_status lofp_amplitude(lofp_circuit c, const int32_t *S, const int32_t *T, lofp_c128 *out);
+
+/* Number of valid paths of Eq. (1) for each pattern (conservation-valid
+ * sequences of intermediate configurations from S to T_i, counted on the
+ * device by the contraction in the counting semiring; exact below 2^53).
+ * T: host int32[batch*m]; counts: host double[batch]. */
+lofp_status lofp_path_counts(lofp_circuit c, const int32_t *S, int32_t batch, const int32_t *T,
+                             double *counts);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LOFP_H */

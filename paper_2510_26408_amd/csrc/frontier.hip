@@ -1,0 +1,91 @@
+// frontier.hip -- merged frontiers (Schroedinger-Feynman interpolation, Sec. I):
+// the amplitudes of every configuration reachable at a stage, expanded one
+// beam splitter at a time from S (forward) or from T (backward).  Each thread
+// produces one configuration of the target stage by gathering the (at most
+// N+1) configurations of the source stage that differ from it on the split
+// cut, so the summation order is fixed and the result deterministic.
+#include "lofp_device.h"
+
+namespace lofp {
+
+__global__ void k_seed(int B, const int64_t *__restrict__ off, double2 *__restrict__ vec)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= B) return;
+    if (off[p + 1] > off[p]) vec[off[p]] = make_double2(1.0, 0.0);
+}
+
+hipError_t launch_seed(int B, const int64_t *off, double2 *vec, hipStream_t stream)
+{
+    if (B == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seed, dim3((B + 255) / 256), dim3(256), 0, stream, B, off, vec);
+    return hipGetLastError();
+}
+
+template <int NCM, bool FWD>
+__global__ __launch_bounds__(256) void k_gate(GateArgs g)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= g.total_tgt) return;
+    const int p = find_pattern(g.off_tgt, g.B, k);
+    const int64_t i = k - g.off_tgt[p];
+    const int nc = g.m - 1, W = table_cols(g.n), span = (g.D + 1) * nc;
+    const int16_t *lo = g.lo + (int64_t)p * span, *hi = g.hi + (int64_t)p * span;
+    const int32_t *Ct = g.C_tgt + (int64_t)p * nc * W;
+    const int32_t *Es = g.E_src + (int64_t)p * nc * W;
+    const int a = g.cut;
+
+    // unrank the target configuration; collect the neighbours of cut a and
+    // the source rank of every cut other than a
+    int prev = 0, next = g.n, cur = 0;
+    int64_t rem = i, K = 0;
+    int pv = 0;
+#pragma unroll
+    for (int r = 0; r < NCM; ++r) {
+        if (r < nc) {
+            const int t = g.st_tgt[r];
+            const int L = lo[t * nc + r], H = hi[t * nc + r];
+            const int32_t *Cr = Ct + r * W;
+            const int64_t base = Cr[pv];
+            int v = pv > L ? pv : L;
+            while (v < H && (int64_t)Cr[v + 1] - base <= rem) ++v;
+            rem -= (int64_t)Cr[v] - base;
+            pv = v;
+            if (r == a - 1) prev = v;
+            if (r == a + 1) next = v;
+            if (r == a) cur = v;
+            else K += Es[r * W + v];
+        }
+    }
+    const int N = next - prev;
+    const int ts = g.st_src[a];
+    const int Ls = lo[ts * nc + a], Hs = hi[ts * nc + a];
+    const int ulo = Ls > prev ? Ls : prev, uhi = Hs < next ? Hs : next;
+    const double2 *Wn = g.W + sector_offset(N);
+    const double2 *src = g.src + g.off_src[p];
+    const int32_t *Ea = Es + a * W;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int u = ulo; u <= uhi; ++u) {
+        const double2 w = FWD ? Wn[(u - prev) * (N + 1) + (cur - prev)] : Wn[(cur - prev) * (N + 1) + (u - prev)];
+        acc = cfma(w, src[K + Ea[u]], acc);
+    }
+    g.dst[k] = acc;
+}
+
+hipError_t launch_gate(const GateArgs &a, bool forward, hipStream_t stream)
+{
+    if (a.total_tgt == 0) return hipSuccess;
+    const int block = 256;
+    const dim3 grid((unsigned)((a.total_tgt + block - 1) / block));
+    const int nc = a.m - 1;
+    if (nc <= 15) {
+        if (forward) hipLaunchKernelGGL((k_gate<15, true>), grid, dim3(block), 0, stream, a);
+        else hipLaunchKernelGGL((k_gate<15, false>), grid, dim3(block), 0, stream, a);
+    } else {
+        if (forward) hipLaunchKernelGGL((k_gate<31, true>), grid, dim3(block), 0, stream, a);
+        else hipLaunchKernelGGL((k_gate<31, false>), grid, dim3(block), 0, stream, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lofp

@@ -1,0 +1,142 @@
+// lofp_device.h -- declarations shared by the kernel files and the host API.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lofp_core.h"
+
+namespace lofp {
+
+// Complex FP64 helpers (double2 = {re, im}).
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 acc)
+{
+    return make_double2(acc.x + a.x * b.x - a.y * b.y, acc.y + a.x * b.y + a.y * b.x);
+}
+
+// Compensated accumulator: running sum s and the accumulated rounding error
+// c, each addition done with Knuth's branch-free TwoSum.
+struct CSum {
+    double s, c;
+};
+__device__ __forceinline__ void csum_add(CSum &a, double x)
+{
+    double t = a.s + x;
+    double z = t - a.s;
+    double e = (a.s - (t - z)) + (x - z);
+    a.s = t;
+    a.c += e;
+}
+__device__ __forceinline__ void csum_merge(CSum &a, const CSum &b)
+{
+    csum_add(a, b.s);
+    a.c += b.c;
+}
+
+// Find the pattern owning flattened index k: largest p with off[p] <= k.
+__device__ __forceinline__ int find_pattern(const int64_t *off, int B, int64_t k)
+{
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `stream` and return the hipError_t of the launch.
+
+// a2: transition tables for every gate and every sector N <= n_tab.
+hipError_t launch_build_tables(int G, int n_tab, const double *theta, const double *phi,
+                               double2 *table, hipStream_t stream);
+
+// a1: per-pattern cut bounds.
+hipError_t launch_bounds(int B, int m, int D, int n, const int32_t *S, const int32_t *T,
+                         const int8_t *fr_lo, const int8_t *fr_hi, const int8_t *br_lo,
+                         const int8_t *br_hi, const uint8_t *cut_gate, int16_t *lo, int16_t *hi,
+                         int32_t *infeasible, hipStream_t stream);
+
+// a1/a3: per (stage slot, pattern) rank tables and state counts.
+hipError_t launch_stage_tables(int B, int m, int D, int n, int nslots, const int32_t *slot_stage,
+                               const uint8_t *stage_time, const int16_t *lo, const int16_t *hi,
+                               const int32_t *infeasible, int32_t *C, int32_t *E, int32_t *count,
+                               int32_t *overflow, hipStream_t stream);
+
+// a3: seed a frontier (single state per pattern with value 1).
+hipError_t launch_seed(int B, const int64_t *off, double2 *vec, hipStream_t stream);
+
+// a3: one beam splitter applied to a merged frontier (forward: stage g -> g+1;
+// backward: stage g+1 -> g).
+struct GateArgs {
+    int B, m, n, D;
+    int cut;                  // beam splitter on modes (cut, cut+1)
+    const uint8_t *st_tgt;    // stage_time row of the stage being produced
+    const uint8_t *st_src;    // stage_time row of the stage being read
+    const int16_t *lo, *hi;   // [B][(D+1)(m-1)]
+    const int32_t *C_tgt;     // [B][(m-1)(n+2)]
+    const int32_t *E_src;     // [B][(m-1)(n+2)]
+    const int64_t *off_tgt;   // [B+1]
+    const int64_t *off_src;   // [B+1]
+    const double2 *W;         // this gate's table (all sectors)
+    const double2 *src;
+    double2 *dst;
+    int64_t total_tgt;
+};
+hipError_t launch_gate(const GateArgs &a, bool forward, hipStream_t stream);
+
+// a4: depth-first enumeration of the middle beam splitters.
+struct DfsArgs {
+    int B, m, n, D;
+    int levels;               // number of middle beam splitters
+    const int4 *level_info;   // [levels]: {cut, layer, table offset, 0}
+    const double2 *tab;       // compact tables of the middle gates
+    int tab_len;              // entries in tab
+    const uint8_t *st_front;  // stage_time row of the forward frontier stage
+    const int16_t *lo, *hi;
+    const int32_t *C_front;   // [B][(m-1)(n+2)] rank tables of the frontier
+    const int32_t *E_back;    // [B][(m-1)(n+2)] rank tables of the backward stage
+    const int64_t *off_front; // [B+1]
+    const int64_t *off_back;  // [B+1]
+    double2 *front;           // frontier values; overwritten by value * suffix sum
+    const double2 *back;      // backward frontier values
+    int64_t total;            // frontier entries
+    unsigned long long *work_counter;
+    unsigned long long *stat_leaves;
+    unsigned long long *stat_edges;
+    int fp32_products;        // 1: running products in FP32
+};
+hipError_t launch_dfs(const DfsArgs &a, int grid, int block, hipStream_t stream);
+
+// a5: per-pattern compensated reduction: sum of vec over the pattern's
+// entries, or of vec[i] * back[i] when back != nullptr.
+hipError_t launch_reduce(int B, const int64_t *off, const double2 *vec, const double2 *back,
+                         double2 *out, hipStream_t stream);
+
+// a6: mode-axis contraction.
+struct ContractArgs {
+    int B, m, n, D, G;
+    const int32_t *S;         // [m]
+    const int32_t *T;         // [B][m]
+    const int16_t *lo, *hi;   // [B][(D+1)(m-1)]
+    const int32_t *infeasible;
+    const int32_t *gate_cut;  // [G]
+    const int32_t *gate_layer;// [G]
+    const int32_t *cut_ngates;// [m-1]  gates on each cut
+    const int32_t *cut_gates; // [m-1][D] gate ids on each cut in time order
+    const int32_t *ver_at;    // [(D+1)][m-1] version index of cut r at time t
+    const double2 *table;
+    int tab_stride;
+    double2 *out;             // amplitudes, or counts in .x when count_only
+    int count_only;
+    unsigned long long *stat_transitions;
+    int max_states;           // workspace states per pattern (per buffer)
+    double2 *ws;              // [B][2][max_states] workspace
+    int32_t *overflow;
+};
+hipError_t launch_contract(const ContractArgs &a, hipStream_t stream);
+
+}  // namespace lofp

@@ -1,0 +1,79 @@
+// plan.hip -- per-pattern cut bounds (light cones of Sec. II.B tightened by
+// photon conservation) and the dense rank tables of every needed stage.
+#include "lofp_device.h"
+
+namespace lofp {
+
+// One thread per pattern.
+__global__ void k_bounds(int B, int m, int D, int n, const int32_t *__restrict__ S,
+                         const int32_t *__restrict__ T, const int8_t *__restrict__ fr_lo,
+                         const int8_t *__restrict__ fr_hi, const int8_t *__restrict__ br_lo,
+                         const int8_t *__restrict__ br_hi, const uint8_t *__restrict__ cut_gate,
+                         int16_t *__restrict__ lo, int16_t *__restrict__ hi, int32_t *__restrict__ infeasible)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= B) return;
+    const int nc = m - 1, span = (D + 1) * nc;
+    const int32_t *Tp = T + (int64_t)p * m;
+    int16_t *L = lo + (int64_t)p * span, *H = hi + (int64_t)p * span;
+    int nT = 0, bad = 0;
+    for (int i = 0; i < m; ++i) { nT += Tp[i]; bad |= Tp[i] < 0; }
+    if (bad || nT != n) {
+        for (int i = 0; i < span; ++i) { L[i] = 1; H[i] = 0; }
+        infeasible[p] = 1;
+        return;
+    }
+    light_cone_bounds(m, D, S, Tp, fr_lo, fr_hi, br_lo, br_hi, L, H);
+    infeasible[p] = propagate_bounds(m, D, n, cut_gate, L, H);
+}
+
+hipError_t launch_bounds(int B, int m, int D, int n, const int32_t *S, const int32_t *T,
+                         const int8_t *fr_lo, const int8_t *fr_hi, const int8_t *br_lo,
+                         const int8_t *br_hi, const uint8_t *cut_gate, int16_t *lo, int16_t *hi,
+                         int32_t *infeasible, hipStream_t stream)
+{
+    if (B == 0) return hipSuccess;
+    const int block = 64;
+    hipLaunchKernelGGL(k_bounds, dim3((B + block - 1) / block), dim3(block), 0, stream, B, m, D, n, S, T,
+                       fr_lo, fr_hi, br_lo, br_hi, cut_gate, lo, hi, infeasible);
+    return hipGetLastError();
+}
+
+// One thread per (stage slot, pattern).
+__global__ void k_stage_tables(int B, int m, int D, int n, int nslots, const int32_t *__restrict__ slot_stage,
+                               const uint8_t *__restrict__ stage_time, const int16_t *__restrict__ lo,
+                               const int16_t *__restrict__ hi, const int32_t *__restrict__ infeasible,
+                               int32_t *__restrict__ C, int32_t *__restrict__ E, int32_t *__restrict__ count,
+                               int32_t *__restrict__ overflow)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)nslots * B) return;
+    const int slot = (int)(k / B), p = (int)(k - (int64_t)slot * B);
+    const int nc = m - 1, span = (D + 1) * nc, tsz = nc * table_cols(n);
+    const int s = slot_stage[slot];
+    int32_t *Cp = C + k * tsz, *Ep = E + k * tsz;
+    if (infeasible[p]) {
+        for (int i = 0; i < tsz; ++i) { Cp[i] = 0; Ep[i] = 0; }
+        count[k] = 0;
+        return;
+    }
+    const int64_t c = build_stage_tables(m, n, stage_time + (int64_t)s * nc, lo + (int64_t)p * span,
+                                         hi + (int64_t)p * span, Cp, Ep);
+    if (c < 0) { atomicOr(overflow, 1); count[k] = 0; return; }
+    count[k] = (int32_t)c;
+}
+
+hipError_t launch_stage_tables(int B, int m, int D, int n, int nslots, const int32_t *slot_stage,
+                               const uint8_t *stage_time, const int16_t *lo, const int16_t *hi,
+                               const int32_t *infeasible, int32_t *C, int32_t *E, int32_t *count,
+                               int32_t *overflow, hipStream_t stream)
+{
+    const int64_t total = (int64_t)nslots * B;
+    if (total == 0) return hipSuccess;
+    const int block = 64;
+    hipLaunchKernelGGL(k_stage_tables, dim3((unsigned)((total + block - 1) / block)), dim3(block), 0, stream,
+                       B, m, D, n, nslots, slot_stage, stage_time, lo, hi, infeasible, C, E, count, overflow);
+    return hipGetLastError();
+}
+
+}  // namespace lofp

@@ -1,0 +1,233 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+Tolerance: 1e-12 absolute for complex128 amplitudes (the stated target), and
+additionally |gpu - oracle| <= 1e-12 * max(1, |oracle|) * 0 + 1e-12 is checked
+together with a relative bound where the amplitude is not tiny."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_26408_amd import lofp, workloads
+
+pytestmark = pytest.mark.gpu
+ATOL = 1e-12
+
+
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(autouse=True)
+def gpu_only():
+    _need_gpu()
+
+
+def flat(layers):
+    return [bs for l in layers for bs in l]
+
+
+def check(got, want, atol=ATOL):
+    got, want = np.asarray(got), np.asarray(want)
+    err = np.abs(got - want)
+    assert err.max() <= atol, (err.max(), int(err.argmax()))
+
+
+def oracle_amps(wl_m, S, Ts, layers):
+    amps, _ = oracle.amplitudes(wl_m, S, Ts, flat(layers), nthreads=8)
+    return amps
+
+
+# ------------------------------------------------------------------ tables
+def test_tables_match_oracle():
+    wl = workloads.make("c1", seed=3)
+    c = lofp.Circuit(wl.m, wl.layers)
+    gates = flat(wl.layers)
+    for g in (0, 5, len(gates) - 1):
+        _, _, th, ph = gates[g]
+        for N in range(0, 9):
+            got = c.bs_table(g, N)                  # [x1, y1]
+            want = oracle.bs_sector(th, ph, N).T    # oracle is [y1, x1]
+            check(got, want, 1e-14 * max(1, N))
+
+
+def test_table_special_angles():
+    layers = [[(0, 1, 0.0, 1.0)], [(0, 1, math.pi / 2, 0.4)], [(0, 1, math.pi / 4, 2.0)]]
+    c = lofp.Circuit(2, layers)
+    for N in range(0, 7):
+        assert np.array_equal(c.bs_table(0, N), np.eye(N + 1))
+        check(c.bs_table(1, N), oracle.bs_sector(math.pi / 2, 0.4, N).T, 1e-13)
+    assert abs(c.bs_table(2, 2)[1, 1]) < 1e-15   # Hong-Ou-Mandel
+
+
+# ---------------------------------------------------------- small circuits
+@pytest.mark.parametrize("method", [lofp.METHOD_PATHSUM, lofp.METHOD_CONTRACT])
+def test_paper_correctness_protocol(method):
+    """Sec. III.A: 6-mode inputs at depths 3..6, every output; probabilities sum
+    to 1 and agree with the oracle."""
+    cases = [((1, 1, 1, 1, 1, 1), 3), ((0, 0, 4, 0, 0, 4), 4), ((2, 0, 3, 0, 0, 3), 5), ((2, 0, 0, 2, 0, 2), 6)]
+    for k, (S, D) in enumerate(cases):
+        layers = workloads.random_brickwork(6, D, np.random.Generator(np.random.PCG64(40 + k)))
+        pats = np.array(oracle.all_patterns(6, sum(S)), dtype=np.int32)
+        c = lofp.Circuit(6, layers)
+        got = c.amplitudes(S, pats, lofp.make_opts(method=method))
+        want = oracle_amps(6, np.array(S), pats, layers)
+        check(got, want)
+        assert abs(np.sum(np.abs(got) ** 2) - 1) < 1e-12
+        tvd = 0.5 * np.abs(np.abs(got) ** 2 - np.abs(want) ** 2).sum()
+        assert tvd < 1e-13
+
+
+@pytest.mark.parametrize("fl,bl", [(0, 0), (0, 4), (1, 2), (2, 2), (1, 3), (0, 1), (4, 4), (3, 4)])
+def test_c1_all_patterns_every_cut(fl, bl):
+    wl = workloads.make("c1", seed=0)
+    pats = np.array(oracle.all_patterns(wl.m, wl.n), dtype=np.int32)
+    c = lofp.Circuit(wl.m, wl.layers)
+    st = lofp.Stats()
+    got = c.amplitudes(wl.S, pats, lofp.make_opts(method=lofp.METHOD_PATHSUM, fwd_layer=fl, bwd_layer=bl), st)
+    check(got, oracle_amps(wl.m, wl.S, pats, wl.layers))
+    assert st.fwd_layer == fl and st.bwd_layer == bl
+
+
+@pytest.mark.parametrize("D", [0, 1, 2, 3])
+def test_shallow_and_empty_circuits(D):
+    m = 6
+    layers = workloads.random_brickwork(m, D, np.random.Generator(np.random.PCG64(7 + D)))
+    S = np.array([1, 0, 2, 0, 1, 0], dtype=np.int32)
+    pats = np.array(oracle.all_patterns(m, 4), dtype=np.int32)
+    c = lofp.Circuit(m, layers)
+    for method in (lofp.METHOD_PATHSUM, lofp.METHOD_CONTRACT):
+        got = c.amplitudes(S, pats, lofp.make_opts(method=method))
+        if D == 0:
+            want = np.array([1.0 if np.array_equal(T, S) else 0.0 for T in pats])
+        else:
+            want = oracle_amps(m, S, pats, layers)
+        check(got, want)
+
+
+def test_exact_zero_for_infeasible_and_nonconserving():
+    wl = workloads.make("c1", seed=0)
+    c = lofp.Circuit(wl.m, wl.layers)
+    T_far = np.zeros(wl.m, dtype=np.int32)
+    T_far[4:8] = 1                       # four photons must all move by 4 in depth 4: impossible
+    T_more = wl.Ts[0].copy()
+    T_more[0] += 1
+    for method in (lofp.METHOD_PATHSUM, lofp.METHOD_CONTRACT):
+        got = c.amplitudes(wl.S, np.stack([T_far, T_more]), lofp.make_opts(method=method))
+        assert got[0] == 0 and got[1] == 0
+
+
+def test_single_photon_and_bunched():
+    m, D = 7, 5
+    layers = workloads.random_brickwork(m, D, np.random.Generator(np.random.PCG64(11)))
+    U = oracle.compose(m, flat(layers))
+    c = lofp.Circuit(m, layers)
+    for s in range(m):
+        S = np.eye(m, dtype=np.int32)[s]
+        got = c.amplitudes(S, np.eye(m, dtype=np.int32))
+        check(got, U[:, s])
+    S = np.zeros(m, dtype=np.int32)
+    S[3] = 5
+    pats = np.array(oracle.all_patterns(m, 5), dtype=np.int32)
+    for method in (lofp.METHOD_PATHSUM, lofp.METHOD_CONTRACT):
+        check(c.amplitudes(S, pats, lofp.make_opts(method=method)), oracle_amps(m, S, pats, layers))
+
+
+def test_empty_batch():
+    wl = workloads.make("c1", seed=0)
+    c = lofp.Circuit(wl.m, wl.layers)
+    assert c.amplitudes(wl.S, np.zeros((0, wl.m), dtype=np.int32)).shape == (0,)
+
+
+# ----------------------------------------------------- workload-shaped cases
+@pytest.mark.parametrize("name,batch", [("c2", 24), ("c3", 48)])
+def test_workloads_pathsum_and_contract(name, batch):
+    wl = workloads.make(name, seed=1, batch=batch)
+    c = lofp.Circuit(wl.m, wl.layers)
+    want = oracle_amps(wl.m, wl.S, wl.Ts, wl.layers)
+    for opts in (lofp.make_opts(method=lofp.METHOD_PATHSUM),
+                 lofp.make_opts(method=lofp.METHOD_PATHSUM, fwd_layer=wl.depth - 4, bwd_layer=wl.depth - 2),
+                 lofp.make_opts(method=lofp.METHOD_CONTRACT)):
+        check(c.amplitudes(wl.S, wl.Ts, opts), want)
+
+
+def test_c5_contraction():
+    wl = workloads.make("c5", seed=1, batch=32)
+    c = lofp.Circuit(wl.m, wl.layers)
+    want = oracle_amps(wl.m, wl.S, wl.Ts, wl.layers)
+    got = c.amplitudes(wl.S, wl.Ts, lofp.make_opts(method=lofp.METHOD_CONTRACT))
+    check(got, want)
+
+
+def test_c2_full_batch_sampled():
+    """Full 4096-pattern batch in the launch configuration the benchmark
+    times; 64 sampled patterns checked against the oracle."""
+    import torch
+    wl = workloads.make("c2", seed=0)
+    c = lofp.Circuit(wl.m, wl.layers)
+    T = torch.from_numpy(wl.Ts).cuda()
+    out = torch.zeros(wl.batch, dtype=torch.complex128, device="cuda")
+    st = lofp.Stats()
+    c.amplitudes_device(wl.S, T, out, lofp.make_opts(method=lofp.METHOD_PATHSUM), stats=st)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    idx = np.random.default_rng(0).choice(wl.batch, 64, replace=False)
+    check(got[idx], oracle_amps(wl.m, wl.S, wl.Ts[idx], wl.layers))
+    assert st.dfs_leaves > 0
+
+
+# ------------------------------------------------------------ path counts
+def test_path_counts_match_enumeration():
+    for (m, D, S) in [(5, 4, (1, 0, 1, 0, 1)), (6, 5, (2, 0, 1, 0, 1, 0))]:
+        layers = workloads.random_brickwork(m, D, np.random.Generator(np.random.PCG64(m + D)))
+        pats = np.array(oracle.all_patterns(m, sum(S)), dtype=np.int32)
+        c = lofp.Circuit(m, layers)
+        got = c.path_counts(S, pats)
+        want = [oracle.path_count_bruteforce(m, S, T, flat(layers)) for T in pats]
+        assert np.array_equal(got, np.array(want, dtype=np.float64))
+
+
+def test_leaf_count_matches_path_count_when_frontiers_are_endpoints():
+    """With the forward frontier at S and the backward one at T, every valid
+    path is enumerated once by the depth-first kernel."""
+    wl = workloads.make("c1", seed=2)
+    pats = np.array(oracle.all_patterns(wl.m, wl.n), dtype=np.int32)
+    c = lofp.Circuit(wl.m, wl.layers)
+    st = lofp.Stats()
+    c.amplitudes(wl.S, pats, lofp.make_opts(method=lofp.METHOD_PATHSUM, fwd_layer=0, bwd_layer=wl.depth), st)
+    assert st.dfs_leaves == int(c.path_counts(wl.S, pats).sum())
+
+
+# ------------------------------------------------------------- determinism
+def test_deterministic_and_independent_of_batch():
+    wl = workloads.make("c2", seed=5, batch=64)
+    c = lofp.Circuit(wl.m, wl.layers)
+    a = c.amplitudes(wl.S, wl.Ts)
+    b = c.amplitudes(wl.S, wl.Ts)
+    assert np.array_equal(a, b)
+    for p in (0, 17, 63):
+        alone = c.amplitudes(wl.S, wl.Ts[p:p + 1])
+        assert alone[0] == a[p]
+
+
+# ------------------------------------------------------------ FP32 products
+def test_fp32_products_within_bound():
+    wl = workloads.make("c2", seed=3, batch=32)
+    c = lofp.Circuit(wl.m, wl.layers)
+    ref = c.amplitudes(wl.S, wl.Ts)
+    f32 = c.amplitudes(wl.S, wl.Ts, lofp.make_opts(precision=lofp.PREC_FP32))
+    err = np.abs(f32 - ref)
+    # products of at most `levels` FP32 factors: relative error per path
+    # <= (2 levels + 2) 2^-24; summed paths of magnitude <= 1 each
+    assert err.max() < 1e-5
+
+
+def test_pathsum_state_space_overflow_is_reported():
+    wl = workloads.make("c5", seed=0, batch=2)
+    c = lofp.Circuit(wl.m, wl.layers)
+    with pytest.raises(lofp.LofpError) as e:
+        c.amplitudes(wl.S, wl.Ts, lofp.make_opts(method=lofp.METHOD_PATHSUM, fwd_layer=3, bwd_layer=3))
+    assert e.value.status == lofp.ENOMEM
