@@ -4,8 +4,10 @@ Workload (default): m=16 modes, n=8 photons in the even modes, depth-8
 brickwork of nearest-neighbour beam splitters (theta ~ U(0, pi/2), phi ~
 U(0, 2 pi), seed 0), 4096 collision-free output patterns with every sorted
 output mode within distance 8 of its sorted input mode.  One step = one call
-of the library on the whole batch (cut bounds, merged frontiers, depth-first
-path enumeration, compensated reduction), inputs resident in HBM.
+of the library on the whole batch with inputs resident in HBM; the library
+picks the form (mode-axis contraction when its state fits, as the paper does
+for depth > 2, else merged frontiers + depth-first path enumeration); both
+forms are reported, each with the roofline of its dominant kernel.
 
 Prints one JSON line.  `value` is represented valid paths per second: the
 number of conservation-valid paths of Eq. (1) summed over the batch (counted
@@ -36,12 +38,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2")
-    ap.add_argument("--method", default="pathsum", choices=["pathsum", "contract"])
+    ap.add_argument("--method", default="auto", choices=["auto", "pathsum", "contract"])
     ap.add_argument("--fwd-layer", type=int, default=-1)
     ap.add_argument("--bwd-layer", type=int, default=-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
+    ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -62,7 +67,7 @@ def main():
     dev = torch.device("cuda:0")
     wl = workloads.make(args.config, seed=0)
     circ = lofp.Circuit(wl.m, wl.layers)
-    method = lofp.METHOD_PATHSUM if args.method == "pathsum" else lofp.METHOD_CONTRACT
+    method = {"auto": lofp.METHOD_AUTO, "pathsum": lofp.METHOD_PATHSUM, "contract": lofp.METHOD_CONTRACT}[args.method]
     opts = lofp.make_opts(method=method, fwd_layer=args.fwd_layer, bwd_layer=args.bwd_layer, record_timing=True)
     T = torch.from_numpy(wl.Ts).to(dev)
     out = torch.zeros(wl.batch, dtype=torch.complex128, device=dev)
@@ -129,42 +134,23 @@ def main():
     }
 
     # roofline of the dominant kernel, from HIP events on the launch stream
-    if args.method == "pathsum":
-        ms_dfs = avg("ms_dfs")
-        ms_fwd = avg("ms_forward")
-        if ms_dfs >= ms_fwd and ms_dfs > 0:
-            flops = 6.0 * edges + 8.0 * leaves
-            achieved = flops / (ms_dfs * 1e-3) / 1e12
-            res["roofline"] = {"kernel": "k_dfs", "bound": "alu", "achieved": achieved,
-                               "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                               "traffic": None, "avg_ms": ms_dfs,
-                               "algorithmic": "6 flops per tree edge (complex FP64 product) + 8 per leaf"}
-        else:
-            # forward frontier: per produced state one 16 B write plus its
-            # predecessors' 16 B reads (counted as bfs_states * 32 B lower bound)
-            byts = 32.0 * s0["bfs_states"]
-            achieved = byts / (ms_fwd * 1e-3) / 1e9
-            res["roofline"] = {"kernel": "k_gate (forward)", "bound": "hbm", "achieved": achieved,
-                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                               "traffic": None, "avg_ms": ms_fwd,
-                               "algorithmic": "32 B per frontier state (one 16 B write, one 16 B read)"}
+    used = s0["method_used"]
+    res["config"]["method_used"] = "contract" if used == lofp.METHOD_CONTRACT else "pathsum"
+    if used == lofp.METHOD_CONTRACT:
+        res["roofline"] = contract_roofline(avg("ms_contract"), s0["transitions"])
     else:
-        ms_c = avg("ms_contract")
-        res["roofline"] = {"kernel": "k_contract", "bound": "alu", "avg_ms": ms_c, "traffic": None}
-
-    # single-pattern latency (plain form, batch of 1)
-    lat = []
-    T1 = T[:1].contiguous()
-    o1 = out[:1]
-    for i in range(60):
+        res["roofline"] = pathsum_roofline(s0, avg)
+    if args.calib_copy_mib > 0:
+        nb = args.calib_copy_mib * (1 << 20)
+        xa = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        xb = torch.empty_like(xa)
+        xb.copy_(xa)
         torch.cuda.synchronize()
-        a = time.perf_counter()
-        circ.amplitudes_device(wl.S, T[i:i + 1].contiguous(), o1, lofp.make_opts(method=method), stream=stream)
-        torch.cuda.synchronize()
-        lat.append((time.perf_counter() - a) * 1e3)
-    lat = np.array(lat[10:])
-    res["latency_single_ms"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}
+        res["calib_copy_bytes"] = nb
+        del xa, xb
 
+    if not args.no_latency:
+        res["latency_single_ms"] = single_latency(circ, wl, T, out, method, stream, torch, lofp)
     if not args.no_variants:
         res["variants"] = variants(lofp, workloads, torch, dev, stream)
 
@@ -173,34 +159,100 @@ def main():
     print(json.dumps(res), flush=True)
 
 
-def variants(lofp, workloads, torch, dev, stream):
-    """Contraction form on the same batch and on the m=32, n=16 workload."""
-    out = {}
-    for name in ("c2", "c5"):
-        wl = workloads.make(name, seed=0)
-        circ = lofp.Circuit(wl.m, wl.layers)
-        T = torch.from_numpy(wl.Ts).to(dev)
-        o = torch.zeros(wl.batch, dtype=torch.complex128, device=dev)
-        opts = lofp.make_opts(method=lofp.METHOD_CONTRACT, record_timing=True)
-        for _ in range(2):
-            circ.amplitudes_device(wl.S, T, o, opts, stream=stream, stats=lofp.Stats())
+def single_latency(circ, wl, T, out, method, stream, torch, lofp):
+    """Latency of one-pattern calls of the same form (p50/p99 over 50)."""
+    lat = []
+    o1 = out[:1]
+    for i in range(60):
         torch.cuda.synchronize()
-        K = 10
-        sts = []
-        t0 = time.perf_counter()
-        for _ in range(K):
-            st = lofp.Stats()
-            circ.amplitudes_device(wl.S, T, o, opts, stream=stream, stats=st)
-            sts.append(st.as_dict())
+        a = time.perf_counter()
+        circ.amplitudes_device(wl.S, T[i:i + 1].contiguous(), o1, lofp.make_opts(method=method), stream=stream)
         torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / K
-        paths = float(circ.path_counts(wl.S, wl.Ts).sum())
-        ms_k = float(np.mean([s["ms_contract"] for s in sts]))
-        trans = sts[-1]["transitions"]
-        out[f"contract_{name}"] = {"batch": wl.batch, "ms_per_step": ms, "amplitudes_per_s": wl.batch / (ms * 1e-3),
-                                   "paths_per_s": paths / (ms * 1e-3), "kernel_ms": ms_k,
-                                   "transitions": trans}
+        lat.append((time.perf_counter() - a) * 1e3)
+    lat = np.array(lat[10:])
+    return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}
+
+
+def traffic_for(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel's source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))[kernel]
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha16"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
+def contract_roofline(ms_k, transitions):
+    # one complex FP64 multiply-add (8 flops) per state transition
+    flops = 8.0 * transitions
+    achieved = flops / (ms_k * 1e-3) / 1e12 if ms_k > 0 else 0.0
+    return {"kernel": "k_contract", "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic_for("k_contract"),
+            "avg_ms": ms_k, "algorithmic": "8 FP64 flops (complex multiply-add) per contraction transition"}
+
+
+def pathsum_roofline(s0, avg):
+    ms_dfs, ms_fwd = avg("ms_dfs"), avg("ms_forward")
+    if ms_dfs >= ms_fwd and ms_dfs > 0:
+        flops = 6.0 * s0["dfs_edges"] + 8.0 * s0["dfs_leaves"]
+        achieved = flops / (ms_dfs * 1e-3) / 1e12
+        return {"kernel": "k_dfs", "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "avg_ms": ms_dfs,
+                "algorithmic": "6 FP64 flops per tree edge (complex product) + 8 per leaf"}
+    # forward frontier: per produced state one 16 B write plus one 16 B read of
+    # each predecessor (counted once: 32 B per state)
+    byts = 32.0 * s0["bfs_states"]
+    achieved = byts / (ms_fwd * 1e-3) / 1e9 if ms_fwd > 0 else 0.0
+    return {"kernel": "k_gate (forward)", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_ms": ms_fwd,
+            "algorithmic": "32 B per frontier state (one 16 B write, one 16 B read)"}
+
+
+def run_variant(lofp, workloads, torch, dev, stream, name, method, steps=5):
+    wl = workloads.make(name, seed=0)
+    circ = lofp.Circuit(wl.m, wl.layers)
+    T = torch.from_numpy(wl.Ts).to(dev)
+    o = torch.zeros(wl.batch, dtype=torch.complex128, device=dev)
+    opts = lofp.make_opts(method=method, record_timing=True)
+    for _ in range(2):
+        circ.amplitudes_device(wl.S, T, o, opts, stream=stream, stats=lofp.Stats())
+    torch.cuda.synchronize()
+    sts = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = lofp.Stats()
+        circ.amplitudes_device(wl.S, T, o, opts, stream=stream, stats=st)
+        sts.append(st.as_dict())
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    paths = float(circ.path_counts(wl.S, wl.Ts).sum())
+    avg = lambda k: float(np.mean([s[k] for s in sts]))
+    s0 = sts[-1]
+    out = {"workload": wl.note, "batch": wl.batch, "ms_per_step": ms, "amplitudes_per_s": wl.batch / (ms * 1e-3),
+           "paths_per_s": paths / (ms * 1e-3),
+           "phases_ms": {k: avg(k) for k in ("ms_plan", "ms_forward", "ms_backward", "ms_dfs", "ms_reduce",
+                                             "ms_contract", "ms_total")}}
+    if method == lofp.METHOD_CONTRACT:
+        out["transitions"] = s0["transitions"]
+        out["roofline"] = contract_roofline(avg("ms_contract"), s0["transitions"])
+    else:
+        out.update({k: s0[k] for k in ("fwd_layer", "bwd_layer", "dfs_levels", "frontier_states",
+                                        "backward_states", "bfs_states", "dfs_leaves", "dfs_edges")})
+        out["roofline"] = pathsum_roofline(s0, avg)
     return out
+
+
+def variants(lofp, workloads, torch, dev, stream):
+    """The depth-first path-sum form on the same batch, and the contraction on
+    the m=32, n=16 workload."""
+    return {"pathsum_c2": run_variant(lofp, workloads, torch, dev, stream, "c2", lofp.METHOD_PATHSUM, steps=3),
+            "contract_c5": run_variant(lofp, workloads, torch, dev, stream, "c5", lofp.METHOD_CONTRACT, steps=20)}
 
 
 def host_threads() -> int:

@@ -25,9 +25,8 @@
  *   - Results are bit-reproducible for a fixed (circuit, S, T, opts) and do
  *     not depend on the other patterns of the batch.
  *
- * Limits: m <= 32 modes, total photon number n <= 64 and at most 15 photons
- * in one mode of S or T (LOFP_ENOTSUP otherwise).  Non-adjacent pairs are
- * rejected with LOFP_ENOTSUP.
+ * Limits: m <= 32 modes and total photon number n <= 64 (LOFP_ENOTSUP
+ * otherwise).  Non-adjacent pairs are rejected with LOFP_ENOTSUP.
  */
 #ifndef LOFP_H
 #define LOFP_H
@@ -64,7 +63,7 @@ typedef struct {
 typedef struct lofp_circuit_s *lofp_circuit;
 
 enum {
-    LOFP_METHOD_AUTO = 0,     /* path sum for every workload                 */
+    LOFP_METHOD_AUTO = 0,     /* contraction when its state fits, else path sum */
     LOFP_METHOD_PATHSUM = 1,  /* frontier split + depth-first path sum       */
     LOFP_METHOD_CONTRACT = 2  /* mode-axis layer-block contraction (Sec. II.C) */
 };
@@ -105,6 +104,8 @@ typedef struct {
     double ms_reduce;         /*   final compensated reduction                 */
     double ms_contract;       /*   contraction kernel                          */
     double ms_total;          /*   whole call on the stream                    */
+    int32_t method_used;      /* LOFP_METHOD_PATHSUM or LOFP_METHOD_CONTRACT   */
+    int32_t reserved_[3];
 } lofp_stats;
 
 /* Message for the last non-OK status on this thread ("" if none). */

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -81,6 +82,13 @@ struct lofp_circuit_s {
     std::vector<int8_t> fr_lo, fr_hi, br_lo, br_hi;  // [(D+1)][m]
     std::vector<uint8_t> stage_time;       // [(G+1)][nc]
     std::vector<int32_t> cut_ngates, cut_gates, ver_at;
+    // contraction step program (built once per circuit)
+    bool prog_built = false;
+    bool prog_on_device = false;
+    std::string prog_error;
+    int nvars = 0;
+    std::vector<int32_t> var_cut, var_time;
+    std::vector<ContractStep> steps;
     std::mutex mu;
 
     // device state (lazy)
@@ -88,10 +96,10 @@ struct lofp_circuit_s {
     int n_tab = -1;
     int tab_stride = 0;
     DevBuf d_table, d_theta, d_phi, d_fr_lo, d_fr_hi, d_br_lo, d_br_hi, d_cut_gate, d_stage_time;
-    DevBuf d_gate_cut, d_gate_layer, d_cut_ngates, d_cut_gates, d_ver_at;
+    DevBuf d_gate_cut, d_gate_layer, d_cut_ngates, d_cut_gates, d_ver_at, d_var_cut, d_var_time, d_steps;
     // per-call workspace
-    DevBuf d_S, d_lo, d_hi, d_inf, d_C, d_E, d_count, d_slot_stage, d_off, d_fa, d_fb, d_ba, d_bb;
-    DevBuf d_levels, d_tab_mid, d_counters, d_T, d_out, d_ws;
+    DevBuf d_S, d_lo, d_hi, d_inf, d_C, d_E, d_count, d_slot_stage, d_off, d_coff, d_fa, d_fb, d_ba, d_bb;
+    DevBuf d_levels, d_tab_mid, d_counters, d_T, d_out, d_ws, d_cfg, d_rankb;
 };
 
 namespace {
@@ -270,54 +278,195 @@ lofp_status run_bounds(lofp_circuit_s &c, int B, int n, const int32_t *T_dev, hi
     return LOFP_OK;
 }
 
+// Contraction program: the splitters in cut-major order (top cut first, each
+// cut's splitters in time order).  Every free version of a cut is a variable;
+// a step introduces the variables its splitter reads for the first time and
+// sums out those it reads for the last time.  The live list after a step
+// starts with the step's own still-live references so the kernel finds them
+// at fixed positions.
+void build_program(lofp_circuit_s &c)
+{
+    c.prog_built = true;
+    c.prog_error.clear();
+    const int nc = c.nc, Dm = std::max(c.D, 1);
+    std::vector<std::vector<int>> var_of(nc);
+    c.var_cut.clear();
+    c.var_time.clear();
+    for (int r = 0; r < nc; ++r) {
+        const int k = c.cut_ngates[r];
+        var_of[r].assign(k + 1, -1);
+        for (int v = 1; v < k; ++v) {
+            var_of[r][v] = (int)c.var_cut.size();
+            c.var_cut.push_back(r);
+            c.var_time.push_back(c.gate_layer[c.cut_gates[(size_t)r * Dm + v - 1]] + 1);
+        }
+    }
+    c.nvars = (int)c.var_cut.size();
+    if (c.nvars > kMaxContractVars) { c.prog_error = "too many free cut versions for the contraction"; return; }
+    struct Ref { int kind, arg; };  // kind: CREF_* with arg = cut, or -1 with arg = variable
+    auto version_ref = [&](int r, int v) -> Ref {
+        if (r < 0) return {CREF_ZERO, 0};
+        if (r >= nc) return {CREF_N, 0};
+        if (v == 0) return {CREF_SPRE, r};
+        if (v == c.cut_ngates[r]) return {CREF_TPRE, r};
+        return {-1, var_of[r][v]};
+    };
+    std::vector<std::array<Ref, 4>> fac;
+    std::vector<int> fgate;
+    for (int r = 0; r < nc; ++r) {
+        const int k = c.cut_ngates[r];
+        for (int j = 1; j <= k; ++j) {
+            const int g = c.cut_gates[(size_t)r * Dm + j - 1];
+            const int l = c.gate_layer[g];
+            std::array<Ref, 4> f;
+            f[0] = version_ref(r, j - 1);
+            f[1] = version_ref(r, j);
+            f[2] = r > 0 ? version_ref(r - 1, c.ver_at[(size_t)l * nc + r - 1]) : Ref{CREF_ZERO, 0};
+            f[3] = r + 1 < nc ? version_ref(r + 1, c.ver_at[(size_t)l * nc + r + 1]) : Ref{CREF_N, 0};
+            fac.push_back(f);
+            fgate.push_back(g);
+        }
+    }
+    std::vector<int> last_use(c.nvars, -1);
+    for (size_t f = 0; f < fac.size(); ++f)
+        for (const Ref &x : fac[f])
+            if (x.kind < 0) last_use[x.arg] = (int)f;
+    std::vector<int> active;
+    c.steps.clear();
+    for (size_t f = 0; f < fac.size(); ++f) {
+        ContractStep st;
+        std::memset(&st, 0, sizeof(st));
+        st.gate = fgate[f];
+        std::vector<int> F;
+        for (const Ref &x : fac[f])
+            if (x.kind < 0 && std::find(F.begin(), F.end(), x.arg) == F.end()) F.push_back(x.arg);
+        std::vector<int> summed, kept;
+        for (int v : F) (last_use[v] == (int)f ? summed : kept).push_back(v);
+        std::vector<int> nl = kept;
+        for (int v : active)
+            if (std::find(F.begin(), F.end(), v) == F.end()) nl.push_back(v);
+        if ((int)nl.size() > kMaxActive || (int)active.size() > kMaxActive || summed.size() > 2) {
+            c.prog_error = "contraction state has too many live cut versions";
+            return;
+        }
+        st.n_new = (int)nl.size();
+        st.n_old = (int)active.size();
+        st.n_sum = (int)summed.size();
+        for (int q = 0; q < st.n_old; ++q) st.old_vars[q] = active[q];
+        for (int q = 0; q < st.n_new; ++q) {
+            st.new_vars[q] = nl[q];
+            auto it = std::find(active.begin(), active.end(), nl[q]);
+            st.new_to_old[q] = it == active.end() ? -1 : (int)(it - active.begin());
+        }
+        for (int q = 0; q < st.n_sum; ++q) {
+            st.sum_vars[q] = summed[q];
+            auto it = std::find(active.begin(), active.end(), summed[q]);
+            st.sum_to_old[q] = it == active.end() ? -1 : (int)(it - active.begin());
+        }
+        for (int k = 0; k < 4; ++k) {
+            const Ref &x = fac[f][k];
+            if (x.kind >= 0) {
+                st.ref_kind[k] = x.kind;
+                st.ref_arg[k] = x.arg;
+            } else {
+                auto it = std::find(summed.begin(), summed.end(), x.arg);
+                if (it != summed.end()) {
+                    st.ref_kind[k] = CREF_SUM;
+                    st.ref_arg[k] = (int)(it - summed.begin());
+                } else {
+                    st.ref_kind[k] = CREF_NEW;
+                    st.ref_arg[k] = (int)(std::find(nl.begin(), nl.end(), x.arg) - nl.begin());
+                }
+            }
+        }
+        c.steps.push_back(st);
+        active = nl;
+    }
+    if (!active.empty()) c.prog_error = "contraction program left live versions";
+}
+
+// Largest contraction state of the program under the given per-time bounds.
+int64_t program_state_bound(const lofp_circuit_s &c, const std::vector<int16_t> &lo, const std::vector<int16_t> &hi)
+{
+    int64_t mx = 1;
+    for (const ContractStep &st : c.steps) {
+        int64_t ns = 1;
+        for (int q = 0; q < st.n_new; ++q) {
+            const int v = st.new_vars[q];
+            const size_t i = (size_t)c.var_time[v] * c.nc + c.var_cut[v];
+            ns *= std::max(1, hi[i] - lo[i] + 1);
+            if (ns > (1LL << 40)) return ns;
+        }
+        mx = std::max(mx, ns);
+    }
+    return mx;
+}
+
+lofp_status prepare_program(lofp_circuit_s &c, hipStream_t s)
+{
+    if (!c.prog_built) build_program(c);
+    if (!c.prog_error.empty()) return fail(LOFP_ENOTSUP, c.prog_error);
+    if (!c.prog_on_device) {
+        HIPCHK(upload(c.d_var_cut, c.var_cut, s));
+        HIPCHK(upload(c.d_var_time, c.var_time, s));
+        HIPCHK(upload(c.d_steps, c.steps, s));
+        c.prog_on_device = true;
+    }
+    return LOFP_OK;
+}
+
 lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
                          lofp_c128 *out_dev, int count_only, hipStream_t s, lofp_stats *st, Timer &tm)
 {
-    // workspace bound from the S-side intervals (per-pattern ones are subsets)
-    std::vector<int16_t> lo, hi;
-    s_only_bounds(c, S, n, lo, hi);
-    auto dom = [&](int r) -> int64_t {
-        if (r < 0 || r >= c.nc) return 1;
-        int64_t d = 1;
-        const int k = c.cut_ngates[r];
-        for (int j = 1; j < k; ++j) {
-            const int t = c.gate_layer[c.cut_gates[(size_t)r * std::max(c.D, 1) + j - 1]] + 1;
-            d *= std::max(0, hi[(size_t)t * c.nc + r] - lo[(size_t)t * c.nc + r] + 1);
-        }
-        return d;
-    };
-    int64_t max_states = 1;
-    for (int r = -1; r < c.nc; ++r) max_states = std::max(max_states, dom(r) * dom(r + 1));
-    if (max_states > (1 << 26)) return fail(LOFP_ENOMEM, "contraction state space too large");
-    for (int r = 0; r < c.nc; ++r)
-        if (c.cut_ngates[r] >= 16) return fail(LOFP_ENOTSUP, "more than 15 beam splitters on one cut");
-    HIPCHK(ensure(c.d_ws, (size_t)B * 2 * max_states * sizeof(double2)));
-    tm.mark();
-    lofp_status rc = run_bounds(c, B, n, T_dev, s);
+    lofp_status rc = prepare_program(c, s);
     if (rc != LOFP_OK) return rc;
     tm.mark();
-    HIPCHK(hipMemsetAsync(c.d_counters.p, 0, 8 * sizeof(unsigned long long), s));
+    rc = run_bounds(c, B, n, T_dev, s);
+    if (rc != LOFP_OK) return rc;
+    unsigned long long *ctr = c.d_counters.as<unsigned long long>();
+    HIPCHK(hipMemsetAsync(ctr, 0, 8 * sizeof(unsigned long long), s));
     ContractArgs a{};
-    a.B = B; a.m = c.m; a.n = n; a.D = c.D; a.G = c.G;
+    a.B = B; a.m = c.m; a.n = n; a.D = c.D;
     a.S = c.d_S.as<int32_t>();
     a.T = T_dev;
     a.lo = c.d_lo.as<int16_t>(); a.hi = c.d_hi.as<int16_t>();
     a.infeasible = c.d_inf.as<int32_t>();
-    a.gate_cut = c.d_gate_cut.as<int32_t>(); a.gate_layer = c.d_gate_layer.as<int32_t>();
-    a.cut_ngates = c.d_cut_ngates.as<int32_t>(); a.cut_gates = c.d_cut_gates.as<int32_t>();
-    a.ver_at = c.d_ver_at.as<int32_t>();
+    a.nvars = c.nvars;
+    a.var_cut = c.d_var_cut.as<int32_t>();
+    a.var_time = c.d_var_time.as<int32_t>();
+    a.nsteps = (int)c.steps.size();
+    a.steps = c.d_steps.as<ContractStep>();
     a.table = c.d_table.as<double2>(); a.tab_stride = c.tab_stride;
     a.out = reinterpret_cast<double2 *>(out_dev);
     a.count_only = count_only;
-    a.stat_transitions = c.d_counters.as<unsigned long long>() + 3;
-    a.max_states = (int)max_states;
-    a.ws = c.d_ws.as<double2>();
-    a.overflow = reinterpret_cast<int32_t *>(c.d_counters.as<unsigned long long>() + 4);
+    a.stat_transitions = ctr + 3;
+    a.overflow = reinterpret_cast<int32_t *>(ctr + 4);
+    // state size: the S-side bound holds for every pattern; only when it is too
+    // large for LDS ask the device for this batch's exact maximum
+    std::vector<int16_t> slo, shi;
+    s_only_bounds(c, S, n, slo, shi);
+    int64_t max_states = program_state_bound(c, slo, shi);
+    a.max_states = (int)std::min<int64_t>(max_states, 1 << 22);
+    a.ws = nullptr;
+    if (max_states > (1 << 22) || contract_lds_bytes(a, true) > 64 * 1024) {
+        int *d_max = reinterpret_cast<int32_t *>(ctr + 5);
+        HIPCHK(launch_contract_sizes(a, d_max, s));
+        int mx = 0;
+        HIPCHK(hipMemcpyAsync(&mx, d_max, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (mx > (1 << 22)) return fail(LOFP_ENOMEM, "contraction state exceeds 2^22 entries");
+        a.max_states = std::max(mx, 1);
+        if (contract_lds_bytes(a, true) > 64 * 1024) {
+            HIPCHK(ensure(c.d_ws, (size_t)B * 2 * a.max_states * sizeof(double2)));
+            a.ws = c.d_ws.as<double2>();
+        }
+    }
+    tm.mark();
     HIPCHK(launch_contract(a, s));
     tm.mark();
     if (st) {
         unsigned long long h[8];
-        HIPCHK(hipMemcpyAsync(h, c.d_counters.p, sizeof(h), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (h[4]) return fail(LOFP_ENOMEM, "contraction workspace overflow");
         st->transitions = (int64_t)h[3];
@@ -363,18 +512,29 @@ lofp_status run_pathsum(lofp_circuit_s &c, const int32_t *S, int n, int B, const
     HIPCHK(hipStreamSynchronize(s));
     if (cnt.back()) return fail(LOFP_ENOMEM, "a frontier state space exceeds 2^31 states");
     std::vector<int64_t> off((size_t)nslots * (B + 1));
+    std::vector<int32_t> coff((size_t)nslots * (B + 1));   // chunk offsets (kGateChunk)
     std::vector<int64_t> tot(nslots);
+    std::vector<int32_t> nch(nslots);
+    static_assert(kGateChunk == kDfsChunk, "one chunk size for frontier and depth-first kernels");
     for (int k = 0; k < nslots; ++k) {
-        int64_t acc = 0;
+        int64_t acc = 0, ca = 0;
         for (int p = 0; p < B; ++p) {
             off[(size_t)k * (B + 1) + p] = acc;
+            coff[(size_t)k * (B + 1) + p] = (int32_t)ca;
             acc += cnt[(size_t)k * B + p];
+            ca += (cnt[(size_t)k * B + p] + kGateChunk - 1) / kGateChunk;
         }
+        if (ca > 0x7fffffffLL) return fail(LOFP_ENOMEM, "too many frontier chunks");
         off[(size_t)k * (B + 1) + B] = acc;
+        coff[(size_t)k * (B + 1) + B] = (int32_t)ca;
         tot[k] = acc;
+        nch[k] = (int32_t)ca;
     }
     HIPCHK(upload(c.d_off, off, s));
+    HIPCHK(upload(c.d_coff, coff, s));
     const int64_t *d_off = c.d_off.as<int64_t>();
+    auto coffp = [&](int stage) { return c.d_coff.as<int32_t>() + (size_t)slot_of[stage] * (B + 1); };
+    auto nchp = [&](int stage) { return nch[slot_of[stage]]; };
     auto offp = [&](int stage) { return d_off + (size_t)slot_of[stage] * (B + 1); };
     auto Cp = [&](int stage) { return c.d_C.as<int32_t>() + (size_t)slot_of[stage] * B * tsz; };
     auto Ep = [&](int stage) { return c.d_E.as<int32_t>() + (size_t)slot_of[stage] * B * tsz; };
@@ -402,6 +562,7 @@ lofp_status run_pathsum(lofp_circuit_s &c, const int32_t *S, int n, int B, const
         a.off_tgt = offp(g + 1); a.off_src = offp(g);
         a.W = c.d_table.as<double2>() + (size_t)g * c.tab_stride;
         a.src = F; a.dst = Fn; a.total_tgt = totp(g + 1);
+        a.chunk_off = coffp(g + 1); a.nchunks = nchp(g + 1);
         HIPCHK(launch_gate(a, true, s));
         std::swap(F, Fn);
     }
@@ -419,6 +580,7 @@ lofp_status run_pathsum(lofp_circuit_s &c, const int32_t *S, int n, int B, const
         a.off_tgt = offp(g); a.off_src = offp(g + 1);
         a.W = c.d_table.as<double2>() + (size_t)g * c.tab_stride;
         a.src = Bv; a.dst = Bn; a.total_tgt = totp(g);
+        a.chunk_off = coffp(g); a.nchunks = nchp(g);
         HIPCHK(launch_gate(a, false, s));
         std::swap(Bv, Bn);
     }
@@ -428,49 +590,75 @@ lofp_status run_pathsum(lofp_circuit_s &c, const int32_t *S, int n, int B, const
     HIPCHK(hipMemsetAsync(ctr, 0, 8 * sizeof(unsigned long long), s));
     const int levels = sb - sf;
     if (levels > 0 && totp(sf) > 0) {
-        // compact LDS image of the middle gates' tables (sectors 0..n)
+        // compact image of the middle gates' tables: sectors up to the largest
+        // photon number the S-side light cone allows at each gate
+        std::vector<int16_t> slo, shi;
+        s_only_bounds(c, S, n, slo, shi);
         std::vector<int4> info(levels);
-        const int per = sector_offset(n + 1);
+        std::vector<int> nmax(levels);
+        int tab_len = 0;
         for (int d = 0; d < levels; ++d) {
-            const int g = sf + d;
-            info[d] = make_int4(c.gate_cut[g], c.gate_layer[g], d * per, 0);
+            const int g = sf + d, a = c.gate_cut[g], l = c.gate_layer[g];
+            const int up = a + 1 < nc ? shi[(size_t)l * nc + a + 1] : n;
+            const int dn = a > 0 ? slo[(size_t)l * nc + a - 1] : 0;
+            nmax[d] = std::max(0, std::min(n, up - dn));
+            info[d] = make_int4(a, l, tab_len, 0);
+            tab_len += sector_offset(nmax[d] + 1);
         }
         HIPCHK(upload(c.d_levels, info, s));
-        HIPCHK(ensure(c.d_tab_mid, (size_t)levels * per * sizeof(double2)));
+        HIPCHK(ensure(c.d_tab_mid, (size_t)std::max(tab_len, 1) * sizeof(double2)));
         for (int d = 0; d < levels; ++d)
-            HIPCHK(hipMemcpyAsync(c.d_tab_mid.as<double2>() + (size_t)d * per,
+            HIPCHK(hipMemcpyAsync(c.d_tab_mid.as<double2>() + info[d].z,
                                   c.d_table.as<double2>() + (size_t)(sf + d) * c.tab_stride,
-                                  (size_t)per * sizeof(double2), hipMemcpyDeviceToDevice, s));
+                                  (size_t)sector_offset(nmax[d] + 1) * sizeof(double2), hipMemcpyDeviceToDevice, s));
+        const int words = nc <= 8 ? 2 : nc <= 16 ? 4 : nc <= 24 ? 6 : 8;
+        HIPCHK(ensure(c.d_cfg, (size_t)totp(sf) * words * sizeof(uint32_t)));
+        HIPCHK(ensure(c.d_rankb, (size_t)totp(sf) * sizeof(int32_t)));
+        AnnotateArgs an{};
+        an.B = B; an.m = c.m; an.n = n; an.D = D;
+        an.st_front = c.d_stage_time.as<uint8_t>() + (size_t)sf * nc;
+        an.lo = c.d_lo.as<int16_t>(); an.hi = c.d_hi.as<int16_t>();
+        an.C_front = Cp(sf); an.E_back = Ep(sb);
+        an.off_front = offp(sf);
+        an.chunk_off = coffp(sf); an.nchunks = nchp(sf);
+        an.cfg_words = words;
+        an.cfg = c.d_cfg.as<uint32_t>();
+        an.rank_back = c.d_rankb.as<int32_t>();
+        HIPCHK(launch_annotate(an, s));
         DfsArgs a{};
         a.B = B; a.m = c.m; a.n = n; a.D = D;
         a.levels = levels;
         a.level_info = c.d_levels.as<int4>();
         a.tab = c.d_tab_mid.as<double2>();
-        a.tab_len = levels * per;
-        a.st_front = c.d_stage_time.as<uint8_t>() + (size_t)sf * nc;
+        a.tab_len = tab_len;
         a.lo = c.d_lo.as<int16_t>(); a.hi = c.d_hi.as<int16_t>();
-        a.C_front = Cp(sf); a.E_back = Ep(sb);
+        a.E_back = Ep(sb);
+        a.cfg = c.d_cfg.as<uint32_t>();
+        a.rank_back = c.d_rankb.as<int32_t>();
+        a.cfg_words = words;
         a.off_front = offp(sf); a.off_back = offp(sb);
         a.front = F; a.back = Bv;
         a.total = totp(sf);
+        a.chunk_off = coffp(sf);
+        a.nchunks = nchp(sf);
         a.work_counter = ctr;
         a.stat_leaves = ctr + 1;
         a.stat_edges = ctr + 2;
         a.fp32_products = o.precision == LOFP_PREC_FP32;
-        const int block = 64;
+        const size_t lds = dfs_lds_bytes(a);
+        if (lds > 64 * 1024)
+            return fail(LOFP_ENOTSUP, "too many beam splitters between the frontiers for the LDS stack; "
+                                      "move the forward frontier later");
         int dev = 0, ncu = 256;
         if (hipGetDevice(&dev) == hipSuccess) {
             hipDeviceProp_t prop;
             if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
                 ncu = prop.multiProcessorCount;
         }
-        const size_t lds = (size_t)levels * block * (sizeof(double2) + sizeof(int2)) + levels * sizeof(int4) +
-                           (size_t)a.tab_len * sizeof(double2);
-        const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(16, (160 * 1024) / std::max<size_t>(lds, 1)));
-        int64_t grid = (int64_t)ncu * per_cu;
-        grid = std::min<int64_t>(grid, (a.total + block - 1) / block);
+        const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / std::max<size_t>(lds, 1)));
+        const int64_t grid = std::min<int64_t>((int64_t)ncu * per_cu, a.nchunks);
         tm.mark();  // 4
-        HIPCHK(launch_dfs(a, (int)std::max<int64_t>(grid, 1), block, s));
+        HIPCHK(launch_dfs(a, (int)std::max<int64_t>(grid, 1), s));
         tm.mark();  // 5
         HIPCHK(launch_reduce(B, offp(sf), F, nullptr, reinterpret_cast<double2 *>(out_dev), s));
     } else {
@@ -579,9 +767,10 @@ lofp_status lofp_circuit_destroy(lofp_circuit c)
     if (!c) return fail(LOFP_EINVAL, "null circuit");
     DevBuf *bufs[] = {&c->d_table, &c->d_theta, &c->d_phi, &c->d_fr_lo, &c->d_fr_hi, &c->d_br_lo, &c->d_br_hi,
                       &c->d_cut_gate, &c->d_stage_time, &c->d_gate_cut, &c->d_gate_layer, &c->d_cut_ngates,
-                      &c->d_cut_gates, &c->d_ver_at, &c->d_S, &c->d_lo, &c->d_hi, &c->d_inf, &c->d_C, &c->d_E,
-                      &c->d_count, &c->d_slot_stage, &c->d_off, &c->d_fa, &c->d_fb, &c->d_ba, &c->d_bb,
-                      &c->d_levels, &c->d_tab_mid, &c->d_counters, &c->d_T, &c->d_out, &c->d_ws};
+                      &c->d_cut_gates, &c->d_ver_at, &c->d_var_cut, &c->d_var_time, &c->d_steps, &c->d_S, &c->d_lo, &c->d_hi, &c->d_inf, &c->d_C, &c->d_E,
+                      &c->d_count, &c->d_slot_stage, &c->d_off, &c->d_coff, &c->d_fa, &c->d_fb, &c->d_ba, &c->d_bb,
+                      &c->d_levels, &c->d_tab_mid, &c->d_counters, &c->d_T, &c->d_out, &c->d_ws,
+                      &c->d_cfg, &c->d_rankb};
     for (DevBuf *b : bufs) release(*b);
     delete c;
     return LOFP_OK;
@@ -677,7 +866,20 @@ lofp_status lofp_amplitudes_device(lofp_circuit c, const int32_t *S, int32_t bat
     tm.on = o.record_timing != 0 && stats != nullptr;
     tm.s = s;
     tm.mark();
-    if (o.method == LOFP_METHOD_CONTRACT) {
+    int method = o.method;
+    if (method == LOFP_METHOD_AUTO) {
+        // the paper's choice for depth > 2: contract along the modes when the
+        // contraction state is affordable, otherwise enumerate paths
+        method = LOFP_METHOD_PATHSUM;
+        if (prepare_program(*c, s) == LOFP_OK) {
+            std::vector<int16_t> slo, shi;
+            s_only_bounds(*c, S, n, slo, shi);
+            if (program_state_bound(*c, slo, shi) <= (1 << 20)) method = LOFP_METHOD_CONTRACT;
+        }
+        g_err.clear();
+    }
+    if (stats) stats->method_used = method;
+    if (method == LOFP_METHOD_CONTRACT) {
         Timer inner;
         inner.on = tm.on;
         inner.s = s;

@@ -4,169 +4,204 @@
 // from one block to the next, the photon numbers of the waveguides crossing
 // the boundary together with their summed amplitudes.  Here the boundary
 // between modes r and r+1 is the cut r, and what crosses it over the whole
-// circuit is the sequence of values A_t(r): it changes only at the beam
-// splitters on that cut, so the state of cut r is the tuple of its values
-// between consecutive splitters (its "versions"; the first is fixed by S, the
-// last by T).  In a brickwork circuit a cut changes once per block of two
-// layers.  A beam splitter on cut r reads the current versions of cuts r-1,
-// r and r+1, so the sweep keeps the pair (state of cut r-1, state of cut r):
+// circuit is the sequence of its values A_t(r): it changes only at the beam
+// splitters on that cut, so its history is a short tuple of "versions" (the
+// first fixed by S, the last by T; in a brickwork one version per block of
+// two layers).  A valid path is one choice of every free version, and its
+// weight is the product over splitters of W_g(x1, N, y1), each reading four
+// versions: cut r before and after the splitter and cuts r-1 and r+1 at that
+// time (W = 0 outside 0 <= x1, y1 <= N, which also enforces the order between
+// neighbouring cuts).
 //
-//   V_{r+1}(a_r, a_{r+1}) = sum_{a_{r-1}} V_r(a_{r-1}, a_r) Phi_r(a_{r-1}, a_r, a_{r+1})
+// The sum over all versions is contracted one splitter at a time, cut by cut
+// from the top (the order of the paper's blocks): a dense state holds the
+// partial sum as a function of the versions that are still needed; each step
+// introduces the versions its splitter touches for the first time, multiplies
+// by the splitter's transition amplitude, and sums out versions that no later
+// splitter reads.  The host turns the circuit into this step program once
+// (which versions are live, where each one sits); per pattern only the value
+// ranges (from that pattern's cut bounds) differ.
 //
-// where Phi_r is the product of the transition amplitudes of every splitter on
-// cut r, and pairs that violate the order A_t(r) <= A_t(r+1) at some time are
-// zero.  The amplitude is the sum of V after the last cut.  With unit weights
-// the same sweep counts the valid paths.
-//
-// One 256-thread block per pattern; V lives in a per-pattern global workspace
-// (two buffers), each step is one pass over the target pairs, and the final
-// sum is compensated and done in a fixed order.
+// One 256-thread block per pattern; the two state buffers live in LDS when
+// they fit, else in a per-pattern global workspace.  Each step is one pass
+// over the new state, each entry gathered in a fixed order; the final sum is
+// compensated and combined in a fixed order.  With unit weights the same
+// program counts the valid paths.
 #include "lofp_device.h"
 
 namespace lofp {
 
-constexpr int kMaxVer = 16;  // versions per cut (splitters on one cut + 1)
-
-struct CutState {
-    int nv;               // number of versions (gates on the cut + 1)
-    int val[kMaxVer];     // value of each version
-};
-
-// Decode the state index of cut r (mixed radix over the free versions, first
-// free version fastest).  Versions 0 and nv-1 are fixed by S and T.
-__device__ __forceinline__ void decode_cut(const ContractArgs &g, int r, int idx, int spre, int tpre,
-                                           const int16_t *lo, const int16_t *hi, CutState &cs)
+// exact small-integer quotient via the float reciprocal (values < 2^22)
+__device__ __forceinline__ int qdiv(int a, int d, float inv)
 {
-    const int nc = g.m - 1;
-    if (r < 0 || r >= nc) {
-        cs.nv = 1;
-        cs.val[0] = r < 0 ? 0 : g.n;
-        return;
-    }
-    const int k = g.cut_ngates[r];
-    cs.nv = k + 1;
-    cs.val[0] = spre;
-#pragma unroll
-    for (int j = 1; j < kMaxVer; ++j) {
-        if (j < k) {
-            const int t = g.gate_layer[g.cut_gates[r * g.D + j - 1]] + 1;
-            const int L = lo[t * nc + r], H = hi[t * nc + r];
-            const int rad = H - L + 1;
-            const int q = idx / rad;
-            cs.val[j] = L + (idx - q * rad);
-            idx = q;
-        }
-    }
-    if (k > 0) cs.val[k] = tpre;
+    int q = __float2int_rz(__int2float_rn(a) * inv);
+    int r = a - q * d;
+    if (r < 0) { --q; r += d; }
+    if (r >= d) { ++q; }
+    return q;
 }
 
-__device__ __forceinline__ int cut_domain(const ContractArgs &g, int r, const int16_t *lo, const int16_t *hi)
-{
-    const int nc = g.m - 1;
-    if (r < 0 || r >= nc) return 1;
-    const int k = g.cut_ngates[r];
-    int dom = 1;
-    for (int j = 1; j < k; ++j) {
-        const int t = g.gate_layer[g.cut_gates[r * g.D + j - 1]] + 1;
-        const int rad = hi[t * nc + r] - lo[t * nc + r] + 1;
-        dom *= rad > 0 ? rad : 0;
-    }
-    return dom;
-}
+enum { RK_CONST = 0, RK_NEW = 1, RK_SUM = 2 };
 
-// value of cut (r) at time t, from its decoded versions
-__device__ __forceinline__ int value_at(const ContractArgs &g, int r, int t, const CutState &cs)
+// One wave (64 lanes) per pattern: contraction states here hold tens to a few
+// thousand entries, so a wave covers a step in a few passes and many patterns
+// stay resident per CU.  Every lane derives the step layout itself (no serial
+// section, no block barrier beyond the wave's).
+template <bool COUNT, bool LDS_STATE, int BS>
+__global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
 {
-    const int nc = g.m - 1;
-    if (r < 0) return 0;
-    if (r >= nc) return g.n;
-    return cs.val[g.ver_at[t * nc + r]];
-}
-
-__device__ __forceinline__ bool ordered(const ContractArgs &g, int r, const CutState &lo_c, const CutState &hi_c)
-{
-    // A_t(r) <= A_t(r+1) for every time t
-    for (int t = 0; t <= g.D; ++t)
-        if (value_at(g, r, t, lo_c) > value_at(g, r + 1, t, hi_c)) return false;
-    return true;
-}
-
-template <bool COUNT>
-__global__ __launch_bounds__(256) void k_contract(ContractArgs g)
-{
+    extern __shared__ __align__(16) unsigned char smem[];
     const int p = blockIdx.x;
     const int nc = g.m - 1, span = (g.D + 1) * nc;
     const int16_t *lo = g.lo + (int64_t)p * span, *hi = g.hi + (int64_t)p * span;
     const int32_t *Tp = g.T + (int64_t)p * g.m;
-    double2 *bufA = g.ws + (int64_t)p * 2 * g.max_states;
-    double2 *bufB = bufA + g.max_states;
-    __shared__ CSum part[2][4];
+    int *vlo = reinterpret_cast<int *>(smem);                 // [nvars]
+    int *vrad = vlo + g.nvars;                                // [nvars]
+    int *spre = vrad + g.nvars;                               // [nc]
+    int *tpre = spre + nc;                                    // [nc]
+    double2 *bufA, *bufB;
+    if (LDS_STATE) {
+        size_t off = (size_t)(2 * g.nvars + 2 * nc) * sizeof(int);
+        off = (off + 15) & ~(size_t)15;
+        bufA = reinterpret_cast<double2 *>(smem + off);
+        bufB = bufA + g.max_states;
+    } else {
+        bufA = g.ws + (int64_t)p * 2 * g.max_states;
+        bufB = bufA + g.max_states;
+    }
     if (g.infeasible[p]) {
         if (threadIdx.x == 0) g.out[p] = make_double2(0.0, 0.0);
         return;
     }
-    // prefix sums of S and T for the fixed versions
-    __shared__ int spre[kMaxCuts + 1], tpre[kMaxCuts + 1];
     if (threadIdx.x == 0) {
         int s = 0, t = 0;
         for (int r = 0; r < nc; ++r) { s += g.S[r]; t += Tp[r]; spre[r] = s; tpre[r] = t; }
     }
-    __syncthreads();
-
-    // V_0(a_{-1}, a_0) = 1 on every state of cut 0 (cut -1 has one state)
-    int dom_prev = 1, dom_cur = cut_domain(g, 0, lo, hi);
-    if ((int64_t)dom_prev * dom_cur > g.max_states) { if (threadIdx.x == 0) atomicOr(g.overflow, 1); return; }
-    for (int i = threadIdx.x; i < dom_cur; i += blockDim.x) bufA[i] = make_double2(1.0, 0.0);
+    for (int v = threadIdx.x; v < g.nvars; v += blockDim.x) {
+        const int t = g.var_time[v], r = g.var_cut[v];
+        const int L = lo[t * nc + r], H = hi[t * nc + r];
+        vlo[v] = L;
+        vrad[v] = H - L + 1;
+    }
+    if (threadIdx.x == 0) bufA[0] = make_double2(1.0, 0.0);
     __syncthreads();
     unsigned long long trans = 0;
+    int cur_size = 1;
 
-    for (int r = 0; r < nc; ++r) {
-        const int dom_next = cut_domain(g, r + 1, lo, hi);
-        const int64_t ntgt = (int64_t)dom_cur * dom_next;
-        if (ntgt > g.max_states) { if (threadIdx.x == 0) atomicOr(g.overflow, 1); return; }
-        const int k = g.cut_ngates[r];
-        for (int64_t q = threadIdx.x; q < ntgt; q += blockDim.x) {
-            const int ar = (int)(q / dom_next), an = (int)(q - (int64_t)ar * dom_next);
-            CutState cr, cn, cp;
-            decode_cut(g, r, ar, spre[r], tpre[r], lo, hi, cr);
-            decode_cut(g, r + 1, an, r + 1 < nc ? spre[r + 1] : 0, r + 1 < nc ? tpre[r + 1] : 0, lo, hi, cn);
-            double2 acc = make_double2(0.0, 0.0);
-            if (ordered(g, r, cr, cn)) {
-                for (int ap = 0; ap < dom_prev; ++ap) {
-                    const double2 vprev = bufA[(int64_t)ap * dom_cur + ar];
-                    if (vprev.x == 0.0 && vprev.y == 0.0) continue;
-                    decode_cut(g, r - 1, ap, r > 0 ? spre[r - 1] : 0, r > 0 ? tpre[r - 1] : 0, lo, hi, cp);
-                    double2 phi = make_double2(1.0, 0.0);
-                    bool ok = true;
-                    for (int j = 1; j <= k; ++j) {
-                        const int gid = g.cut_gates[r * g.D + j - 1];
-                        const int l = g.gate_layer[gid];
-                        const int vm = value_at(g, r - 1, l, cp), vp = value_at(g, r + 1, l, cn);
-                        const int x1 = cr.val[j - 1] - vm, y1 = cr.val[j] - vm, N = vp - vm;
-                        if (x1 < 0 || y1 < 0 || x1 > N || y1 > N) { ok = false; break; }
-                        if (!COUNT)
-                            phi = cmul(phi, g.table[(int64_t)gid * g.tab_stride + sector_offset(N) + x1 * (N + 1) + y1]);
-                    }
-                    if (!ok) continue;
-                    ++trans;
-                    acc = COUNT ? make_double2(acc.x + vprev.x, 0.0) : cfma(vprev, phi, acc);
+    for (int si = 0; si < g.nsteps; ++si) {
+        const ContractStep &st = g.steps[si];
+        const int n_new = st.n_new, n_old = st.n_old;
+        // old-layout strides
+        int ostr[kMaxActive];
+        {
+            int os = 1;
+#pragma unroll
+            for (int q = 0; q < kMaxActive; ++q) {
+                ostr[q] = os;
+                if (q < n_old) os *= vrad[st.old_vars[q]];
+            }
+        }
+        // new-layout strides and, per new variable, its stride in the old layout
+        int nstr[kMaxActive], mstr[kMaxActive];
+        float ninv[kMaxActive];
+        int ns = 1;
+        int nlo4[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < kMaxActive; ++q) {
+            nstr[q] = ns;
+            ninv[q] = 1.0f / (float)ns;
+            mstr[q] = 0;
+            if (q < n_new) {
+                const int v = st.new_vars[q];
+                const int src = st.new_to_old[q];
+                int ms = 0;
+#pragma unroll
+                for (int q2 = 0; q2 < kMaxActive; ++q2) ms = (q2 == src) ? ostr[q2] : ms;
+                mstr[q] = ms;
+                if (q < 4) nlo4[q] = vlo[v];
+                ns *= vrad[v];
+            }
+        }
+        const int new_size = ns;
+        if (new_size > g.max_states) {
+            if (threadIdx.x == 0) atomicOr(g.overflow, 1);
+            return;
+        }
+        int srad0 = 1, srad1 = 1, slo0 = 0, slo1 = 0, sstr0 = 0, sstr1 = 0;
+        if (st.n_sum > 0) {
+            const int v = st.sum_vars[0], src = st.sum_to_old[0];
+            srad0 = vrad[v]; slo0 = vlo[v];
+#pragma unroll
+            for (int q2 = 0; q2 < kMaxActive; ++q2) sstr0 = (q2 == src) ? ostr[q2] : sstr0;
+        }
+        if (st.n_sum > 1) {
+            const int v = st.sum_vars[1], src = st.sum_to_old[1];
+            srad1 = vrad[v]; slo1 = vlo[v];
+#pragma unroll
+            for (int q2 = 0; q2 < kMaxActive; ++q2) sstr1 = (q2 == src) ? ostr[q2] : sstr1;
+        }
+        int rk[4], ra[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int kind = st.ref_kind[k], arg = st.ref_arg[k];
+            if (kind == CREF_NEW) { rk[k] = RK_NEW; ra[k] = arg; }
+            else if (kind == CREF_SUM) { rk[k] = RK_SUM; ra[k] = arg; }
+            else {
+                rk[k] = RK_CONST;
+                ra[k] = kind == CREF_ZERO ? 0 : kind == CREF_N ? g.n : kind == CREF_SPRE ? spre[arg] : tpre[arg];
+            }
+        }
+        const double2 *Wg = g.table + (int64_t)st.gate * g.tab_stride;
+        for (int e = threadIdx.x; e < new_size; e += blockDim.x) {
+            int rem = e, base_old = 0;
+            int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
+#pragma unroll
+            for (int q = kMaxActive - 1; q >= 0; --q) {
+                if (q < n_new) {
+                    const int d = qdiv(rem, nstr[q], ninv[q]);
+                    rem -= d * nstr[q];
+                    base_old += d * mstr[q];
+                    if (q == 0) d0 = d;
+                    if (q == 1) d1 = d;
+                    if (q == 2) d2 = d;
+                    if (q == 3) d3 = d;
                 }
             }
-            bufB[q] = acc;
+            const int nv0 = nlo4[0] + d0, nv1 = nlo4[1] + d1, nv2 = nlo4[2] + d2, nv3 = nlo4[3] + d3;
+            double2 acc = make_double2(0.0, 0.0);
+            for (int i1 = 0; i1 < srad1; ++i1) {
+                for (int i0 = 0; i0 < srad0; ++i0) {
+                    const int oi = base_old + i0 * sstr0 + i1 * sstr1;
+                    const double2 prev = bufA[oi];
+                    if (prev.x == 0.0 && prev.y == 0.0) continue;
+                    int val[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int a = ra[k];
+                        const int vn = a == 0 ? nv0 : a == 1 ? nv1 : a == 2 ? nv2 : nv3;
+                        const int vs = a == 0 ? slo0 + i0 : slo1 + i1;
+                        val[k] = rk[k] == RK_NEW ? vn : rk[k] == RK_SUM ? vs : a;
+                    }
+                    const int N = val[3] - val[2], x1 = val[0] - val[2], y1 = val[1] - val[2];
+                    if (x1 < 0 || y1 < 0 || x1 > N || y1 > N) continue;
+                    ++trans;
+                    if (COUNT) acc.x += prev.x;
+                    else acc = cfma(prev, Wg[sector_offset(N) + x1 * (N + 1) + y1], acc);
+                }
+            }
+            bufB[e] = acc;
         }
         __syncthreads();
         double2 *t = bufA; bufA = bufB; bufB = t;
-        dom_prev = dom_cur;
-        dom_cur = dom_next;
+        cur_size = new_size;
     }
-    // amplitude = sum over the states of cut m-2 (cut m-1 has one state)
+    // amplitude = sum of the final state (a single entry once every version is summed)
     CSum sr{0.0, 0.0}, si{0.0, 0.0};
-    for (int i = threadIdx.x; i < dom_prev; i += blockDim.x) {
+    for (int i = threadIdx.x; i < cur_size; i += blockDim.x) {
         const double2 x = bufA[i];
         csum_add(sr, x.x);
         csum_add(si, x.y);
     }
-    // fixed-order block combine
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         CSum b{__shfl_xor(sr.s, off, 64), __shfl_xor(sr.c, off, 64)};
@@ -175,22 +210,76 @@ __global__ __launch_bounds__(256) void k_contract(ContractArgs g)
         csum_merge(sr, b);
         csum_merge(si, c);
     }
-    const int wv = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) { part[0][wv] = sr; part[1][wv] = si; }
+    __shared__ CSum part[2][BS / 64];
+    if ((threadIdx.x & 63) == 0) { part[0][threadIdx.x >> 6] = sr; part[1][threadIdx.x >> 6] = si; }
     __syncthreads();
     if (threadIdx.x == 0) {
         CSum a = part[0][0], b = part[1][0];
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) { csum_merge(a, part[0][w]); csum_merge(b, part[1][w]); }
+        for (int w = 1; w < BS / 64; ++w) { csum_merge(a, part[0][w]); csum_merge(b, part[1][w]); }
         g.out[p] = make_double2(a.s + a.c, b.s + b.c);
     }
     atomicAdd(g.stat_transitions, trans);
 }
 
+// Largest state of the step program for each pattern (one thread per pattern).
+__global__ void k_contract_sizes(ContractArgs g, int *max_size)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= g.B || g.infeasible[p]) return;
+    const int nc = g.m - 1, span = (g.D + 1) * nc;
+    const int16_t *lo = g.lo + (int64_t)p * span, *hi = g.hi + (int64_t)p * span;
+    long long mx = 1;
+    for (int si = 0; si < g.nsteps; ++si) {
+        const ContractStep &st = g.steps[si];
+        long long ns = 1;
+        for (int q = 0; q < st.n_new; ++q) {
+            const int v = st.new_vars[q];
+            const int t = g.var_time[v], r = g.var_cut[v];
+            ns *= (long long)(hi[t * nc + r] - lo[t * nc + r] + 1);
+        }
+        if (ns > mx) mx = ns;
+    }
+    atomicMax(max_size, mx > (1 << 22) ? (1 << 22) + 1 : (int)mx);
+}
+
+hipError_t launch_contract_sizes(const ContractArgs &a, int *max_size, hipStream_t stream)
+{
+    if (a.B == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_contract_sizes, dim3((a.B + 63) / 64), dim3(64), 0, stream, a, max_size);
+    return hipGetLastError();
+}
+
+size_t contract_lds_bytes(const ContractArgs &a, bool state_in_lds)
+{
+    size_t off = (size_t)(2 * a.nvars + 2 * (a.m - 1)) * sizeof(int);
+    off = (off + 15) & ~(size_t)15;
+    return off + (state_in_lds ? (size_t)2 * a.max_states * sizeof(double2) : 0);
+}
+
+template <bool COUNT, bool LDS_STATE>
+static void launch_contract_t(const ContractArgs &a, size_t dyn, hipStream_t stream)
+{
+    // small states: one wave per pattern keeps more patterns resident;
+    // large states: four waves share the pattern's LDS state
+    if (a.max_states <= 512)
+        hipLaunchKernelGGL((k_contract<COUNT, LDS_STATE, 64>), dim3(a.B), dim3(64), dyn, stream, a);
+    else
+        hipLaunchKernelGGL((k_contract<COUNT, LDS_STATE, 256>), dim3(a.B), dim3(256), dyn, stream, a);
+}
+
 hipError_t launch_contract(const ContractArgs &a, hipStream_t stream)
 {
     if (a.B == 0) return hipSuccess;
-    if (a.count_only) hipLaunchKernelGGL((k_contract<true>), dim3(a.B), dim3(256), 0, stream, a);
-    else hipLaunchKernelGGL((k_contract<false>), dim3(a.B), dim3(256), 0, stream, a);
+    const bool in_lds = a.ws == nullptr;
+    const size_t dyn = contract_lds_bytes(a, in_lds);
+    if (dyn > 64 * 1024) return hipErrorInvalidValue;
+    if (a.count_only) {
+        if (in_lds) launch_contract_t<true, true>(a, dyn, stream);
+        else launch_contract_t<true, false>(a, dyn, stream);
+    } else {
+        if (in_lds) launch_contract_t<false, true>(a, dyn, stream);
+        else launch_contract_t<false, false>(a, dyn, stream);
+    }
     return hipGetLastError();
 }
 

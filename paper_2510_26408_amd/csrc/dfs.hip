@@ -41,192 +41,302 @@ struct PackedCuts {
     }
 };
 
-template <int NW, bool TAB_LDS, bool FP32>
-__global__ __launch_bounds__(64) void k_dfs(DfsArgs g)
+constexpr int kTabMax = kMaxCuts * (kMaxPhotons + 2);
+
+// ---------------------------------------------------------------- annotate
+// One block per chunk of consecutive frontier entries of one pattern.
+__global__ __launch_bounds__(kDfsChunk) void k_annotate(AnnotateArgs g)
+{
+    __shared__ int32_t sC[kTabMax], sE[kTabMax];
+    __shared__ int16_t sL[kMaxCuts], sH[kMaxCuts];
+    __shared__ int s_p;
+    const int nc = g.m - 1, W = table_cols(g.n), span = (g.D + 1) * nc, tsz = nc * W;
+    if (threadIdx.x == 0) {
+        int lo = 0, hi = g.B - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (g.chunk_off[mid] <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
+        }
+        s_p = lo;
+    }
+    __syncthreads();
+    const int p = s_p;
+    const int16_t *lo = g.lo + (int64_t)p * span, *hi = g.hi + (int64_t)p * span;
+    for (int i = threadIdx.x; i < tsz; i += blockDim.x) {
+        sC[i] = g.C_front[(int64_t)p * tsz + i];
+        sE[i] = g.E_back[(int64_t)p * tsz + i];
+    }
+    for (int r = threadIdx.x; r < nc; r += blockDim.x) {
+        const int t = g.st_front[r];
+        sL[r] = lo[t * nc + r];
+        sH[r] = hi[t * nc + r];
+    }
+    __syncthreads();
+    const int64_t i = (int64_t)(blockIdx.x - g.chunk_off[p]) * kDfsChunk + threadIdx.x;
+    const int64_t base = g.off_front[p];
+    if (i >= g.off_front[p + 1] - base) return;
+    int64_t rem = i;
+    int pv = 0, rank = 0;
+    uint32_t w = 0;
+    uint32_t *out = g.cfg + (base + i) * g.cfg_words;
+    for (int r = 0; r < nc; ++r) {
+        const int L = sL[r], H = sH[r];
+        const int32_t *Cr = sC + r * W;
+        const int64_t b0 = Cr[pv];
+        int v = pv > L ? pv : L;
+        while (v < H && (int64_t)Cr[v + 1] - b0 <= rem) ++v;
+        rem -= (int64_t)Cr[v] - b0;
+        pv = v;
+        w |= (uint32_t)v << ((r & 3) * 8);
+        if ((r & 3) == 3) { out[r >> 2] = w; w = 0; }
+        rank += sE[r * W + v];
+    }
+    if (nc & 3) out[(nc - 1) >> 2] = w;
+    for (int q = (nc + 3) >> 2; q < g.cfg_words; ++q) out[q] = 0;
+    g.rank_back[base + i] = rank;
+}
+
+hipError_t launch_annotate(const AnnotateArgs &a, hipStream_t stream)
+{
+    if (a.nchunks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_annotate, dim3(a.nchunks), dim3(kDfsChunk), 0, stream, a);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------- dfs
+constexpr int kMaxLevels = 128;
+
+// Dynamic LDS layout of k_dfs.
+struct DfsLds {
+    size_t tab, lev, stP, stM, E, LH, total;
+};
+__host__ __device__ inline DfsLds dfs_layout(int tab_len, int levels, int tsz)
+{
+    DfsLds L;
+    size_t o = 0;
+    L.tab = o; o += (size_t)tab_len * 16;
+    L.stP = o; o += (size_t)levels * kDfsBlock * 16;
+    L.lev = o; o += (size_t)levels * 16;
+    L.stM = o; o += (size_t)levels * kDfsBlock * 8;
+    L.LH = o; o += (size_t)levels * 8;
+    L.E = o; o += (size_t)tsz * 4;
+    L.total = (o + 15) & ~(size_t)15;
+    return L;
+}
+
+// Four waves per block share the middle gates' tables.  The block takes
+// chunks of kDfsChunk consecutive frontier entries of one pattern; the
+// pattern's backward rank table and the cut intervals of the levels are staged
+// in LDS when the pattern changes, and lanes pull entries from an LDS counter.
+template <int NW, bool FP32, bool TAB_LDS>
+__global__ __launch_bounds__(kDfsBlock) void k_dfs(DfsArgs g)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    double2 *tab_s = reinterpret_cast<double2 *>(smem);
-    int4 *lev = reinterpret_cast<int4 *>(tab_s + (TAB_LDS ? g.tab_len : 0));
-    double2 *stP = reinterpret_cast<double2 *>(lev + g.levels);
-    int2 *stM = reinterpret_cast<int2 *>(stP + g.levels * blockDim.x);
-    const int tid = threadIdx.x, bd = blockDim.x;
+    const int nc = g.m - 1, W = table_cols(g.n), span = (g.D + 1) * nc, tsz = nc * W;
+    const DfsLds Ly = dfs_layout(TAB_LDS ? g.tab_len : 0, g.levels, tsz);
+    double2 *tab_s = reinterpret_cast<double2 *>(smem + Ly.tab);
+    const double2 *tab = TAB_LDS ? tab_s : g.tab;
+    int4 *lev = reinterpret_cast<int4 *>(smem + Ly.lev);
+    double2 *stP = reinterpret_cast<double2 *>(smem + Ly.stP);
+    int2 *stM = reinterpret_cast<int2 *>(smem + Ly.stM);
+    int32_t *sE = reinterpret_cast<int32_t *>(smem + Ly.E);
+    int2 *sLH = reinterpret_cast<int2 *>(smem + Ly.LH);
+    __shared__ int s_chunk, s_p, s_cnt, s_beg, s_end;
+    const int tid = threadIdx.x, bd = kDfsBlock;
 
     if (TAB_LDS)
         for (int i = tid; i < g.tab_len; i += bd) tab_s[i] = g.tab[i];
     for (int i = tid; i < g.levels; i += bd) lev[i] = g.level_info[i];
     __syncthreads();
-    const double2 *tab = TAB_LDS ? tab_s : g.tab;
 
-    const int nc = g.m - 1, W = table_cols(g.n), span = (g.D + 1) * nc;
     const int last = g.levels - 1;
-
-    PackedCuts<NW> A;
-    int64_t k = 0;
-    const int16_t *plo = nullptr, *phi = nullptr;
-    const int32_t *Eb = nullptr;
-    const double2 *Bp = nullptr;
-    int d = 0, v = 0, vhi = -1, old = 0, prev = 0, N = 0, x1 = 0, a = 0, tb = 0, rank = 0;
-    double2 P = make_double2(1.0, 0.0);
-    float2 Pf = make_float2(1.f, 0.f);
-    CSum sr{0.0, 0.0}, si{0.0, 0.0};
     unsigned long long leaves = 0, edges = 0;
-    bool need = true;
-
-    auto init_level = [&]() {
-        const int4 L = lev[d];
-        a = L.x;
-        tb = L.z;
-        const int t = L.y + 1;
-        prev = a > 0 ? A.get(a - 1) : 0;
-        const int next = a + 1 < nc ? A.get(a + 1) : g.n;
-        old = A.get(a);
-        x1 = old - prev;
-        N = next - prev;
-        const int Lo = plo[t * nc + a], Hi = phi[t * nc + a];
-        v = Lo > prev ? Lo : prev;
-        vhi = Hi < next ? Hi : next;
-    };
+    int cur_p = -1;
 
     while (true) {
-        if (need) {
-            const unsigned long long kk = atomicAdd(g.work_counter, 1ull);
-            if (kk >= (unsigned long long)g.total) break;
-            k = (int64_t)kk;
-            const int p = find_pattern(g.off_front, g.B, k);
-            const int64_t i = k - g.off_front[p];
-            plo = g.lo + (int64_t)p * span;
-            phi = g.hi + (int64_t)p * span;
-            Eb = g.E_back + (int64_t)p * nc * W;
-            Bp = g.back + g.off_back[p];
-            const int32_t *Cf = g.C_front + (int64_t)p * nc * W;
-            // unrank the frontier configuration into packed cut values
-            int64_t rem = i;
-            int pv = 0;
-            rank = 0;
-#pragma unroll
-            for (int q = 0; q < NW; ++q) A.w[q] = 0;
-#pragma unroll
-            for (int r = 0; r < 4 * NW; ++r) {
-                if (r < nc) {
-                    const int t = g.st_front[r];
-                    const int Lr = plo[t * nc + r], Hr = phi[t * nc + r];
-                    const int32_t *Cr = Cf + r * W;
-                    const int64_t base = Cr[pv];
-                    int vv = pv > Lr ? pv : Lr;
-                    while (vv < Hr && (int64_t)Cr[vv + 1] - base <= rem) ++vv;
-                    rem -= (int64_t)Cr[vv] - base;
-                    pv = vv;
-                    A.w[r >> 2] |= (uint32_t)vv << ((r & 3) * 8);
-                    rank += Eb[r * W + vv];
-                }
+        if (tid == 0) s_chunk = (int)atomicAdd(g.work_counter, 1ull);
+        __syncthreads();
+        const int c = s_chunk;
+        if (c >= g.nchunks) break;
+        if (tid == 0) {
+            int lo = 0, hi = g.B - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (g.chunk_off[mid] <= c) lo = mid; else hi = mid - 1;
             }
-            d = 0;
-            P = make_double2(1.0, 0.0);
-            Pf = make_float2(1.f, 0.f);
-            sr = CSum{0.0, 0.0};
-            si = CSum{0.0, 0.0};
-            init_level();
-            need = false;
+            s_p = lo;
+            s_cnt = 0;
+            const int64_t cnt = g.off_front[lo + 1] - g.off_front[lo];
+            const int64_t b = (int64_t)(c - g.chunk_off[lo]) * kDfsChunk;
+            s_beg = (int)b;
+            s_end = (int)(b + kDfsChunk < cnt ? b + kDfsChunk : cnt);
         }
-        if (v > vhi) {
-            if (d == 0) {
-                const double2 f = g.front[k];
-                const double2 s = make_double2(sr.s + sr.c, si.s + si.c);
-                g.front[k] = cmul(f, s);
-                need = true;
-                continue;
+        __syncthreads();
+        const int p = s_p;
+        if (p != cur_p) {
+            const int16_t *plo = g.lo + (int64_t)p * span, *phi = g.hi + (int64_t)p * span;
+            for (int i = tid; i < tsz; i += bd) sE[i] = g.E_back[(int64_t)p * tsz + i];
+            for (int d = tid; d < g.levels; d += bd) {
+                const int4 L = lev[d];
+                const int t = L.y + 1;
+                sLH[d] = make_int2(plo[t * nc + L.x], phi[t * nc + L.x]);
             }
-            A.set(a, old);
-            --d;
-            const int2 M = stM[d * bd + tid];
-            if (FP32) {
-                const double2 q = stP[d * bd + tid];
-                Pf = make_float2((float)q.x, (float)q.y);
-            } else {
-                P = stP[d * bd + tid];
-            }
-            rank = M.y;
-            v = (M.x & 0xff) + 1;
-            vhi = (M.x >> 8) & 0xff;
-            old = (M.x >> 16) & 0xff;
+            cur_p = p;
+        }
+        __syncthreads();
+        const int beg = s_beg, end = s_end;
+        const int64_t kbase = g.off_front[p];
+        const double2 *Bp = g.back + g.off_back[p];
+
+        PackedCuts<NW> A;
+        int64_t k = 0;
+        int d = 0, v = 0, vhi = -1, old = 0, prev = 0, N = 0, x1 = 0, a = 0, tb = 0, rank = 0;
+        double2 P = make_double2(1.0, 0.0);
+        float2 Pf = make_float2(1.f, 0.f);
+        CSum sr{0.0, 0.0}, si{0.0, 0.0};
+        bool need = true;
+
+        auto init_level = [&]() {
             const int4 L = lev[d];
             a = L.x;
             tb = L.z;
             prev = a > 0 ? A.get(a - 1) : 0;
             const int next = a + 1 < nc ? A.get(a + 1) : g.n;
+            old = A.get(a);
             x1 = old - prev;
             N = next - prev;
-            continue;
-        }
-        const double2 w = tab[tb + sector_offset(N) + x1 * (N + 1) + (v - prev)];
-        const int rn = rank + Eb[a * W + v] - Eb[a * W + old];
-        ++edges;
-        if (FP32) {
-            const float2 wf = make_float2((float)w.x, (float)w.y);
-            const float2 Pn = make_float2(Pf.x * wf.x - Pf.y * wf.y, Pf.x * wf.y + Pf.y * wf.x);
-            if (d == last) {
-                const double2 b = Bp[rn];
-                const double2 c = cmul(make_double2((double)Pn.x, (double)Pn.y), b);
-                csum_add(sr, c.x);
-                csum_add(si, c.y);
-                ++leaves;
-                ++v;
+            const int2 LH = sLH[d];
+            v = LH.x > prev ? LH.x : prev;
+            vhi = LH.y < next ? LH.y : next;
+        };
+
+        while (true) {
+            if (need) {
+                const int e = beg + atomicAdd(&s_cnt, 1);
+                if (e >= end) break;
+                k = kbase + e;
+#pragma unroll
+                for (int q = 0; q < NW; ++q) A.w[q] = g.cfg[k * g.cfg_words + q];
+                rank = g.rank_back[k];
+                d = 0;
+                P = make_double2(1.0, 0.0);
+                Pf = make_float2(1.f, 0.f);
+                sr = CSum{0.0, 0.0};
+                si = CSum{0.0, 0.0};
+                init_level();
+                need = false;
+            }
+            if (v > vhi) {
+                if (d == 0) {
+                    const double2 f = g.front[k];
+                    const double2 s = make_double2(sr.s + sr.c, si.s + si.c);
+                    g.front[k] = cmul(f, s);
+                    need = true;
+                    continue;
+                }
+                A.set(a, old);
+                --d;
+                const int2 M = stM[d * bd + tid];
+                if (FP32) {
+                    const double2 q = stP[d * bd + tid];
+                    Pf = make_float2((float)q.x, (float)q.y);
+                } else {
+                    P = stP[d * bd + tid];
+                }
+                rank = M.y;
+                v = (M.x & 0xff) + 1;
+                vhi = (M.x >> 8) & 0xff;
+                old = (M.x >> 16) & 0xff;
+                const int4 L = lev[d];
+                a = L.x;
+                tb = L.z;
+                prev = a > 0 ? A.get(a - 1) : 0;
+                const int next = a + 1 < nc ? A.get(a + 1) : g.n;
+                x1 = old - prev;
+                N = next - prev;
                 continue;
             }
-            stP[d * bd + tid] = make_double2((double)Pf.x, (double)Pf.y);
-            stM[d * bd + tid] = make_int2(v | (vhi << 8) | (old << 16), rank);
-            A.set(a, v);
-            ++d;
-            Pf = Pn;
-        } else {
-            const double2 Pn = cmul(P, w);
+            const int wrow = tb + sector_offset(N) + x1 * (N + 1) - prev;
+            const int32_t *Ea = sE + a * W;
+            const int rbase = rank - Ea[old];
             if (d == last) {
-                const double2 c = cmul(Pn, Bp[rn]);
-                csum_add(sr, c.x);
-                csum_add(si, c.y);
-                ++leaves;
-                ++v;
+                // the whole leaf level in one iteration: independent loads
+                for (; v <= vhi; ++v) {
+                    const double2 w = tab[wrow + v];
+                    const double2 b = Bp[rbase + Ea[v]];
+                    double2 c2;
+                    if (FP32) {
+                        const float2 Pn = make_float2(Pf.x * (float)w.x - Pf.y * (float)w.y,
+                                                      Pf.x * (float)w.y + Pf.y * (float)w.x);
+                        c2 = cmul(make_double2((double)Pn.x, (double)Pn.y), b);
+                    } else {
+                        c2 = cmul(cmul(P, w), b);
+                    }
+                    csum_add(sr, c2.x);
+                    csum_add(si, c2.y);
+                    ++leaves;
+                }
                 continue;
             }
-            stP[d * bd + tid] = P;
+            const double2 w = tab[wrow + v];
+            const int rn = rbase + Ea[v];
+            ++edges;
             stM[d * bd + tid] = make_int2(v | (vhi << 8) | (old << 16), rank);
+            if (FP32) {
+                stP[d * bd + tid] = make_double2((double)Pf.x, (double)Pf.y);
+                Pf = make_float2(Pf.x * (float)w.x - Pf.y * (float)w.y, Pf.x * (float)w.y + Pf.y * (float)w.x);
+            } else {
+                stP[d * bd + tid] = P;
+                P = cmul(P, w);
+            }
             A.set(a, v);
             ++d;
-            P = Pn;
+            rank = rn;
+            init_level();
         }
-        rank = rn;
-        init_level();
+        __syncthreads();
     }
     atomicAdd(g.stat_leaves, leaves);
-    atomicAdd(g.stat_edges, edges);
+    atomicAdd(g.stat_edges, edges + leaves);
 }
 
-template <bool TAB_LDS, bool FP32>
-static hipError_t launch_dfs_nw(const DfsArgs &a, int grid, int block, size_t lds, hipStream_t stream)
+static bool dfs_tables_in_lds(const DfsArgs &a)
+{
+    return dfs_layout(a.tab_len, a.levels, (a.m - 1) * table_cols(a.n)).total <= 64 * 1024;
+}
+
+size_t dfs_lds_bytes(const DfsArgs &a)
+{
+    return dfs_layout(dfs_tables_in_lds(a) ? a.tab_len : 0, a.levels, (a.m - 1) * table_cols(a.n)).total;
+}
+
+template <bool FP32, bool TAB_LDS>
+static void launch_dfs_t(const DfsArgs &a, dim3 gr, size_t lds, hipStream_t stream)
 {
     const int nc = a.m - 1;
-    if (nc <= 8) hipLaunchKernelGGL((k_dfs<2, TAB_LDS, FP32>), dim3(grid), dim3(block), lds, stream, a);
-    else if (nc <= 16) hipLaunchKernelGGL((k_dfs<4, TAB_LDS, FP32>), dim3(grid), dim3(block), lds, stream, a);
-    else if (nc <= 24) hipLaunchKernelGGL((k_dfs<6, TAB_LDS, FP32>), dim3(grid), dim3(block), lds, stream, a);
-    else hipLaunchKernelGGL((k_dfs<8, TAB_LDS, FP32>), dim3(grid), dim3(block), lds, stream, a);
-    return hipGetLastError();
+    const dim3 bl(kDfsBlock);
+    if (nc <= 8) hipLaunchKernelGGL((k_dfs<2, FP32, TAB_LDS>), gr, bl, lds, stream, a);
+    else if (nc <= 16) hipLaunchKernelGGL((k_dfs<4, FP32, TAB_LDS>), gr, bl, lds, stream, a);
+    else if (nc <= 24) hipLaunchKernelGGL((k_dfs<6, FP32, TAB_LDS>), gr, bl, lds, stream, a);
+    else hipLaunchKernelGGL((k_dfs<8, FP32, TAB_LDS>), gr, bl, lds, stream, a);
 }
 
-hipError_t launch_dfs(const DfsArgs &a, int grid, int block, hipStream_t stream)
+hipError_t launch_dfs(const DfsArgs &a, int grid, hipStream_t stream)
 {
-    if (a.total == 0 || a.levels == 0) return hipSuccess;
-    const size_t stack = (size_t)a.levels * block * (sizeof(double2) + sizeof(int2));
-    const size_t meta = (size_t)a.levels * sizeof(int4);
-    const size_t tabb = (size_t)a.tab_len * sizeof(double2);
-    const bool lds_tab = tabb + meta + stack <= 64 * 1024;
-    const size_t lds = (lds_tab ? tabb : 0) + meta + stack;
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
-    if (lds_tab) {
-        if (a.fp32_products) return launch_dfs_nw<true, true>(a, grid, block, lds, stream);
-        return launch_dfs_nw<true, false>(a, grid, block, lds, stream);
+    if (a.total == 0 || a.levels == 0 || a.nchunks == 0) return hipSuccess;
+    if (a.levels > kMaxLevels) return hipErrorInvalidValue;
+    const size_t lds = dfs_lds_bytes(a);
+    if (lds > 64 * 1024) return hipErrorInvalidValue;
+    const bool in_lds = dfs_tables_in_lds(a);
+    const dim3 gr(grid);
+    if (a.fp32_products) {
+        if (in_lds) launch_dfs_t<true, true>(a, gr, lds, stream);
+        else launch_dfs_t<true, false>(a, gr, lds, stream);
+    } else {
+        if (in_lds) launch_dfs_t<false, true>(a, gr, lds, stream);
+        else launch_dfs_t<false, false>(a, gr, lds, stream);
     }
-    if (a.fp32_products) return launch_dfs_nw<false, true>(a, grid, block, lds, stream);
-    return launch_dfs_nw<false, false>(a, grid, block, lds, stream);
+    return hipGetLastError();
 }
 
 }  // namespace lofp

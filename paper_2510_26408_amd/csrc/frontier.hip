@@ -22,30 +22,57 @@ hipError_t launch_seed(int B, const int64_t *off, double2 *vec, hipStream_t stre
     return hipGetLastError();
 }
 
+constexpr int kTabMax = kMaxCuts * (kMaxPhotons + 2);
+
+// One block per chunk of kGateChunk consecutive target states of one pattern;
+// the pattern's rank tables and intervals are staged in LDS once per block.
 template <int NCM, bool FWD>
-__global__ __launch_bounds__(256) void k_gate(GateArgs g)
+__global__ __launch_bounds__(kGateChunk) void k_gate(GateArgs g)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= g.total_tgt) return;
-    const int p = find_pattern(g.off_tgt, g.B, k);
-    const int64_t i = k - g.off_tgt[p];
-    const int nc = g.m - 1, W = table_cols(g.n), span = (g.D + 1) * nc;
+    __shared__ int32_t sC[kTabMax], sE[kTabMax];
+    __shared__ int16_t sL[kMaxCuts], sH[kMaxCuts];
+    __shared__ int s_p, s_Ls, s_Hs;
+    const int nc = g.m - 1, W = table_cols(g.n), span = (g.D + 1) * nc, tsz = nc * W;
+    if (threadIdx.x == 0) {
+        int lo = 0, hi = g.B - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (g.chunk_off[mid] <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
+        }
+        s_p = lo;
+    }
+    __syncthreads();
+    const int p = s_p;
     const int16_t *lo = g.lo + (int64_t)p * span, *hi = g.hi + (int64_t)p * span;
-    const int32_t *Ct = g.C_tgt + (int64_t)p * nc * W;
-    const int32_t *Es = g.E_src + (int64_t)p * nc * W;
+    const int32_t *Ct = g.C_tgt + (int64_t)p * tsz;
+    const int32_t *Es = g.E_src + (int64_t)p * tsz;
+    for (int i = threadIdx.x; i < tsz; i += blockDim.x) { sC[i] = Ct[i]; sE[i] = Es[i]; }
+    for (int r = threadIdx.x; r < nc; r += blockDim.x) {
+        const int t = g.st_tgt[r];
+        sL[r] = lo[t * nc + r];
+        sH[r] = hi[t * nc + r];
+    }
     const int a = g.cut;
+    if (threadIdx.x == 0) {
+        const int ts = g.st_src[a];
+        s_Ls = lo[ts * nc + a];
+        s_Hs = hi[ts * nc + a];
+    }
+    __syncthreads();
+    const int64_t i = (int64_t)(blockIdx.x - g.chunk_off[p]) * kGateChunk + threadIdx.x;
+    const int64_t base_t = g.off_tgt[p];
+    if (i >= g.off_tgt[p + 1] - base_t) return;
 
     // unrank the target configuration; collect the neighbours of cut a and
-    // the source rank of every cut other than a
+    // the source rank contributed by every cut other than a
     int prev = 0, next = g.n, cur = 0;
     int64_t rem = i, K = 0;
     int pv = 0;
 #pragma unroll
     for (int r = 0; r < NCM; ++r) {
         if (r < nc) {
-            const int t = g.st_tgt[r];
-            const int L = lo[t * nc + r], H = hi[t * nc + r];
-            const int32_t *Cr = Ct + r * W;
+            const int L = sL[r], H = sH[r];
+            const int32_t *Cr = sC + r * W;
             const int64_t base = Cr[pv];
             int v = pv > L ? pv : L;
             while (v < H && (int64_t)Cr[v + 1] - base <= rem) ++v;
@@ -54,29 +81,28 @@ __global__ __launch_bounds__(256) void k_gate(GateArgs g)
             if (r == a - 1) prev = v;
             if (r == a + 1) next = v;
             if (r == a) cur = v;
-            else K += Es[r * W + v];
+            else K += sE[r * W + v];
         }
     }
     const int N = next - prev;
-    const int ts = g.st_src[a];
-    const int Ls = lo[ts * nc + a], Hs = hi[ts * nc + a];
+    const int Ls = s_Ls, Hs = s_Hs;
     const int ulo = Ls > prev ? Ls : prev, uhi = Hs < next ? Hs : next;
     const double2 *Wn = g.W + sector_offset(N);
     const double2 *src = g.src + g.off_src[p];
-    const int32_t *Ea = Es + a * W;
+    const int32_t *Ea = sE + a * W;
     double2 acc = make_double2(0.0, 0.0);
     for (int u = ulo; u <= uhi; ++u) {
         const double2 w = FWD ? Wn[(u - prev) * (N + 1) + (cur - prev)] : Wn[(cur - prev) * (N + 1) + (u - prev)];
         acc = cfma(w, src[K + Ea[u]], acc);
     }
-    g.dst[k] = acc;
+    g.dst[base_t + i] = acc;
 }
 
 hipError_t launch_gate(const GateArgs &a, bool forward, hipStream_t stream)
 {
-    if (a.total_tgt == 0) return hipSuccess;
-    const int block = 256;
-    const dim3 grid((unsigned)((a.total_tgt + block - 1) / block));
+    if (a.total_tgt == 0 || a.nchunks == 0) return hipSuccess;
+    const int block = kGateChunk;
+    const dim3 grid((unsigned)a.nchunks);
     const int nc = a.m - 1;
     if (nc <= 15) {
         if (forward) hipLaunchKernelGGL((k_gate<15, true>), grid, dim3(block), 0, stream, a);

@@ -85,7 +85,10 @@ struct GateArgs {
     const double2 *src;
     double2 *dst;
     int64_t total_tgt;
+    const int32_t *chunk_off;  // [B+1] prefix of ceil(count_tgt[p] / kGateChunk)
+    int nchunks;
 };
+constexpr int kGateChunk = 256;
 hipError_t launch_gate(const GateArgs &a, bool forward, hipStream_t stream);
 
 // a4: depth-first enumeration of the middle beam splitters.
@@ -95,48 +98,86 @@ struct DfsArgs {
     const int4 *level_info;   // [levels]: {cut, layer, table offset, 0}
     const double2 *tab;       // compact tables of the middle gates
     int tab_len;              // entries in tab
-    const uint8_t *st_front;  // stage_time row of the forward frontier stage
     const int16_t *lo, *hi;
-    const int32_t *C_front;   // [B][(m-1)(n+2)] rank tables of the frontier
     const int32_t *E_back;    // [B][(m-1)(n+2)] rank tables of the backward stage
+    const uint32_t *cfg;      // [total][cfg_words] packed cut values of each entry
+    const int32_t *rank_back; // [total] rank of each entry's configuration at s_b
+    int cfg_words;
     const int64_t *off_front; // [B+1]
     const int64_t *off_back;  // [B+1]
     double2 *front;           // frontier values; overwritten by value * suffix sum
     const double2 *back;      // backward frontier values
     int64_t total;            // frontier entries
+    const int32_t *chunk_off; // [B+1] prefix of ceil(count_front[p] / kDfsChunk)
+    int nchunks;
     unsigned long long *work_counter;
     unsigned long long *stat_leaves;
     unsigned long long *stat_edges;
     int fp32_products;        // 1: running products in FP32
 };
-hipError_t launch_dfs(const DfsArgs &a, int grid, int block, hipStream_t stream);
+constexpr int kDfsChunk = 256;
+constexpr int kDfsBlock = 128;
+hipError_t launch_dfs(const DfsArgs &a, int grid, hipStream_t stream);
+size_t dfs_lds_bytes(const DfsArgs &a);
+
+// a3/a4: per frontier entry, its packed cut values (cfg_words words of four
+// 8-bit cut values) and its rank in the backward stage's state space.
+struct AnnotateArgs {
+    int B, m, n, D;
+    const uint8_t *st_front;
+    const int16_t *lo, *hi;
+    const int32_t *C_front, *E_back;
+    const int64_t *off_front;
+    const int32_t *chunk_off;
+    int nchunks;
+    int cfg_words;
+    uint32_t *cfg;
+    int32_t *rank_back;
+};
+hipError_t launch_annotate(const AnnotateArgs &a, hipStream_t stream);
 
 // a5: per-pattern compensated reduction: sum of vec over the pattern's
 // entries, or of vec[i] * back[i] when back != nullptr.
 hipError_t launch_reduce(int B, const int64_t *off, const double2 *vec, const double2 *back,
                          double2 *out, hipStream_t stream);
 
-// a6: mode-axis contraction.
+// a6: mode-axis contraction, one splitter per step.
+constexpr int kMaxActive = 16;         // live versions in a contraction state
+constexpr int kMaxContractVars = 1024; // free versions in a circuit
+enum { CREF_ZERO = 0, CREF_N = 1, CREF_SPRE = 2, CREF_TPRE = 3, CREF_NEW = 4, CREF_SUM = 5 };
+struct ContractStep {
+    int gate;
+    int n_new, n_old, n_sum;
+    int new_vars[kMaxActive];     // live free versions after the step (refs first)
+    int old_vars[kMaxActive];     // live free versions before the step
+    int new_to_old[kMaxActive];   // position in the old layout, or -1 if introduced
+    int sum_vars[2];              // versions summed out by this step
+    int sum_to_old[2];            // their old position, or -1 if introduced and summed here
+    int ref_kind[4], ref_arg[4];  // cut before / after the splitter, cut below, cut above
+};
 struct ContractArgs {
-    int B, m, n, D, G;
+    int B, m, n, D;
     const int32_t *S;         // [m]
     const int32_t *T;         // [B][m]
     const int16_t *lo, *hi;   // [B][(D+1)(m-1)]
     const int32_t *infeasible;
-    const int32_t *gate_cut;  // [G]
-    const int32_t *gate_layer;// [G]
-    const int32_t *cut_ngates;// [m-1]  gates on each cut
-    const int32_t *cut_gates; // [m-1][D] gate ids on each cut in time order
-    const int32_t *ver_at;    // [(D+1)][m-1] version index of cut r at time t
+    int nvars;
+    const int32_t *var_cut;   // [nvars]
+    const int32_t *var_time;  // [nvars] time index whose bounds apply
+    int nsteps;
+    const ContractStep *steps;
     const double2 *table;
     int tab_stride;
     double2 *out;             // amplitudes, or counts in .x when count_only
     int count_only;
     unsigned long long *stat_transitions;
-    int max_states;           // workspace states per pattern (per buffer)
-    double2 *ws;              // [B][2][max_states] workspace
+    int max_states;           // entries per state buffer
+    double2 *ws;              // [B][2][max_states] when the state does not fit LDS
     int32_t *overflow;
 };
 hipError_t launch_contract(const ContractArgs &a, hipStream_t stream);
+hipError_t launch_contract_sizes(const ContractArgs &a, int *max_size, hipStream_t stream);
+// dynamic LDS of the contraction kernel (state buffers included when in LDS)
+size_t contract_lds_bytes(const ContractArgs &a, bool state_in_lds);
 
 }  // namespace lofp

@@ -231,3 +231,16 @@ def test_pathsum_state_space_overflow_is_reported():
     with pytest.raises(lofp.LofpError) as e:
         c.amplitudes(wl.S, wl.Ts, lofp.make_opts(method=lofp.METHOD_PATHSUM, fwd_layer=3, bwd_layer=3))
     assert e.value.status == lofp.ENOMEM
+
+
+def test_auto_picks_contraction_and_matches_pathsum():
+    wl = workloads.make("c2", seed=2, batch=32)
+    c = lofp.Circuit(wl.m, wl.layers)
+    st = lofp.Stats()
+    a = c.amplitudes(wl.S, wl.Ts, lofp.make_opts(), st)
+    assert st.method_used == lofp.METHOD_CONTRACT
+    st2 = lofp.Stats()
+    b = c.amplitudes(wl.S, wl.Ts, lofp.make_opts(method=lofp.METHOD_PATHSUM), st2)
+    assert st2.method_used == lofp.METHOD_PATHSUM
+    check(a, b)
+    check(a, oracle_amps(wl.m, wl.S, wl.Ts, wl.layers))
