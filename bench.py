@@ -249,10 +249,63 @@ def run_variant(lofp, workloads, torch, dev, stream, name, method, steps=5):
 
 
 def variants(lofp, workloads, torch, dev, stream):
-    """The depth-first path-sum form on the same batch, and the contraction on
-    the m=32, n=16 workload."""
+    """The depth-first path-sum form on the same batch, the contraction on the
+    m=32, n=16 workload, and the served mixed-request workload."""
     return {"pathsum_c2": run_variant(lofp, workloads, torch, dev, stream, "c2", lofp.METHOD_PATHSUM, steps=3),
-            "contract_c5": run_variant(lofp, workloads, torch, dev, stream, "c5", lofp.METHOD_CONTRACT, steps=20)}
+            "contract_c5": run_variant(lofp, workloads, torch, dev, stream, "c5", lofp.METHOD_CONTRACT, steps=20),
+            "served_c4": serve_variant(lofp, workloads)}
+
+
+def serve_variant(lofp, workloads, n_req=2000, n_warm=200, rate_frac=0.5):
+    """Served mixed requests: m in {12,16,24}, n=m/2, depth in {4,6,8}, a fresh
+    circuit and pattern per request, FP32 path products with FP64 sums.
+    First the saturated throughput (everything submitted at once), then
+    Poisson arrivals at rate_frac of it; p50/p99 from submit to completion."""
+    reqs = workloads.served_requests(n_req + n_warm, rate_hz=1.0, seed=7)
+    circs = [lofp.Circuit(r.m, r.layers) for r in reqs]
+    srv = lofp.Server(max_batch=512, streams=3, precision=lofp.PREC_FP32)
+    try:
+        # saturated: submit all at once
+        t0 = time.perf_counter()
+        tk = [srv.submit(c, r.S, r.T) for c, r in zip(circs, reqs)]
+        amps32 = [srv.result(t)[0] for t in tk]
+        sat = len(reqs) / (time.perf_counter() - t0)
+    finally:
+        srv.close()
+    # complex128 reference for the FP32 form, same library (multi-circuit batch)
+    f64 = lofp.amplitudes_multi([(c, r.S, r.T) for c, r in zip(circs, reqs)])
+    a32 = np.array(amps32)
+    nz = np.abs(f64) > 1e-14
+    rel = float((np.abs(a32 - f64)[nz] / np.abs(f64)[nz]).max()) if nz.any() else 0.0
+    # Poisson arrivals at rate_frac * saturated (fresh circuits, new seed)
+    rate = rate_frac * sat
+    reqs2 = workloads.served_requests(n_req + n_warm, rate_hz=rate, seed=8)
+    circs2 = [lofp.Circuit(r.m, r.layers) for r in reqs2]
+    srv = lofp.Server(max_batch=512, streams=3, precision=lofp.PREC_FP32)
+    lats = []
+    try:
+        t0 = time.perf_counter()
+        tk = []
+        for c, r in zip(circs2, reqs2):
+            delay = r.arrival_s - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tk.append(srv.submit(c, r.S, r.T))
+        for i, t in enumerate(tk):
+            amp, lat = srv.result(t)
+            if i >= n_warm:
+                lats.append(lat)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    finally:
+        srv.close()
+    lats = np.array(lats)
+    return {"requests": n_req, "warmup": n_warm, "precision": "fp32 products, fp64 sums",
+            "saturated_amplitudes_per_s": sat, "rate_hz": rate,
+            "offered_amplitudes_per_s": (n_req + n_warm) / wall,
+            "p50_ms": float(np.percentile(lats, 50)), "p99_ms": float(np.percentile(lats, 99)),
+            "mean_batch": st["mean_batch"], "launches": st["launches"],
+            "max_rel_err_fp32_vs_c128": rel}
 
 
 def host_threads() -> int:

@@ -174,6 +174,64 @@ lofp_status lofp_amplitude(lofp_circuit c, const int32_t *S, const int32_t *T, l
 lofp_status lofp_path_counts(lofp_circuit c, const int32_t *S, int32_t batch, const int32_t *T,
                              double *counts);
 
+/* ---------------------------------------------------------------------------
+ * Many circuits per launch.
+ * One request = one circuit, one S and one T (host memory, copied at the call).
+ * Circuits may all differ in mode count, depth and angles. */
+typedef struct {
+    lofp_circuit circuit;
+    const int32_t *S;   /* int32[m of that circuit] */
+    const int32_t *T;   /* int32[m of that circuit] */
+} lofp_request;
+
+/* Amplitudes of `count` requests evaluated by the mode-axis contraction
+ * (Sec. II.C) in one bounds launch and one contraction launch on `stream`;
+ * each circuit's tables and step program stay resident on the device.  out:
+ * host lofp_c128[count].  opts: precision (FP64 or FP32 products; sums stay
+ * FP64) and record_timing; method must be AUTO or CONTRACT.  Synchronises
+ * `stream`.  Errors: EINVAL for null fields or bad occupations, ENOTSUP for a
+ * circuit the contraction cannot take, ENOMEM past 2^22 state entries. */
+lofp_status lofp_amplitudes_multi(int32_t count, const lofp_request *req, lofp_c128 *out,
+                                  const lofp_opts *opts, void *stream, lofp_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of amplitude requests.
+ * A worker thread admits whatever has been submitted (up to max_batch, while
+ * the admitted workspace stays within memory_budget bytes), launches it as
+ * one multi-circuit batch on the next free stream, and keeps admitting while
+ * earlier batches run (up to `streams` batches in flight).  A result does
+ * not depend on which other requests shared its batch.  The caller keeps each
+ * circuit alive until its requests have completed. */
+typedef struct lofp_server_s *lofp_server;
+
+typedef struct {
+    int32_t max_batch;      /* requests per launch (default 256)              */
+    int32_t streams;        /* batches in flight, one HIP stream each (2, <=8) */
+    int64_t memory_budget;  /* device workspace bytes admitted at once (1 GiB) */
+    int32_t precision;      /* LOFP_PREC_* for every request                   */
+    int32_t reserved[3];
+} lofp_server_opts;
+
+typedef struct {
+    int64_t submitted, completed, launches;
+    double mean_batch;      /* requests per launch                            */
+    double p50_ms, p99_ms, max_ms;   /* submit-to-completion latency          */
+} lofp_server_stats;
+
+/* Start a server on the current device (opts may be NULL). */
+lofp_status lofp_server_create(const lofp_server_opts *opts, lofp_server *out);
+/* Queue one request (S, T: host int32[m], copied); *ticket identifies it. */
+lofp_status lofp_server_submit(lofp_server s, lofp_circuit c, const int32_t *S, const int32_t *T,
+                               uint64_t *ticket);
+/* *done = 1 and out / latency_ms filled (either may be NULL) once the ticket
+ * has completed; wait = 1 blocks until then.  A completed ticket is
+ * consumed.  EDEVICE if its batch failed. */
+lofp_status lofp_server_result(lofp_server s, uint64_t ticket, int32_t wait, lofp_c128 *out,
+                               double *latency_ms, int32_t *done);
+lofp_status lofp_server_get_stats(lofp_server s, lofp_server_stats *out);
+/* Finish every queued request, stop the worker and free the server. */
+lofp_status lofp_server_destroy(lofp_server s);
+
 #ifdef __cplusplus
 }
 #endif

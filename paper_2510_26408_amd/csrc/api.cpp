@@ -11,14 +11,16 @@
 #include <string>
 #include <vector>
 
-#include "lofp.h"
-#include "lofp_device.h"
+#include "host_internal.h"
 
 using namespace lofp;
 
-namespace {
+namespace lofp {
+namespace host {
 
+namespace {
 thread_local std::string g_err;
+}
 
 lofp_status fail(lofp_status s, const std::string &msg)
 {
@@ -26,83 +28,14 @@ lofp_status fail(lofp_status s, const std::string &msg)
     return s;
 }
 
-#define HIPCHK(call)                                                                              \
-    do {                                                                                          \
-        hipError_t e_ = (call);                                                                   \
-        if (e_ != hipSuccess)                                                                     \
-            return fail(e_ == hipErrorOutOfMemory ? LOFP_ENOMEM : LOFP_EDEVICE,                   \
-                        std::string(#call) + ": " + hipGetErrorString(e_));                       \
-    } while (0)
+void clear_error() { g_err.clear(); }
+const char *last_error() { return g_err.c_str(); }
 
-struct DevBuf {
-    void *p = nullptr;
-    size_t cap = 0;
-    template <class T> T *as() const { return static_cast<T *>(p); }
-};
+}  // namespace host
+}  // namespace lofp
 
-hipError_t ensure(DevBuf &b, size_t bytes)
-{
-    if (bytes == 0) bytes = 16;
-    if (bytes <= b.cap) return hipSuccess;
-    if (b.p) {
-        hipError_t e = hipFree(b.p);
-        if (e != hipSuccess) return e;
-    }
-    b.p = nullptr;
-    b.cap = 0;
-    hipError_t e = hipMalloc(&b.p, bytes);
-    if (e == hipSuccess) b.cap = bytes;
-    return e;
-}
-
-void release(DevBuf &b)
-{
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.cap = 0;
-}
-
-template <class T>
-hipError_t upload(DevBuf &b, const std::vector<T> &v, hipStream_t s)
-{
-    hipError_t e = ensure(b, v.size() * sizeof(T));
-    if (e != hipSuccess) return e;
-    if (v.empty()) return hipSuccess;
-    return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
-}
-
-}  // namespace
-
-struct lofp_circuit_s {
-    int m = 0, D = 0, G = 0, nc = 0;
-    std::vector<lofp_bs> gates;            // application order
-    std::vector<int32_t> gate_cut, gate_layer, layer_start;
-    std::vector<uint8_t> cut_gate;         // [D][nc]
-    std::vector<int32_t> gate_at;          // [D][nc] gate id or -1
-    std::vector<int8_t> fr_lo, fr_hi, br_lo, br_hi;  // [(D+1)][m]
-    std::vector<uint8_t> stage_time;       // [(G+1)][nc]
-    std::vector<int32_t> cut_ngates, cut_gates, ver_at;
-    // contraction step program (built once per circuit)
-    bool prog_built = false;
-    bool prog_on_device = false;
-    std::string prog_error;
-    int nvars = 0;
-    std::vector<int32_t> var_cut, var_time;
-    std::vector<ContractStep> steps;
-    std::mutex mu;
-
-    // device state (lazy)
-    bool dev_ready = false;
-    int n_tab = -1;
-    int tab_stride = 0;
-    DevBuf d_table, d_theta, d_phi, d_fr_lo, d_fr_hi, d_br_lo, d_br_hi, d_cut_gate, d_stage_time;
-    DevBuf d_gate_cut, d_gate_layer, d_cut_ngates, d_cut_gates, d_ver_at, d_var_cut, d_var_time, d_steps;
-    // per-call workspace
-    DevBuf d_S, d_lo, d_hi, d_inf, d_C, d_E, d_count, d_slot_stage, d_off, d_coff, d_fa, d_fb, d_ba, d_bb;
-    DevBuf d_levels, d_tab_mid, d_counters, d_T, d_out, d_ws, d_cfg, d_rankb;
-};
-
-namespace {
+namespace lofp {
+namespace host {
 
 // -------------------------------------------------------------- light cones
 // Reach intervals: a photon in mode s can be in modes [lo, hi] after some
@@ -226,6 +159,7 @@ lofp_status device_init(lofp_circuit_s &c, int n, hipStream_t s)
         HIPCHK(upload(c.d_ver_at, c.ver_at, s));
         HIPCHK(ensure(c.d_counters, 8 * sizeof(unsigned long long)));
         c.dev_ready = true;
+        c.pending_init = true;
     }
     if (c.n_tab < n) {
         const int nt = std::max(n, 4);
@@ -235,35 +169,10 @@ lofp_status device_init(lofp_circuit_s &c, int n, hipStream_t s)
                                    c.d_table.as<double2>(), s));
         c.n_tab = nt;
         c.tab_stride = stride;
+        c.pending_init = true;
     }
     return LOFP_OK;
 }
-
-struct Timer {
-    bool on = false;
-    hipStream_t s = nullptr;
-    std::vector<hipEvent_t> ev;
-    void mark()
-    {
-        if (!on) return;
-        hipEvent_t e;
-        if (hipEventCreate(&e) == hipSuccess) {
-            (void)hipEventRecord(e, s);
-            ev.push_back(e);
-        }
-    }
-    double ms(size_t a, size_t b)
-    {
-        float f = 0.f;
-        if (!on || b >= ev.size() || a >= ev.size()) return 0.0;
-        (void)hipEventElapsedTime(&f, ev[a], ev[b]);
-        return f;
-    }
-    ~Timer()
-    {
-        for (auto e : ev) (void)hipEventDestroy(e);
-    }
-};
 
 lofp_status run_bounds(lofp_circuit_s &c, int B, int n, const int32_t *T_dev, hipStream_t s)
 {
@@ -411,14 +320,30 @@ lofp_status prepare_program(lofp_circuit_s &c, hipStream_t s)
         HIPCHK(upload(c.d_var_time, c.var_time, s));
         HIPCHK(upload(c.d_steps, c.steps, s));
         c.prog_on_device = true;
+        c.pending_init = true;
+    }
+    return LOFP_OK;
+}
+
+lofp_status ready_on_stream(lofp_circuit_s &c, hipStream_t s)
+{
+    if (c.pending_init) {
+        if (!c.ready_ev) HIPCHK(hipEventCreateWithFlags(&c.ready_ev, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(c.ready_ev, s));
+        c.ready_stream = s;
+        c.pending_init = false;
+    } else if (c.ready_ev && c.ready_stream != s) {
+        HIPCHK(hipStreamWaitEvent(s, c.ready_ev, 0));
     }
     return LOFP_OK;
 }
 
 lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
-                         lofp_c128 *out_dev, int count_only, hipStream_t s, lofp_stats *st, Timer &tm)
+                         lofp_c128 *out_dev, int count_only, int fp32, hipStream_t s, lofp_stats *st, Timer &tm)
 {
     lofp_status rc = prepare_program(c, s);
+    if (rc != LOFP_OK) return rc;
+    rc = ready_on_stream(c, s);
     if (rc != LOFP_OK) return rc;
     tm.mark();
     rc = run_bounds(c, B, n, T_dev, s);
@@ -439,6 +364,7 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
     a.table = c.d_table.as<double2>(); a.tab_stride = c.tab_stride;
     a.out = reinterpret_cast<double2 *>(out_dev);
     a.count_only = count_only;
+    a.fp32 = fp32;
     a.stat_transitions = ctr + 3;
     a.overflow = reinterpret_cast<int32_t *>(ctr + 4);
     // state size: the S-side bound holds for every pattern; only when it is too
@@ -693,12 +619,15 @@ lofp_status run_pathsum(lofp_circuit_s &c, const int32_t *S, int n, int B, const
     return LOFP_OK;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace lofp
+
+using namespace lofp::host;
 
 // ===================================================================== C-ABI
 extern "C" {
 
-const char *lofp_last_error(void) { return g_err.c_str(); }
+const char *lofp_last_error(void) { return lofp::host::last_error(); }
 
 const char *lofp_version(void) { return "lofp-mi355x 0.1 (gfx950)"; }
 
@@ -771,7 +700,9 @@ lofp_status lofp_circuit_destroy(lofp_circuit c)
                       &c->d_count, &c->d_slot_stage, &c->d_off, &c->d_coff, &c->d_fa, &c->d_fb, &c->d_ba, &c->d_bb,
                       &c->d_levels, &c->d_tab_mid, &c->d_counters, &c->d_T, &c->d_out, &c->d_ws,
                       &c->d_cfg, &c->d_rankb};
+    if (c->ready_ev) (void)hipStreamSynchronize(c->ready_stream);
     for (DevBuf *b : bufs) release(*b);
+    if (c->ready_ev) (void)hipEventDestroy(c->ready_ev);
     delete c;
     return LOFP_OK;
 }
@@ -876,14 +807,14 @@ lofp_status lofp_amplitudes_device(lofp_circuit c, const int32_t *S, int32_t bat
             s_only_bounds(*c, S, n, slo, shi);
             if (program_state_bound(*c, slo, shi) <= (1 << 20)) method = LOFP_METHOD_CONTRACT;
         }
-        g_err.clear();
+        clear_error();
     }
     if (stats) stats->method_used = method;
     if (method == LOFP_METHOD_CONTRACT) {
         Timer inner;
         inner.on = tm.on;
         inner.s = s;
-        rc = run_contract(*c, S, n, batch, T_dev, out_dev, 0, s, stats, inner);
+        rc = run_contract(*c, S, n, batch, T_dev, out_dev, 0, o.precision == LOFP_PREC_FP32, s, stats, inner);
         if (rc == LOFP_OK && stats && tm.on) {
             stats->ms_plan = inner.ms(0, 1);
             stats->ms_contract = inner.ms(1, 2);
@@ -892,7 +823,8 @@ lofp_status lofp_amplitudes_device(lofp_circuit c, const int32_t *S, int32_t bat
         Timer inner;
         inner.on = tm.on;
         inner.s = s;
-        rc = run_pathsum(*c, S, n, batch, T_dev, out_dev, o, s, stats, inner);
+        rc = ready_on_stream(*c, s);
+        if (rc == LOFP_OK) rc = run_pathsum(*c, S, n, batch, T_dev, out_dev, o, s, stats, inner);
     }
     if (rc != LOFP_OK) return rc;
     tm.mark();
@@ -959,7 +891,7 @@ lofp_status lofp_path_counts(lofp_circuit c, const int32_t *S, int32_t batch, co
     HIPCHK(hipMemcpyAsync(c->d_T.p, T, (size_t)batch * c->m * sizeof(int32_t), hipMemcpyHostToDevice, s));
     Timer tm;
     lofp_stats st{};
-    rc = run_contract(*c, S, n, batch, c->d_T.as<int32_t>(), c->d_out.as<lofp_c128>(), 1, s, &st, tm);
+    rc = run_contract(*c, S, n, batch, c->d_T.as<int32_t>(), c->d_out.as<lofp_c128>(), 1, 0, s, &st, tm);
     if (rc != LOFP_OK) return rc;
     std::vector<double2> h(batch);
     HIPCHK(hipMemcpyAsync(h.data(), c->d_out.p, (size_t)batch * sizeof(double2), hipMemcpyDeviceToHost, s));

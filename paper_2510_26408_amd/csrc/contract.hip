@@ -43,18 +43,14 @@ __device__ __forceinline__ int qdiv(int a, int d, float inv)
 
 enum { RK_CONST = 0, RK_NEW = 1, RK_SUM = 2 };
 
-// One wave (64 lanes) per pattern: contraction states here hold tens to a few
-// thousand entries, so a wave covers a step in a few passes and many patterns
-// stay resident per CU.  Every lane derives the step layout itself (no serial
-// section, no block barrier beyond the wave's).
-template <bool COUNT, bool LDS_STATE, int BS>
-__global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
+// The contraction of one pattern by one block.  F32: each transition product
+// prev * W is formed in FP32 (the path-product precision of the FP32 form);
+// states and sums stay FP64.
+template <bool COUNT, bool F32, bool LDS_STATE, int BS>
+__device__ void contract_one(const ContractJob &g, unsigned char *smem, unsigned long long *stat_transitions,
+                             int32_t *overflow)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int p = blockIdx.x;
-    const int nc = g.m - 1, span = (g.D + 1) * nc;
-    const int16_t *lo = g.lo + (int64_t)p * span, *hi = g.hi + (int64_t)p * span;
-    const int32_t *Tp = g.T + (int64_t)p * g.m;
+    const int nc = g.m - 1;
     int *vlo = reinterpret_cast<int *>(smem);                 // [nvars]
     int *vrad = vlo + g.nvars;                                // [nvars]
     int *spre = vrad + g.nvars;                               // [nc]
@@ -64,22 +60,21 @@ __global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
         size_t off = (size_t)(2 * g.nvars + 2 * nc) * sizeof(int);
         off = (off + 15) & ~(size_t)15;
         bufA = reinterpret_cast<double2 *>(smem + off);
-        bufB = bufA + g.max_states;
     } else {
-        bufA = g.ws + (int64_t)p * 2 * g.max_states;
-        bufB = bufA + g.max_states;
+        bufA = g.ws;
     }
-    if (g.infeasible[p]) {
-        if (threadIdx.x == 0) g.out[p] = make_double2(0.0, 0.0);
+    bufB = bufA + g.max_states;
+    if (*g.infeasible) {
+        if (threadIdx.x == 0) *g.out = make_double2(0.0, 0.0);
         return;
     }
     if (threadIdx.x == 0) {
         int s = 0, t = 0;
-        for (int r = 0; r < nc; ++r) { s += g.S[r]; t += Tp[r]; spre[r] = s; tpre[r] = t; }
+        for (int r = 0; r < nc; ++r) { s += g.S[r]; t += g.T[r]; spre[r] = s; tpre[r] = t; }
     }
-    for (int v = threadIdx.x; v < g.nvars; v += blockDim.x) {
+    for (int v = threadIdx.x; v < g.nvars; v += BS) {
         const int t = g.var_time[v], r = g.var_cut[v];
-        const int L = lo[t * nc + r], H = hi[t * nc + r];
+        const int L = g.lo[t * nc + r], H = g.hi[t * nc + r];
         vlo[v] = L;
         vrad[v] = H - L + 1;
     }
@@ -124,7 +119,7 @@ __global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
         }
         const int new_size = ns;
         if (new_size > g.max_states) {
-            if (threadIdx.x == 0) atomicOr(g.overflow, 1);
+            if (threadIdx.x == 0) atomicOr(overflow, 1);
             return;
         }
         int srad0 = 1, srad1 = 1, slo0 = 0, slo1 = 0, sstr0 = 0, sstr1 = 0;
@@ -152,7 +147,7 @@ __global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
             }
         }
         const double2 *Wg = g.table + (int64_t)st.gate * g.tab_stride;
-        for (int e = threadIdx.x; e < new_size; e += blockDim.x) {
+        for (int e = threadIdx.x; e < new_size; e += BS) {
             int rem = e, base_old = 0;
             int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
 #pragma unroll
@@ -185,8 +180,18 @@ __global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
                     const int N = val[3] - val[2], x1 = val[0] - val[2], y1 = val[1] - val[2];
                     if (x1 < 0 || y1 < 0 || x1 > N || y1 > N) continue;
                     ++trans;
-                    if (COUNT) acc.x += prev.x;
-                    else acc = cfma(prev, Wg[sector_offset(N) + x1 * (N + 1) + y1], acc);
+                    if (COUNT) {
+                        acc.x += prev.x;
+                    } else {
+                        const double2 w = Wg[sector_offset(N) + x1 * (N + 1) + y1];
+                        if (F32) {
+                            const float px = (float)prev.x, py = (float)prev.y, wx = (float)w.x, wy = (float)w.y;
+                            acc.x += (double)(px * wx - py * wy);
+                            acc.y += (double)(px * wy + py * wx);
+                        } else {
+                            acc = cfma(prev, w, acc);
+                        }
+                    }
                 }
             }
             bufB[e] = acc;
@@ -197,7 +202,7 @@ __global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
     }
     // amplitude = sum of the final state (a single entry once every version is summed)
     CSum sr{0.0, 0.0}, si{0.0, 0.0};
-    for (int i = threadIdx.x; i < cur_size; i += blockDim.x) {
+    for (int i = threadIdx.x; i < cur_size; i += BS) {
         const double2 x = bufA[i];
         csum_add(sr, x.x);
         csum_add(si, x.y);
@@ -216,9 +221,38 @@ __global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
     if (threadIdx.x == 0) {
         CSum a = part[0][0], b = part[1][0];
         for (int w = 1; w < BS / 64; ++w) { csum_merge(a, part[0][w]); csum_merge(b, part[1][w]); }
-        g.out[p] = make_double2(a.s + a.c, b.s + b.c);
+        *g.out = make_double2(a.s + a.c, b.s + b.c);
     }
-    atomicAdd(g.stat_transitions, trans);
+    atomicAdd(stat_transitions, trans);
+}
+
+// Single circuit, one block per pattern.
+template <bool COUNT, bool F32, bool LDS_STATE, int BS>
+__global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int p = blockIdx.x;
+    const int nc = g.m - 1, span = (g.D + 1) * nc;
+    ContractJob j;
+    j.m = g.m; j.n = g.n; j.D = g.D; j.nvars = g.nvars; j.nsteps = g.nsteps;
+    j.tab_stride = g.tab_stride; j.max_states = g.max_states; j.fp32 = g.fp32;
+    j.steps = g.steps; j.var_cut = g.var_cut; j.var_time = g.var_time; j.table = g.table;
+    j.S = g.S; j.T = g.T + (int64_t)p * g.m;
+    j.lo = g.lo + (int64_t)p * span; j.hi = g.hi + (int64_t)p * span;
+    j.infeasible = g.infeasible + p;
+    j.out = g.out + p;
+    j.ws = LDS_STATE ? nullptr : g.ws + (int64_t)p * 2 * g.max_states;
+    contract_one<COUNT, F32, LDS_STATE, BS>(j, smem, g.stat_transitions, g.overflow);
+}
+
+// Many circuits, one block per job.
+template <bool F32, bool LDS_STATE, int BS>
+__global__ __launch_bounds__(BS) void k_contract_multi(const ContractJob *__restrict__ jobs,
+                                                       unsigned long long *stat_transitions, int32_t *overflow)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const ContractJob j = jobs[blockIdx.x];
+    contract_one<false, F32, LDS_STATE, BS>(j, smem, stat_transitions, overflow);
 }
 
 // Largest state of the step program for each pattern (one thread per pattern).
@@ -249,22 +283,27 @@ hipError_t launch_contract_sizes(const ContractArgs &a, int *max_size, hipStream
     return hipGetLastError();
 }
 
-size_t contract_lds_bytes(const ContractArgs &a, bool state_in_lds)
+size_t contract_job_lds_bytes(int nvars, int m, int max_states, bool state_in_lds)
 {
-    size_t off = (size_t)(2 * a.nvars + 2 * (a.m - 1)) * sizeof(int);
+    size_t off = (size_t)(2 * nvars + 2 * (m - 1)) * sizeof(int);
     off = (off + 15) & ~(size_t)15;
-    return off + (state_in_lds ? (size_t)2 * a.max_states * sizeof(double2) : 0);
+    return off + (state_in_lds ? (size_t)2 * max_states * sizeof(double2) : 0);
 }
 
-template <bool COUNT, bool LDS_STATE>
+size_t contract_lds_bytes(const ContractArgs &a, bool state_in_lds)
+{
+    return contract_job_lds_bytes(a.nvars, a.m, a.max_states, state_in_lds);
+}
+
+template <bool COUNT, bool F32, bool LDS_STATE>
 static void launch_contract_t(const ContractArgs &a, size_t dyn, hipStream_t stream)
 {
     // small states: one wave per pattern keeps more patterns resident;
     // large states: four waves share the pattern's LDS state
     if (a.max_states <= 512)
-        hipLaunchKernelGGL((k_contract<COUNT, LDS_STATE, 64>), dim3(a.B), dim3(64), dyn, stream, a);
+        hipLaunchKernelGGL((k_contract<COUNT, F32, LDS_STATE, 64>), dim3(a.B), dim3(64), dyn, stream, a);
     else
-        hipLaunchKernelGGL((k_contract<COUNT, LDS_STATE, 256>), dim3(a.B), dim3(256), dyn, stream, a);
+        hipLaunchKernelGGL((k_contract<COUNT, F32, LDS_STATE, 256>), dim3(a.B), dim3(256), dyn, stream, a);
 }
 
 hipError_t launch_contract(const ContractArgs &a, hipStream_t stream)
@@ -274,11 +313,40 @@ hipError_t launch_contract(const ContractArgs &a, hipStream_t stream)
     const size_t dyn = contract_lds_bytes(a, in_lds);
     if (dyn > 64 * 1024) return hipErrorInvalidValue;
     if (a.count_only) {
-        if (in_lds) launch_contract_t<true, true>(a, dyn, stream);
-        else launch_contract_t<true, false>(a, dyn, stream);
+        if (in_lds) launch_contract_t<true, false, true>(a, dyn, stream);
+        else launch_contract_t<true, false, false>(a, dyn, stream);
+    } else if (a.fp32) {
+        if (in_lds) launch_contract_t<false, true, true>(a, dyn, stream);
+        else launch_contract_t<false, true, false>(a, dyn, stream);
     } else {
-        if (in_lds) launch_contract_t<false, true>(a, dyn, stream);
-        else launch_contract_t<false, false>(a, dyn, stream);
+        if (in_lds) launch_contract_t<false, false, true>(a, dyn, stream);
+        else launch_contract_t<false, false, false>(a, dyn, stream);
+    }
+    return hipGetLastError();
+}
+
+template <bool F32, bool LDS_STATE>
+static void launch_multi_t(int count, const ContractJob *jobs, size_t dyn, int max_states,
+                           unsigned long long *st, int32_t *ov, hipStream_t stream)
+{
+    if (max_states <= 512)
+        hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 64>), dim3(count), dim3(64), dyn, stream, jobs, st, ov);
+    else
+        hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 256>), dim3(count), dim3(256), dyn, stream, jobs, st, ov);
+}
+
+hipError_t launch_contract_multi(int count, const ContractJob *jobs, size_t lds_bytes, int max_states,
+                                 bool state_in_lds, bool fp32, unsigned long long *stat_transitions,
+                                 int32_t *overflow, hipStream_t stream)
+{
+    if (count == 0) return hipSuccess;
+    if (lds_bytes > 64 * 1024) return hipErrorInvalidValue;
+    if (fp32) {
+        if (state_in_lds) launch_multi_t<true, true>(count, jobs, lds_bytes, max_states, stat_transitions, overflow, stream);
+        else launch_multi_t<true, false>(count, jobs, lds_bytes, max_states, stat_transitions, overflow, stream);
+    } else {
+        if (state_in_lds) launch_multi_t<false, true>(count, jobs, lds_bytes, max_states, stat_transitions, overflow, stream);
+        else launch_multi_t<false, false>(count, jobs, lds_bytes, max_states, stat_transitions, overflow, stream);
     }
     return hipGetLastError();
 }

@@ -1,0 +1,145 @@
+// host_internal.h -- host-side internals shared by the C-ABI translation
+// units (api.cpp, serve.cpp).  Not part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "lofp.h"
+#include "lofp_device.h"
+
+namespace lofp {
+namespace host {
+
+lofp_status fail(lofp_status s, const std::string &msg);
+void clear_error();
+const char *last_error();
+
+#define HIPCHK(call)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return ::lofp::host::fail(e_ == hipErrorOutOfMemory ? LOFP_ENOMEM : LOFP_EDEVICE,     \
+                                      std::string(#call) + ": " + hipGetErrorString(e_));         \
+    } while (0)
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+inline hipError_t ensure(DevBuf &b, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    if (bytes <= b.cap) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        if (e != hipSuccess) return e;
+    }
+    b.p = nullptr;
+    b.cap = 0;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e == hipSuccess) b.cap = bytes;
+    return e;
+}
+
+inline void release(DevBuf &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+template <class T>
+hipError_t upload(DevBuf &b, const std::vector<T> &v, hipStream_t s)
+{
+    hipError_t e = ensure(b, v.size() * sizeof(T));
+    if (e != hipSuccess) return e;
+    if (v.empty()) return hipSuccess;
+    return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+}  // namespace host
+}  // namespace lofp
+
+struct lofp_circuit_s {
+    using DevBuf = lofp::host::DevBuf;
+    int m = 0, D = 0, G = 0, nc = 0;
+    std::vector<lofp_bs> gates;            // application order
+    std::vector<int32_t> gate_cut, gate_layer, layer_start;
+    std::vector<uint8_t> cut_gate;         // [D][nc]
+    std::vector<int32_t> gate_at;          // [D][nc] gate id or -1
+    std::vector<int8_t> fr_lo, fr_hi, br_lo, br_hi;  // [(D+1)][m]
+    std::vector<uint8_t> stage_time;       // [(G+1)][nc]
+    std::vector<int32_t> cut_ngates, cut_gates, ver_at;
+    // contraction step program (built once per circuit)
+    // device-side set-up enqueued on some stream; later users on other
+    // streams wait for ready_ev
+    bool pending_init = false;
+    hipEvent_t ready_ev = nullptr;
+    hipStream_t ready_stream = nullptr;
+    bool prog_built = false;
+    bool prog_on_device = false;
+    std::string prog_error;
+    int nvars = 0;
+    std::vector<int32_t> var_cut, var_time;
+    std::vector<lofp::ContractStep> steps;
+    std::mutex mu;
+
+    // device state (lazy)
+    bool dev_ready = false;
+    int n_tab = -1;
+    int tab_stride = 0;
+    DevBuf d_table, d_theta, d_phi, d_fr_lo, d_fr_hi, d_br_lo, d_br_hi, d_cut_gate, d_stage_time;
+    DevBuf d_gate_cut, d_gate_layer, d_cut_ngates, d_cut_gates, d_ver_at, d_var_cut, d_var_time, d_steps;
+    // per-call workspace
+    DevBuf d_S, d_lo, d_hi, d_inf, d_C, d_E, d_count, d_slot_stage, d_off, d_coff, d_fa, d_fb, d_ba, d_bb;
+    DevBuf d_levels, d_tab_mid, d_counters, d_T, d_out, d_ws, d_cfg, d_rankb;
+};
+
+
+namespace lofp {
+namespace host {
+
+struct Timer {
+    bool on = false;
+    hipStream_t s = nullptr;
+    std::vector<hipEvent_t> ev;
+    void mark()
+    {
+        if (!on) return;
+        hipEvent_t e;
+        if (hipEventCreate(&e) == hipSuccess) {
+            (void)hipEventRecord(e, s);
+            ev.push_back(e);
+        }
+    }
+    double ms(size_t a, size_t b)
+    {
+        float f = 0.f;
+        if (!on || b >= ev.size() || a >= ev.size()) return 0.0;
+        (void)hipEventElapsedTime(&f, ev[a], ev[b]);
+        return f;
+    }
+    ~Timer()
+    {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+
+lofp_status check_S(const lofp_circuit_s &c, const int32_t *S, int &n);
+void s_only_bounds(const lofp_circuit_s &c, const int32_t *S, int n, std::vector<int16_t> &lo,
+                   std::vector<int16_t> &hi);
+lofp_status device_init(lofp_circuit_s &c, int n, hipStream_t s);
+lofp_status prepare_program(lofp_circuit_s &c, hipStream_t s);
+void build_program(lofp_circuit_s &c);
+// Record or wait for the circuit's device set-up so that `s` sees it.
+lofp_status ready_on_stream(lofp_circuit_s &c, hipStream_t s);
+int64_t program_state_bound(const lofp_circuit_s &c, const std::vector<int16_t> &lo, const std::vector<int16_t> &hi);
+
+}  // namespace host
+}  // namespace lofp

@@ -170,12 +170,41 @@ struct ContractArgs {
     int tab_stride;
     double2 *out;             // amplitudes, or counts in .x when count_only
     int count_only;
+    int fp32;                 // 1: transition products in FP32, sums in FP64
     unsigned long long *stat_transitions;
     int max_states;           // entries per state buffer
     double2 *ws;              // [B][2][max_states] when the state does not fit LDS
     int32_t *overflow;
 };
 hipError_t launch_contract(const ContractArgs &a, hipStream_t stream);
+
+// Multi-circuit batches: one job per (request) pattern, each with its own
+// circuit program, tables, S, T and bounds.
+struct ContractJob {
+    int m, n, D, nvars, nsteps, tab_stride, max_states, fp32;
+    const ContractStep *steps;
+    const int32_t *var_cut, *var_time;
+    const double2 *table;
+    const int32_t *S, *T;        // this job's S and T (device)
+    const int16_t *lo, *hi;      // this job's bounds [(D+1)(m-1)]
+    const int32_t *infeasible;   // this job's flag
+    double2 *out;                // this job's amplitude
+    double2 *ws;                 // 2 * max_states entries, or nullptr (state in LDS)
+};
+struct BoundsJob {
+    int m, D, n;
+    const int32_t *S, *T;
+    const int8_t *fr_lo, *fr_hi, *br_lo, *br_hi;
+    const uint8_t *cut_gate;
+    int16_t *lo, *hi;
+    int32_t *infeasible;
+};
+hipError_t launch_bounds_multi(int count, const BoundsJob *jobs, hipStream_t stream);
+// lds_bytes: dynamic LDS per block (max over jobs); max_states: max over jobs
+hipError_t launch_contract_multi(int count, const ContractJob *jobs, size_t lds_bytes, int max_states,
+                                 bool state_in_lds, bool fp32, unsigned long long *stat_transitions,
+                                 int32_t *overflow, hipStream_t stream);
+size_t contract_job_lds_bytes(int nvars, int m, int max_states, bool state_in_lds);
 hipError_t launch_contract_sizes(const ContractArgs &a, int *max_size, hipStream_t stream);
 // dynamic LDS of the contraction kernel (state buffers included when in LDS)
 size_t contract_lds_bytes(const ContractArgs &a, bool state_in_lds);

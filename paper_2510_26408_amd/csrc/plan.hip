@@ -39,6 +39,31 @@ hipError_t launch_bounds(int B, int m, int D, int n, const int32_t *S, const int
     return hipGetLastError();
 }
 
+// One thread per job of a multi-circuit batch.
+__global__ void k_bounds_multi(int count, const BoundsJob *__restrict__ jobs)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const BoundsJob j = jobs[i];
+    const int nc = j.m - 1, span = (j.D + 1) * nc;
+    int nT = 0, bad = 0;
+    for (int k = 0; k < j.m; ++k) { nT += j.T[k]; bad |= j.T[k] < 0; }
+    if (bad || nT != j.n) {
+        for (int k = 0; k < span; ++k) { j.lo[k] = 1; j.hi[k] = 0; }
+        *j.infeasible = 1;
+        return;
+    }
+    light_cone_bounds(j.m, j.D, j.S, j.T, j.fr_lo, j.fr_hi, j.br_lo, j.br_hi, j.lo, j.hi);
+    *j.infeasible = propagate_bounds(j.m, j.D, j.n, j.cut_gate, j.lo, j.hi);
+}
+
+hipError_t launch_bounds_multi(int count, const BoundsJob *jobs, hipStream_t stream)
+{
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bounds_multi, dim3((count + 63) / 64), dim3(64), 0, stream, count, jobs);
+    return hipGetLastError();
+}
+
 // One thread per (stage slot, pattern).
 __global__ void k_stage_tables(int B, int m, int D, int n, int nslots, const int32_t *__restrict__ slot_stage,
                                const uint8_t *__restrict__ stage_time, const int16_t *__restrict__ lo,

@@ -1,0 +1,469 @@
+// serve.cpp -- many circuits in one launch, and a serving loop built on it.
+//
+// A multi-circuit batch packs requests whose circuits may all differ (mode
+// count, depth, angles) together with their S and T.  Each request becomes
+// one job of one bounds launch and one contraction launch; the jobs carry
+// pointers to their circuit's resident tables and step program.
+//
+// The server admits requests continuously: a worker thread takes whatever
+// has arrived (up to max_batch, and while the admitted workspace stays under
+// the memory budget), launches it as one batch on the next free stream, and
+// goes on admitting while earlier batches run; several batches overlap on the
+// device.  A request's latency runs from submit to the moment its batch's
+// completion event is observed.  Each job's arithmetic depends only on its
+// own request, so a result is bit-identical whether it ran alone or in a mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <memory>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "host_internal.h"
+
+using namespace lofp;
+using namespace lofp::host;
+
+namespace {
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Req {
+    lofp_circuit c = nullptr;
+    std::vector<int32_t> S, T;
+    int n = 0;
+    int64_t est = 1;        // contraction state bound (entries), from the S-side intervals
+    uint64_t ticket = 0;
+    double t_submit = 0;
+};
+
+// Workspace bytes of one request (bounds + contraction state if global).
+size_t req_bytes(const Req &r)
+{
+    const lofp_circuit_s &c = *r.c;
+    return (size_t)(c.D + 1) * c.nc * 4 + 64 + (size_t)2 * r.est * sizeof(double2);
+}
+
+// Prepare a request on the host: S-side state bound of the circuit's program.
+lofp_status plan_request(Req &r)
+{
+    lofp_circuit_s &c = *r.c;
+    if ((int)r.S.size() != c.m || (int)r.T.size() != c.m) return fail(LOFP_EINVAL, "S/T length");
+    lofp_status rc = check_S(c, r.S.data(), r.n);
+    if (rc != LOFP_OK) return rc;
+    for (int v : r.T)
+        if (v < 0) return fail(LOFP_EINVAL, "negative occupation in T");
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (!c.prog_built) build_program(c);
+    if (!c.prog_error.empty()) return fail(LOFP_ENOTSUP, c.prog_error);
+    // exact per-request intervals (S and T are on the host here)
+    const size_t span = (size_t)(c.D + 1) * c.nc;
+    std::vector<int16_t> lo(span), hi(span);
+    int nT = 0;
+    for (int v : r.T) nT += v;
+    if (nT != r.n) {
+        r.est = 1;
+        return LOFP_OK;
+    }
+    light_cone_bounds(c.m, c.D, r.S.data(), r.T.data(), c.fr_lo.data(), c.fr_hi.data(), c.br_lo.data(),
+                      c.br_hi.data(), lo.data(), hi.data());
+    if (propagate_bounds(c.m, c.D, r.n, c.cut_gate.data(), lo.data(), hi.data())) {
+        r.est = 1;
+        return LOFP_OK;
+    }
+    r.est = std::max<int64_t>(1, program_state_bound(c, lo, hi));
+    if (r.est > (1 << 22)) return fail(LOFP_ENOMEM, "contraction state exceeds 2^22 entries");
+    return LOFP_OK;
+}
+
+struct Batch {
+    hipStream_t s = nullptr;
+    hipEvent_t ev = nullptr;
+    DevBuf d_ST, d_lohi, d_inf, d_out, d_bj, d_cj, d_ws, d_ctr;
+    std::vector<BoundsJob> bj;
+    std::vector<ContractJob> cj;
+    lofp_c128 *h_out = nullptr;
+    size_t h_cap = 0;
+    std::vector<Req> reqs;
+    size_t bytes = 0;
+    bool busy = false;
+
+    ~Batch()
+    {
+        DevBuf *b[] = {&d_ST, &d_lohi, &d_inf, &d_out, &d_bj, &d_cj, &d_ws, &d_ctr};
+        for (DevBuf *x : b) release(*x);
+        if (h_out) (void)hipHostFree(h_out);
+        if (ev) (void)hipEventDestroy(ev);
+    }
+};
+
+// Enqueue one multi-circuit batch on b.s (reqs already planned).
+lofp_status launch_batch(Batch &b, int fp32)
+{
+    const int count = (int)b.reqs.size();
+    hipStream_t s = b.s;
+    // circuits: resident tables and programs (first use uploads them on this
+    // stream; later users on other streams wait for that upload)
+    for (Req &r : b.reqs) {
+        lofp_circuit_s &c = *r.c;
+        std::lock_guard<std::mutex> lk(c.mu);
+        lofp_status rc = device_init(c, r.n, s);
+        if (rc != LOFP_OK) return rc;
+        rc = prepare_program(c, s);
+        if (rc != LOFP_OK) return rc;
+        rc = ready_on_stream(c, s);
+        if (rc != LOFP_OK) return rc;
+    }
+    // pack S, T and the per-request offsets
+    std::vector<int32_t> ST;
+    std::vector<size_t> st_off(count), lh_off(count);
+    size_t lh = 0;
+    int64_t max_est = 1;
+    int max_vars = 0, max_m = 2;
+    for (int i = 0; i < count; ++i) {
+        const Req &r = b.reqs[i];
+        st_off[i] = ST.size();
+        ST.insert(ST.end(), r.S.begin(), r.S.end());
+        ST.insert(ST.end(), r.T.begin(), r.T.end());
+        lh_off[i] = lh;
+        lh += (size_t)(r.c->D + 1) * r.c->nc;
+        max_est = std::max(max_est, r.est);
+        max_vars = std::max(max_vars, r.c->nvars);
+        max_m = std::max(max_m, r.c->m);
+    }
+    HIPCHK(upload(b.d_ST, ST, s));
+    HIPCHK(ensure(b.d_lohi, 2 * std::max<size_t>(lh, 1) * sizeof(int16_t)));
+    HIPCHK(ensure(b.d_inf, count * sizeof(int32_t)));
+    HIPCHK(ensure(b.d_out, count * sizeof(double2)));
+    HIPCHK(ensure(b.d_ctr, 8 * sizeof(unsigned long long)));
+    HIPCHK(hipMemsetAsync(b.d_ctr.p, 0, 8 * sizeof(unsigned long long), s));
+    const bool in_lds = contract_job_lds_bytes(max_vars, max_m, (int)max_est, true) <= 64 * 1024;
+    size_t ws_total = 0;
+    if (!in_lds) {
+        for (const Req &r : b.reqs) ws_total += (size_t)2 * r.est;
+        HIPCHK(ensure(b.d_ws, ws_total * sizeof(double2)));
+    }
+    const int32_t *dST = b.d_ST.as<int32_t>();
+    int16_t *dlo = b.d_lohi.as<int16_t>(), *dhi = dlo + lh;
+    b.bj.resize(count);
+    b.cj.resize(count);
+    size_t ws_off = 0;
+    for (int i = 0; i < count; ++i) {
+        const Req &r = b.reqs[i];
+        const lofp_circuit_s &c = *r.c;
+        BoundsJob &J = b.bj[i];
+        J.m = c.m; J.D = c.D; J.n = r.n;
+        J.S = dST + st_off[i];
+        J.T = dST + st_off[i] + c.m;
+        J.fr_lo = c.d_fr_lo.as<int8_t>(); J.fr_hi = c.d_fr_hi.as<int8_t>();
+        J.br_lo = c.d_br_lo.as<int8_t>(); J.br_hi = c.d_br_hi.as<int8_t>();
+        J.cut_gate = c.d_cut_gate.as<uint8_t>();
+        J.lo = dlo + lh_off[i];
+        J.hi = dhi + lh_off[i];
+        J.infeasible = b.d_inf.as<int32_t>() + i;
+        ContractJob &K = b.cj[i];
+        K.m = c.m; K.n = r.n; K.D = c.D; K.nvars = c.nvars; K.nsteps = (int)c.steps.size();
+        K.tab_stride = c.tab_stride;
+        K.max_states = in_lds ? (int)max_est : (int)r.est;
+        K.fp32 = fp32;
+        K.steps = c.d_steps.as<ContractStep>();
+        K.var_cut = c.d_var_cut.as<int32_t>();
+        K.var_time = c.d_var_time.as<int32_t>();
+        K.table = c.d_table.as<double2>();
+        K.S = J.S; K.T = J.T; K.lo = J.lo; K.hi = J.hi; K.infeasible = J.infeasible;
+        K.out = b.d_out.as<double2>() + i;
+        K.ws = in_lds ? nullptr : b.d_ws.as<double2>() + ws_off;
+        ws_off += (size_t)2 * r.est;
+    }
+    HIPCHK(upload(b.d_bj, b.bj, s));
+    HIPCHK(upload(b.d_cj, b.cj, s));
+    HIPCHK(launch_bounds_multi(count, b.d_bj.as<BoundsJob>(), s));
+    const size_t lds = contract_job_lds_bytes(max_vars, max_m, (int)max_est, in_lds);
+    unsigned long long *ctr = b.d_ctr.as<unsigned long long>();
+    HIPCHK(launch_contract_multi(count, b.d_cj.as<ContractJob>(), lds, (int)max_est, in_lds, fp32 != 0, ctr,
+                                 reinterpret_cast<int32_t *>(ctr + 1), s));
+    if (b.h_cap < (size_t)count) {
+        if (b.h_out) (void)hipHostFree(b.h_out);
+        b.h_out = nullptr;
+        b.h_cap = 0;
+        HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&b.h_out), std::max(count, 256) * sizeof(lofp_c128),
+                             hipHostMallocDefault));
+        b.h_cap = std::max(count, 256);
+    }
+    HIPCHK(hipMemcpyAsync(b.h_out, b.d_out.p, count * sizeof(lofp_c128), hipMemcpyDeviceToHost, s));
+    if (!b.ev) HIPCHK(hipEventCreateWithFlags(&b.ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(b.ev, s));
+    return LOFP_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ server
+struct lofp_server_s {
+    lofp_server_opts o{};
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Req> queue;
+    std::unordered_map<uint64_t, std::pair<lofp_c128, double>> done;   // ticket -> (amp, latency)
+    std::vector<double> latencies;
+    std::vector<std::unique_ptr<Batch>> batches;
+    uint64_t next_ticket = 1;
+    int64_t submitted = 0, completed = 0, launches = 0, launched_reqs = 0;
+    size_t inflight_bytes = 0;
+    bool stop = false;
+    std::string error;
+    std::thread worker;
+    int device = 0;
+};
+
+namespace {
+
+void complete_batch(lofp_server_s &sv, Batch &b)
+{
+    const double t = now_ms();
+    std::lock_guard<std::mutex> lk(sv.mu);
+    for (size_t i = 0; i < b.reqs.size(); ++i) {
+        const double lat = t - b.reqs[i].t_submit;
+        sv.done[b.reqs[i].ticket] = {b.h_out[i], lat};
+        sv.latencies.push_back(lat);
+    }
+    sv.completed += (int64_t)b.reqs.size();
+    sv.inflight_bytes -= b.bytes;
+    b.reqs.clear();
+    b.busy = false;
+    sv.cv.notify_all();
+}
+
+void worker_loop(lofp_server_s *sv)
+{
+    (void)hipSetDevice(sv->device);
+    for (;;) {
+        // completions first
+        for (auto &bp : sv->batches) {
+            Batch &b = *bp;
+            if (b.busy && hipEventQuery(b.ev) == hipSuccess) complete_batch(*sv, b);
+        }
+        Batch *free_b = nullptr;
+        for (auto &bp : sv->batches)
+            if (!bp->busy) { free_b = bp.get(); break; }
+        std::vector<Req> take;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            if (sv->stop && sv->queue.empty()) {
+                bool any = false;
+                for (auto &bp : sv->batches) any |= bp->busy;
+                if (!any) return;
+            }
+            if (!free_b || sv->queue.empty()) {
+                // nothing to launch: wait briefly for arrivals or completions
+                sv->cv.wait_for(lk, std::chrono::microseconds(20));
+                continue;
+            }
+            // admission: arrivals so far, up to max_batch and the memory budget
+            size_t bytes = 0;
+            while (!sv->queue.empty() && (int)take.size() < sv->o.max_batch) {
+                const size_t rb = req_bytes(sv->queue.front());
+                if (!take.empty() && sv->inflight_bytes + bytes + rb > (size_t)sv->o.memory_budget) break;
+                bytes += rb;
+                take.push_back(std::move(sv->queue.front()));
+                sv->queue.pop_front();
+            }
+            sv->inflight_bytes += bytes;
+            free_b->bytes = bytes;
+        }
+        free_b->reqs = std::move(take);
+        free_b->busy = true;
+        lofp_status rc = launch_batch(*free_b, sv->o.precision == LOFP_PREC_FP32);
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->launches++;
+        sv->launched_reqs += (int64_t)free_b->reqs.size();
+        if (rc != LOFP_OK) {
+            sv->error = lofp_last_error();
+            for (const Req &r : free_b->reqs) sv->done[r.ticket] = {lofp_c128{NAN, NAN}, -1.0};
+            sv->completed += (int64_t)free_b->reqs.size();
+            sv->inflight_bytes -= free_b->bytes;
+            free_b->reqs.clear();
+            free_b->busy = false;
+            sv->cv.notify_all();
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+lofp_status lofp_amplitudes_multi(int32_t count, const lofp_request *req, lofp_c128 *out, const lofp_opts *opts,
+                                  void *stream, lofp_stats *stats)
+{
+    if (count < 0) return fail(LOFP_EINVAL, "negative count");
+    if (count > 0 && (!req || !out)) return fail(LOFP_EINVAL, "null requests or out");
+    if (opts && opts->method == LOFP_METHOD_PATHSUM) return fail(LOFP_ENOTSUP, "multi-circuit batches use the contraction");
+    if (stats) { std::memset(stats, 0, sizeof(*stats)); stats->batch = count; stats->method_used = LOFP_METHOD_CONTRACT; }
+    if (count == 0) return LOFP_OK;
+    Batch b;
+    b.s = static_cast<hipStream_t>(stream);
+    b.reqs.resize(count);
+    for (int i = 0; i < count; ++i) {
+        if (!req[i].circuit || !req[i].S || !req[i].T) return fail(LOFP_EINVAL, "null request field");
+        Req &r = b.reqs[i];
+        r.c = req[i].circuit;
+        r.S.assign(req[i].S, req[i].S + r.c->m);
+        r.T.assign(req[i].T, req[i].T + r.c->m);
+        lofp_status rc = plan_request(r);
+        if (rc != LOFP_OK) return rc;
+    }
+    Timer tm;
+    tm.on = stats && opts && opts->record_timing;
+    tm.s = b.s;
+    tm.mark();
+    lofp_status rc = launch_batch(b, opts && opts->precision == LOFP_PREC_FP32);
+    if (rc != LOFP_OK) return rc;
+    tm.mark();
+    HIPCHK(hipStreamSynchronize(b.s));
+    std::memcpy(out, b.h_out, count * sizeof(lofp_c128));
+    if (stats) {
+        unsigned long long h[2];
+        HIPCHK(hipMemcpy(h, b.d_ctr.p, sizeof(h), hipMemcpyDeviceToHost));
+        if (h[1]) return fail(LOFP_ENOMEM, "contraction workspace overflow");
+        stats->transitions = (int64_t)h[0];
+        if (tm.on) stats->ms_total = stats->ms_contract = tm.ms(0, 1);
+    }
+    return LOFP_OK;
+}
+
+lofp_status lofp_server_create(const lofp_server_opts *o, lofp_server *out)
+{
+    if (!out) return fail(LOFP_EINVAL, "out is null");
+    auto *sv = new lofp_server_s();
+    sv->o.max_batch = 256;
+    sv->o.streams = 2;
+    sv->o.memory_budget = (int64_t)1 << 30;
+    sv->o.precision = LOFP_PREC_FP64;
+    if (o) {
+        if (o->max_batch > 0) sv->o.max_batch = o->max_batch;
+        if (o->streams > 0) sv->o.streams = std::min(o->streams, 8);
+        if (o->memory_budget > 0) sv->o.memory_budget = o->memory_budget;
+        sv->o.precision = o->precision;
+    }
+    if (sv->o.precision != LOFP_PREC_FP64 && sv->o.precision != LOFP_PREC_FP32) {
+        delete sv;
+        return fail(LOFP_EINVAL, "bad precision");
+    }
+    (void)hipGetDevice(&sv->device);
+    for (int i = 0; i < sv->o.streams; ++i) {
+        auto b = std::make_unique<Batch>();
+        hipError_t e = hipStreamCreateWithFlags(&b->s, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete sv;
+            return fail(LOFP_EDEVICE, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(e));
+        }
+        sv->batches.push_back(std::move(b));
+    }
+    sv->worker = std::thread(worker_loop, sv);
+    *out = sv;
+    return LOFP_OK;
+}
+
+lofp_status lofp_server_submit(lofp_server sv, lofp_circuit c, const int32_t *S, const int32_t *T, uint64_t *ticket)
+{
+    if (!sv || !c || !S || !T || !ticket) return fail(LOFP_EINVAL, "null argument");
+    Req r;
+    r.c = c;
+    r.S.assign(S, S + c->m);
+    r.T.assign(T, T + c->m);
+    lofp_status rc = plan_request(r);
+    if (rc != LOFP_OK) return rc;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stop) return fail(LOFP_EINVAL, "server is stopping");
+    r.ticket = sv->next_ticket++;
+    r.t_submit = now_ms();
+    *ticket = r.ticket;
+    sv->queue.push_back(std::move(r));
+    sv->submitted++;
+    sv->cv.notify_all();
+    return LOFP_OK;
+}
+
+lofp_status lofp_server_result(lofp_server sv, uint64_t ticket, int32_t wait, lofp_c128 *out, double *latency_ms,
+                               int32_t *done)
+{
+    if (!sv || !done) return fail(LOFP_EINVAL, "null argument");
+    std::unique_lock<std::mutex> lk(sv->mu);
+    if (ticket == 0 || ticket >= sv->next_ticket) return fail(LOFP_EINVAL, "unknown ticket");
+    for (;;) {
+        auto it = sv->done.find(ticket);
+        if (it != sv->done.end()) {
+            if (it->second.second < 0) {
+                const std::string msg = sv->error;
+                sv->done.erase(it);
+                *done = 1;
+                return fail(LOFP_EDEVICE, "request failed: " + msg);
+            }
+            if (out) *out = it->second.first;
+            if (latency_ms) *latency_ms = it->second.second;
+            sv->done.erase(it);
+            *done = 1;
+            return LOFP_OK;
+        }
+        if (!wait) {
+            *done = 0;
+            return LOFP_OK;
+        }
+        sv->cv.wait(lk);
+    }
+}
+
+lofp_status lofp_server_get_stats(lofp_server sv, lofp_server_stats *st)
+{
+    if (!sv || !st) return fail(LOFP_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    std::memset(st, 0, sizeof(*st));
+    st->submitted = sv->submitted;
+    st->completed = sv->completed;
+    st->launches = sv->launches;
+    st->mean_batch = sv->launches ? (double)sv->launched_reqs / (double)sv->launches : 0.0;
+    if (!sv->latencies.empty()) {
+        std::vector<double> v = sv->latencies;
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double q) { return v[std::min(v.size() - 1, (size_t)(q * (v.size() - 1) + 0.5))]; };
+        st->p50_ms = pct(0.50);
+        st->p99_ms = pct(0.99);
+        st->max_ms = v.back();
+    }
+    return LOFP_OK;
+}
+
+lofp_status lofp_server_destroy(lofp_server sv)
+{
+    if (!sv) return fail(LOFP_EINVAL, "null server");
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+        sv->cv.notify_all();
+    }
+    if (sv->worker.joinable()) sv->worker.join();
+    for (auto &b : sv->batches) {
+        if (b->s) (void)hipStreamSynchronize(b->s);
+    }
+    for (auto &b : sv->batches) {
+        hipStream_t s = b->s;
+        b.reset();
+        if (s) (void)hipStreamDestroy(s);
+    }
+    delete sv;
+    return LOFP_OK;
+}
+
+}  // extern "C"

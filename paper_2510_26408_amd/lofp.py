@@ -23,7 +23,8 @@ PREC_FP64, PREC_FP32 = 0, 1
 EXPORTED = (
     "lofp_last_error", "lofp_version", "lofp_circuit_create", "lofp_circuit_destroy", "lofp_light_cone",
     "lofp_bounds", "lofp_bs_table", "lofp_amplitudes_device", "lofp_amplitudes", "lofp_amplitude",
-    "lofp_path_counts",
+    "lofp_path_counts", "lofp_amplitudes_multi", "lofp_server_create", "lofp_server_submit",
+    "lofp_server_result", "lofp_server_get_stats", "lofp_server_destroy",
 )
 
 
@@ -61,6 +62,25 @@ class Stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("reserved")}
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("circuit", ctypes.c_void_p), ("S", ctypes.POINTER(ctypes.c_int32)),
+                ("T", ctypes.POINTER(ctypes.c_int32))]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int32), ("streams", ctypes.c_int32), ("memory_budget", ctypes.c_int64),
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("mean_batch", ctypes.c_double), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -88,6 +108,14 @@ def load():
                                     ctypes.POINTER(Stats)]
     lib.lofp_amplitude.argtypes = [vp, i32p, i32p, ctypes.POINTER(C128)]
     lib.lofp_path_counts.argtypes = [vp, i32p, ctypes.c_int32, i32p, ctypes.POINTER(ctypes.c_double)]
+    lib.lofp_amplitudes_multi.argtypes = [ctypes.c_int32, ctypes.POINTER(Request), ctypes.POINTER(C128),
+                                          ctypes.POINTER(Opts), vp, ctypes.POINTER(Stats)]
+    lib.lofp_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+    lib.lofp_server_submit.argtypes = [vp, vp, i32p, i32p, ctypes.POINTER(ctypes.c_uint64)]
+    lib.lofp_server_result.argtypes = [vp, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(C128),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
+    lib.lofp_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.lofp_server_destroy.argtypes = [vp]
     for f in EXPORTED[2:]:
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -212,6 +240,69 @@ class Circuit:
         _check(load().lofp_path_counts(self._h, _ip(S), Ts.shape[0], _ip(Ts),
                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out
+
+
+def amplitudes_multi(items, opts: Optional[Opts] = None, stats: Optional[Stats] = None) -> np.ndarray:
+    """items: list of (Circuit, S, T).  All evaluated in one multi-circuit launch."""
+    keep = []
+    reqs = (Request * max(1, len(items)))()
+    for i, (c, S, T) in enumerate(items):
+        S, T = _i32(S), _i32(T)
+        keep.append((S, T))
+        reqs[i] = Request(c.handle, _ip(S), _ip(T))
+    out = (C128 * max(1, len(items)))()
+    _check(load().lofp_amplitudes_multi(len(items), reqs, out, ctypes.byref(opts) if opts is not None else None,
+                                        None, ctypes.byref(stats) if stats is not None else None))
+    return np.frombuffer(out, dtype=np.complex128)[:len(items)].copy()
+
+
+class Server:
+    """Continuous-batching request loop (native worker thread)."""
+
+    def __init__(self, max_batch: int = 256, streams: int = 2, memory_budget: int = 1 << 30,
+                 precision: int = PREC_FP64):
+        o = ServerOpts()
+        o.max_batch, o.streams, o.memory_budget, o.precision = max_batch, streams, memory_budget, precision
+        h = ctypes.c_void_p()
+        _check(load().lofp_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, circuit: "Circuit", S, T) -> int:
+        S, T = _i32(S), _i32(T)
+        t = ctypes.c_uint64()
+        _check(load().lofp_server_submit(self._h, circuit.handle, _ip(S), _ip(T), ctypes.byref(t)))
+        self._keep[t.value] = circuit
+        return t.value
+
+    def result(self, ticket: int, wait: bool = True):
+        """(amplitude, latency_ms) or None if not finished (wait=False)."""
+        out = C128()
+        lat = ctypes.c_double()
+        done = ctypes.c_int32()
+        _check(load().lofp_server_result(self._h, ticket, 1 if wait else 0, ctypes.byref(out), ctypes.byref(lat),
+                                         ctypes.byref(done)))
+        if not done.value:
+            return None
+        self._keep.pop(ticket, None)
+        return complex(out.re, out.im), lat.value
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().lofp_server_get_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().lofp_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version() -> str:

@@ -244,3 +244,46 @@ def test_auto_picks_contraction_and_matches_pathsum():
     assert st2.method_used == lofp.METHOD_PATHSUM
     check(a, b)
     check(a, oracle_amps(wl.m, wl.S, wl.Ts, wl.layers))
+
+
+# ------------------------------------------------- many circuits and serving
+def _served(count, seed=0):
+    reqs = workloads.served_requests(count, rate_hz=0.0, seed=seed)
+    return [(lofp.Circuit(r.m, r.layers), r) for r in reqs]
+
+
+def test_multi_circuit_batch_matches_oracle_and_single_calls():
+    items = _served(24, seed=3)
+    got = lofp.amplitudes_multi([(c, r.S, r.T) for c, r in items])
+    for i, (c, r) in enumerate(items):
+        want = oracle.amplitude(r.m, r.S, r.T, flat(r.layers))
+        assert abs(got[i] - want) <= ATOL
+        alone = c.amplitudes(r.S, r.T[None, :], lofp.make_opts(method=lofp.METHOD_CONTRACT))[0]
+        assert alone == got[i]
+
+
+def test_multi_fp32_products_within_bound():
+    items = _served(24, seed=4)
+    f64 = lofp.amplitudes_multi([(c, r.S, r.T) for c, r in items])
+    f32 = lofp.amplitudes_multi([(c, r.S, r.T) for c, r in items], lofp.make_opts(precision=lofp.PREC_FP32))
+    scale = np.maximum(np.abs(f64), 1e-300)
+    nz = np.abs(f64) > 1e-12
+    rel = np.abs(f32 - f64)[nz] / scale[nz]
+    assert rel.max() < 1e-5, rel.max()
+    assert np.all(f32[~nz] == 0) or np.abs(f32[~nz]).max() < 1e-12
+
+
+def test_server_results_same_alone_and_in_mix():
+    items = _served(40, seed=5)
+    alone = [lofp.amplitudes_multi([(c, r.S, r.T)])[0] for c, r in items]
+    srv = lofp.Server(max_batch=16, streams=2)
+    try:
+        tickets = [srv.submit(c, r.S, r.T) for c, r in items]
+        res = [srv.result(t) for t in tickets]
+        st = srv.stats()
+    finally:
+        srv.close()
+    for i, (amp, lat) in enumerate(res):
+        assert amp == alone[i]
+        assert lat >= 0
+    assert st["completed"] == len(items) and st["launches"] >= 3
