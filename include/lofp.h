@@ -105,7 +105,9 @@ typedef struct {
     double ms_contract;       /*   contraction kernel                          */
     double ms_total;          /*   whole call on the stream                    */
     int32_t method_used;      /* LOFP_METHOD_PATHSUM or LOFP_METHOD_CONTRACT   */
-    int32_t reserved_[3];
+    int32_t split_top_keys;   /* contraction split across the batch: distinct  */
+    int32_t split_bottom_keys;/*   top / bottom halves of T (0 if not split)   */
+    int32_t reserved_;
 } lofp_stats;
 
 /* Message for the last non-OK status on this thread ("" if none). */

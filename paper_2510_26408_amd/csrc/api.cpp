@@ -187,67 +187,75 @@ lofp_status run_bounds(lofp_circuit_s &c, int B, int n, const int32_t *T_dev, hi
     return LOFP_OK;
 }
 
-// Contraction program: the splitters in cut-major order (top cut first, each
-// cut's splitters in time order).  Every free version of a cut is a variable;
-// a step introduces the variables its splitter reads for the first time and
-// sums out those it reads for the last time.  The live list after a step
+// Contraction programs.  Every free version of a cut (the cut's value between
+// two of its splitters) is a variable; every splitter is a factor reading four
+// versions (cut r before and after it, cuts r-1 and r+1 at its time).  A
+// schedule takes the factors in a given order: a step introduces the
+// variables its factor reads for the first time and sums out those no later
+// factor (and no external consumer) reads.  The live list after a step
 // starts with the step's own still-live references so the kernel finds them
 // at fixed positions.
-void build_program(lofp_circuit_s &c)
+void build_factors(lofp_circuit_s &c)
 {
-    c.prog_built = true;
-    c.prog_error.clear();
     const int nc = c.nc, Dm = std::max(c.D, 1);
-    std::vector<std::vector<int>> var_of(nc);
+    c.var_of.assign(nc, {});
     c.var_cut.clear();
     c.var_time.clear();
     for (int r = 0; r < nc; ++r) {
         const int k = c.cut_ngates[r];
-        var_of[r].assign(k + 1, -1);
+        c.var_of[r].assign(k + 1, -1);
         for (int v = 1; v < k; ++v) {
-            var_of[r][v] = (int)c.var_cut.size();
+            c.var_of[r][v] = (int)c.var_cut.size();
             c.var_cut.push_back(r);
             c.var_time.push_back(c.gate_layer[c.cut_gates[(size_t)r * Dm + v - 1]] + 1);
         }
     }
     c.nvars = (int)c.var_cut.size();
-    if (c.nvars > kMaxContractVars) { c.prog_error = "too many free cut versions for the contraction"; return; }
-    struct Ref { int kind, arg; };  // kind: CREF_* with arg = cut, or -1 with arg = variable
-    auto version_ref = [&](int r, int v) -> Ref {
+    auto version_ref = [&](int r, int v) -> FRef {
         if (r < 0) return {CREF_ZERO, 0};
         if (r >= nc) return {CREF_N, 0};
         if (v == 0) return {CREF_SPRE, r};
         if (v == c.cut_ngates[r]) return {CREF_TPRE, r};
-        return {-1, var_of[r][v]};
+        return {-1, c.var_of[r][v]};
     };
-    std::vector<std::array<Ref, 4>> fac;
-    std::vector<int> fgate;
+    c.fac.clear();
+    c.fgate.clear();
+    c.fcut.clear();
     for (int r = 0; r < nc; ++r) {
         const int k = c.cut_ngates[r];
         for (int j = 1; j <= k; ++j) {
             const int g = c.cut_gates[(size_t)r * Dm + j - 1];
             const int l = c.gate_layer[g];
-            std::array<Ref, 4> f;
+            std::array<FRef, 4> f;
             f[0] = version_ref(r, j - 1);
             f[1] = version_ref(r, j);
-            f[2] = r > 0 ? version_ref(r - 1, c.ver_at[(size_t)l * nc + r - 1]) : Ref{CREF_ZERO, 0};
-            f[3] = r + 1 < nc ? version_ref(r + 1, c.ver_at[(size_t)l * nc + r + 1]) : Ref{CREF_N, 0};
-            fac.push_back(f);
-            fgate.push_back(g);
+            f[2] = r > 0 ? version_ref(r - 1, c.ver_at[(size_t)l * nc + r - 1]) : FRef{CREF_ZERO, 0};
+            f[3] = r + 1 < nc ? version_ref(r + 1, c.ver_at[(size_t)l * nc + r + 1]) : FRef{CREF_N, 0};
+            c.fac.push_back(f);
+            c.fgate.push_back(g);
+            c.fcut.push_back(r);
         }
     }
+}
+
+Schedule schedule_factors(const lofp_circuit_s &c, const std::vector<int> &order, const std::vector<char> &external)
+{
+    Schedule sc;
+    if (c.nvars > kMaxContractVars) { sc.error = "too many free cut versions for the contraction"; return sc; }
     std::vector<int> last_use(c.nvars, -1);
-    for (size_t f = 0; f < fac.size(); ++f)
-        for (const Ref &x : fac[f])
+    for (size_t f = 0; f < order.size(); ++f)
+        for (const FRef &x : c.fac[order[f]])
             if (x.kind < 0) last_use[x.arg] = (int)f;
+    for (int v = 0; v < c.nvars; ++v)
+        if (!external.empty() && external[v]) last_use[v] = (int)order.size();  // never summed here
     std::vector<int> active;
-    c.steps.clear();
-    for (size_t f = 0; f < fac.size(); ++f) {
+    for (size_t f = 0; f < order.size(); ++f) {
+        const std::array<FRef, 4> &fr = c.fac[order[f]];
         ContractStep st;
         std::memset(&st, 0, sizeof(st));
-        st.gate = fgate[f];
+        st.gate = c.fgate[order[f]];
         std::vector<int> F;
-        for (const Ref &x : fac[f])
+        for (const FRef &x : fr)
             if (x.kind < 0 && std::find(F.begin(), F.end(), x.arg) == F.end()) F.push_back(x.arg);
         std::vector<int> summed, kept;
         for (int v : F) (last_use[v] == (int)f ? summed : kept).push_back(v);
@@ -255,8 +263,8 @@ void build_program(lofp_circuit_s &c)
         for (int v : active)
             if (std::find(F.begin(), F.end(), v) == F.end()) nl.push_back(v);
         if ((int)nl.size() > kMaxActive || (int)active.size() > kMaxActive || summed.size() > 2) {
-            c.prog_error = "contraction state has too many live cut versions";
-            return;
+            sc.error = "contraction state has too many live cut versions";
+            return sc;
         }
         st.n_new = (int)nl.size();
         st.n_old = (int)active.size();
@@ -273,7 +281,7 @@ void build_program(lofp_circuit_s &c)
             st.sum_to_old[q] = it == active.end() ? -1 : (int)(it - active.begin());
         }
         for (int k = 0; k < 4; ++k) {
-            const Ref &x = fac[f][k];
+            const FRef &x = fr[k];
             if (x.kind >= 0) {
                 st.ref_kind[k] = x.kind;
                 st.ref_arg[k] = x.arg;
@@ -288,10 +296,60 @@ void build_program(lofp_circuit_s &c)
                 }
             }
         }
-        c.steps.push_back(st);
+        sc.steps.push_back(st);
         active = nl;
     }
-    if (!active.empty()) c.prog_error = "contraction program left live versions";
+    sc.live_out = active;
+    return sc;
+}
+
+void build_program(lofp_circuit_s &c)
+{
+    c.prog_built = true;
+    c.prog_error.clear();
+    build_factors(c);
+    std::vector<int> order(c.fac.size());
+    for (size_t f = 0; f < order.size(); ++f) order[f] = (int)f;
+    Schedule sc = schedule_factors(c, order, {});
+    if (sc.error.empty() && !sc.live_out.empty()) sc.error = "contraction program left live versions";
+    c.prog_error = sc.error;
+    c.steps = sc.steps;
+}
+
+// Split programs: the factors of cuts 0..rs from the top, and those of cuts
+// m-2..rs+1 from the bottom, each keeping live the versions the other half
+// reads.  Both halves end with the same live versions (those of cuts rs and
+// rs+1 that cross the split).
+SplitProgram *get_split(lofp_circuit_s &c, int rs)
+{
+    auto it = c.splits.find(rs);
+    if (it != c.splits.end()) return it->second.get();
+    auto sp = std::make_unique<SplitProgram>();
+    sp->rs = rs;
+    std::vector<int> top, bot;
+    std::vector<char> ref_top(c.nvars, 0), ref_bot(c.nvars, 0);
+    for (size_t f = 0; f < c.fac.size(); ++f) {
+        const bool is_top = c.fcut[f] <= rs;
+        if (is_top) top.push_back((int)f);
+        for (const FRef &x : c.fac[f])
+            if (x.kind < 0) (is_top ? ref_top : ref_bot)[x.arg] = 1;
+    }
+    // bottom half: cuts from the last upwards, each cut's splitters in time order
+    for (int r = c.nc - 1; r > rs; --r)
+        for (size_t f = 0; f < c.fac.size(); ++f)
+            if (c.fcut[f] == r) bot.push_back((int)f);
+    sp->top = schedule_factors(c, top, ref_bot);
+    sp->bot = schedule_factors(c, bot, ref_top);
+    if (sp->top.error.empty() && sp->bot.error.empty()) {
+        std::vector<int> a = sp->top.live_out, b = sp->bot.live_out;
+        std::sort(a.begin(), a.end());
+        std::sort(b.begin(), b.end());
+        if (a != b) sp->top.error = "split halves disagree on the crossing versions";
+        if ((int)sp->top.live_out.size() > kMaxActive) sp->top.error = "too many crossing versions";
+    }
+    SplitProgram *raw = sp.get();
+    c.splits[rs] = std::move(sp);
+    return raw;
 }
 
 // Largest contraction state of the program under the given per-time bounds.
@@ -338,13 +396,22 @@ lofp_status ready_on_stream(lofp_circuit_s &c, hipStream_t s)
     return LOFP_OK;
 }
 
+lofp_status run_contract_split(lofp_circuit_s &c, int n, int B, const int32_t *T_dev, lofp_c128 *out_dev, int fp32,
+                               hipStream_t s, lofp_stats *st, Timer &tm, bool &used);
+
 lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
-                         lofp_c128 *out_dev, int count_only, int fp32, hipStream_t s, lofp_stats *st, Timer &tm)
+                         lofp_c128 *out_dev, int count_only, int fp32, hipStream_t s, lofp_stats *st, Timer &tm,
+                         bool allow_split = true)
 {
     lofp_status rc = prepare_program(c, s);
     if (rc != LOFP_OK) return rc;
     rc = ready_on_stream(c, s);
     if (rc != LOFP_OK) return rc;
+    if (!count_only && allow_split && B >= 64) {
+        bool used = false;
+        rc = run_contract_split(c, n, B, T_dev, out_dev, fp32, s, st, tm, used);
+        if (rc != LOFP_OK || used) return rc;
+    }
     tm.mark();
     rc = run_bounds(c, B, n, T_dev, s);
     if (rc != LOFP_OK) return rc;
@@ -396,6 +463,179 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
         HIPCHK(hipStreamSynchronize(s));
         if (h[4]) return fail(LOFP_ENOMEM, "contraction workspace overflow");
         st->transitions = (int64_t)h[3];
+    }
+    return LOFP_OK;
+}
+
+// Split contraction for a batch sharing S (Sec. II.C, both ends at once): the
+// top half of the contraction depends on T only through T's modes 0..rs+1, the
+// bottom half only through modes rs+1..m-1, so each distinct top (bottom) part
+// is contracted once and every pattern is finished by a dot product of its two
+// halves over the crossing versions.
+struct KeyMap {
+    std::vector<int32_t> of;                  // key of each pattern
+    std::vector<int32_t> off, members, rep;   // CSR of members per key; representative
+};
+
+static void group_rows(const std::vector<int32_t> &T, int B, int m, int n, int c0, int c1, KeyMap &km)
+{
+    // open addressing on a 64-bit hash of modes [c0, c1], full compare on hit
+    size_t cap = 1;
+    while (cap < (size_t)B * 2 + 2) cap <<= 1;
+    std::vector<int32_t> slot(cap, -1);
+    km.of.assign(B, 0);
+    km.rep.clear();
+    for (int p = 0; p < B; ++p) {
+        const int32_t *row = T.data() + (size_t)p * m;
+        uint64_t h = 1469598103934665603ULL;
+        for (int i = c0; i <= c1; ++i) { h ^= (uint64_t)(uint32_t)row[i]; h *= 1099511628211ULL; }
+        size_t j = (size_t)(h ^ (h >> 29)) & (cap - 1);
+        for (;;) {
+            if (slot[j] < 0) {
+                slot[j] = (int32_t)km.rep.size();
+                km.of[p] = slot[j];
+                km.rep.push_back(p);
+                break;
+            }
+            const int32_t *o = T.data() + (size_t)km.rep[slot[j]] * m;
+            bool eq = true;
+            for (int i = c0; i <= c1 && eq; ++i) eq = o[i] == row[i];
+            if (eq) { km.of[p] = slot[j]; break; }
+            j = (j + 1) & (cap - 1);
+        }
+    }
+    const int nk = (int)km.rep.size();
+    // representative: a member whose photon number is right (its prefix sums
+    // then give the key's fixed versions)
+    std::vector<char> good(nk, 0);
+    for (int p = 0; p < B; ++p) {
+        const int k = km.of[p];
+        if (good[k]) continue;
+        int tot = 0;
+        for (int i = 0; i < m; ++i) tot += T[(size_t)p * m + i];
+        if (tot == n) { km.rep[k] = p; good[k] = 1; }
+    }
+    km.off.assign(nk + 1, 0);
+    for (int p = 0; p < B; ++p) km.off[km.of[p] + 1]++;
+    for (int k = 0; k < nk; ++k) km.off[k + 1] += km.off[k];
+    km.members.assign(B, 0);
+    std::vector<int32_t> fill(km.off.begin(), km.off.end() - 1);
+    for (int p = 0; p < B; ++p) km.members[fill[km.of[p]]++] = p;
+}
+
+lofp_status run_contract_split(lofp_circuit_s &c, int n, int B, const int32_t *T_dev, lofp_c128 *out_dev, int fp32,
+                               hipStream_t s, lofp_stats *st, Timer &tm, bool &used)
+{
+    used = false;
+    const int m = c.m, nc = c.nc, span = (c.D + 1) * nc;
+    if (nc < 4 || c.D < 2) return LOFP_OK;
+    const int rs = (nc - 1) / 2;
+    SplitProgram *sp = get_split(c, rs);
+    if (!sp->top.error.empty() || !sp->bot.error.empty()) return LOFP_OK;
+    // pattern keys (T to the host once)
+    std::vector<int32_t> hT((size_t)B * m);
+    HIPCHK(hipMemcpyAsync(hT.data(), T_dev, hT.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    KeyMap tk, bk;
+    group_rows(hT, B, m, n, 0, rs + 1, tk);
+    group_rows(hT, B, m, n, rs + 1, m - 1, bk);
+    const int ntop = (int)tk.rep.size(), nbot = (int)bk.rep.size();
+    if ((int64_t)(ntop + nbot) * 4 > (int64_t)B * 3) return LOFP_OK;   // little sharing: contract per pattern
+    used = true;
+    if (!sp->on_device) {
+        HIPCHK(upload(sp->d_top, sp->top.steps, s));
+        HIPCHK(upload(sp->d_bot, sp->bot.steps, s));
+        HIPCHK(upload(sp->d_top_live, sp->top.live_out, s));
+        HIPCHK(upload(sp->d_bot_live, sp->bot.live_out, s));
+        sp->on_device = true;
+    }
+    tm.mark();
+    lofp_status rc = run_bounds(c, B, n, T_dev, s);
+    if (rc != LOFP_OK) return rc;
+    // key tables: [of_top | of_bot | off_top | mem_top | off_bot | mem_bot]
+    std::vector<int32_t> kt;
+    auto put = [&](const std::vector<int32_t> &v) { size_t o = kt.size(); kt.insert(kt.end(), v.begin(), v.end()); return o; };
+    const size_t o_of_t = put(tk.of), o_of_b = put(bk.of), o_off_t = put(tk.off), o_mem_t = put(tk.members);
+    const size_t o_off_b = put(bk.off), o_mem_b = put(bk.members);
+    HIPCHK(upload(c.d_keys, kt, s));
+    const int32_t *dk = c.d_keys.as<int32_t>();
+    HIPCHK(ensure(c.d_klohi, (size_t)2 * (ntop + nbot) * span * sizeof(int16_t)));
+    int16_t *tlo = c.d_klohi.as<int16_t>(), *thi = tlo + (size_t)ntop * span;
+    int16_t *blo = thi + (size_t)ntop * span, *bhi = blo + (size_t)nbot * span;
+    HIPCHK(launch_hull(ntop, dk + o_off_t, dk + o_mem_t, c.d_inf.as<int32_t>(), span, c.d_lo.as<int16_t>(),
+                       c.d_hi.as<int16_t>(), tlo, thi, s));
+    HIPCHK(launch_hull(nbot, dk + o_off_b, dk + o_mem_b, c.d_inf.as<int32_t>(), span, c.d_lo.as<int16_t>(),
+                       c.d_hi.as<int16_t>(), blo, bhi, s));
+    // one job per key: top keys first, then bottom keys
+    const int nj = ntop + nbot;
+    std::vector<ContractJob> jobs(nj);
+    HIPCHK(ensure(c.d_kinf, (size_t)nj * sizeof(int32_t)));
+    HIPCHK(hipMemsetAsync(c.d_kinf.p, 0, (size_t)nj * sizeof(int32_t), s));
+    for (int j = 0; j < nj; ++j) {
+        const bool top = j < ntop;
+        const int k = top ? j : j - ntop;
+        ContractJob &J = jobs[j];
+        std::memset(&J, 0, sizeof(J));
+        J.m = m; J.n = n; J.D = c.D; J.nvars = c.nvars;
+        J.nsteps = (int)(top ? sp->top.steps.size() : sp->bot.steps.size());
+        J.tab_stride = c.tab_stride;
+        J.fp32 = fp32;
+        J.steps = (top ? sp->d_top : sp->d_bot).as<ContractStep>();
+        J.var_cut = c.d_var_cut.as<int32_t>();
+        J.var_time = c.d_var_time.as<int32_t>();
+        J.table = c.d_table.as<double2>();
+        J.S = c.d_S.as<int32_t>();
+        J.T = T_dev + (size_t)(top ? tk.rep[k] : bk.rep[k]) * m;
+        J.lo = (top ? tlo : blo) + (size_t)k * span;
+        J.hi = (top ? thi : bhi) + (size_t)k * span;
+        J.infeasible = c.d_kinf.as<int32_t>() + j;
+        J.out = nullptr;
+    }
+    HIPCHK(upload(c.d_jobs, jobs, s));
+    unsigned long long *ctr = c.d_counters.as<unsigned long long>();
+    HIPCHK(hipMemsetAsync(ctr, 0, 8 * sizeof(unsigned long long), s));
+    int *d_max = reinterpret_cast<int *>(ctr + 5);
+    HIPCHK(launch_multi_sizes(nj, c.d_jobs.as<ContractJob>(), d_max, s));
+    int mx = 0;
+    HIPCHK(hipMemcpyAsync(&mx, d_max, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (mx > (1 << 22)) return fail(LOFP_ENOMEM, "contraction state exceeds 2^22 entries");
+    mx = std::max(mx, 1);
+    const bool in_lds = contract_job_lds_bytes(c.nvars, m, mx, true) <= 64 * 1024;
+    MultiOverride ov{mx, nullptr, nullptr, mx};
+    if (!in_lds) {
+        HIPCHK(ensure(c.d_ws, (size_t)nj * 2 * mx * sizeof(double2)));
+        ov.ws_base = c.d_ws.as<double2>();
+    }
+    HIPCHK(ensure(c.d_kstate, (size_t)nj * mx * sizeof(double2)));
+    ov.state_base = c.d_kstate.as<double2>();
+    tm.mark();
+    HIPCHK(launch_contract_multi(nj, c.d_jobs.as<ContractJob>(), contract_job_lds_bytes(c.nvars, m, mx, in_lds), mx,
+                                 in_lds, fp32 != 0, ctr + 3, reinterpret_cast<int32_t *>(ctr + 4), s, ov));
+    JoinArgs ja{};
+    ja.B = B; ja.m = m; ja.n = n; ja.D = c.D;
+    ja.lo = c.d_lo.as<int16_t>(); ja.hi = c.d_hi.as<int16_t>();
+    ja.infeasible = c.d_inf.as<int32_t>();
+    ja.top_of = dk + o_of_t; ja.bot_of = dk + o_of_b;
+    ja.tlo = tlo; ja.thi = thi; ja.blo = blo; ja.bhi = bhi;
+    ja.nshared = (int)sp->top.live_out.size();
+    ja.top_live = sp->d_top_live.as<int32_t>();
+    ja.bot_live = sp->d_bot_live.as<int32_t>();
+    ja.var_cut = c.d_var_cut.as<int32_t>(); ja.var_time = c.d_var_time.as<int32_t>();
+    ja.top_state = c.d_kstate.as<double2>();
+    ja.bot_state = c.d_kstate.as<double2>() + (size_t)ntop * mx;
+    ja.state_cap = mx;
+    ja.out = reinterpret_cast<double2 *>(out_dev);
+    HIPCHK(launch_join(ja, s));
+    tm.mark();
+    if (st) {
+        unsigned long long h[8];
+        HIPCHK(hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (h[4]) return fail(LOFP_ENOMEM, "contraction workspace overflow");
+        st->transitions = (int64_t)h[3];
+        st->split_top_keys = ntop;
+        st->split_bottom_keys = nbot;
     }
     return LOFP_OK;
 }
@@ -699,7 +939,7 @@ lofp_status lofp_circuit_destroy(lofp_circuit c)
                       &c->d_cut_gates, &c->d_ver_at, &c->d_var_cut, &c->d_var_time, &c->d_steps, &c->d_S, &c->d_lo, &c->d_hi, &c->d_inf, &c->d_C, &c->d_E,
                       &c->d_count, &c->d_slot_stage, &c->d_off, &c->d_coff, &c->d_fa, &c->d_fb, &c->d_ba, &c->d_bb,
                       &c->d_levels, &c->d_tab_mid, &c->d_counters, &c->d_T, &c->d_out, &c->d_ws,
-                      &c->d_cfg, &c->d_rankb};
+                      &c->d_cfg, &c->d_rankb, &c->d_keys, &c->d_klohi, &c->d_kinf, &c->d_jobs, &c->d_kstate};
     if (c->ready_ev) (void)hipStreamSynchronize(c->ready_stream);
     for (DevBuf *b : bufs) release(*b);
     if (c->ready_ev) (void)hipEventDestroy(c->ready_ev);

@@ -65,7 +65,7 @@ __device__ void contract_one(const ContractJob &g, unsigned char *smem, unsigned
     }
     bufB = bufA + g.max_states;
     if (*g.infeasible) {
-        if (threadIdx.x == 0) *g.out = make_double2(0.0, 0.0);
+        if (threadIdx.x == 0 && g.out) *g.out = make_double2(0.0, 0.0);
         return;
     }
     if (threadIdx.x == 0) {
@@ -200,6 +200,16 @@ __device__ void contract_one(const ContractJob &g, unsigned char *smem, unsigned
         double2 *t = bufA; bufA = bufB; bufB = t;
         cur_size = new_size;
     }
+    if (g.state_out) {
+        // half of a split contraction: hand the state over instead of summing
+        if (cur_size > g.state_cap) {
+            if (threadIdx.x == 0) atomicOr(overflow, 1);
+            return;
+        }
+        for (int i = threadIdx.x; i < cur_size; i += BS) g.state_out[i] = bufA[i];
+        atomicAdd(stat_transitions, trans);
+        return;
+    }
     // amplitude = sum of the final state (a single entry once every version is summed)
     CSum sr{0.0, 0.0}, si{0.0, 0.0};
     for (int i = threadIdx.x; i < cur_size; i += BS) {
@@ -242,17 +252,177 @@ __global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
     j.infeasible = g.infeasible + p;
     j.out = g.out + p;
     j.ws = LDS_STATE ? nullptr : g.ws + (int64_t)p * 2 * g.max_states;
+    j.state_out = nullptr;
+    j.state_cap = 0;
     contract_one<COUNT, F32, LDS_STATE, BS>(j, smem, g.stat_transitions, g.overflow);
 }
 
 // Many circuits, one block per job.
 template <bool F32, bool LDS_STATE, int BS>
 __global__ __launch_bounds__(BS) void k_contract_multi(const ContractJob *__restrict__ jobs,
-                                                       unsigned long long *stat_transitions, int32_t *overflow)
+                                                       unsigned long long *stat_transitions, int32_t *overflow,
+                                                       MultiOverride ov)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const ContractJob j = jobs[blockIdx.x];
+    ContractJob j = jobs[blockIdx.x];
+    if (ov.max_states > 0) {
+        j.max_states = ov.max_states;
+        j.ws = ov.ws_base ? ov.ws_base + (int64_t)blockIdx.x * 2 * ov.max_states : nullptr;
+        if (ov.state_base) {
+            j.state_out = ov.state_base + (int64_t)blockIdx.x * ov.state_cap;
+            j.state_cap = ov.state_cap;
+        }
+    }
     contract_one<false, F32, LDS_STATE, BS>(j, smem, stat_transitions, overflow);
+}
+
+// Largest state of each job's program under its intervals.
+__global__ void k_multi_sizes(int count, const ContractJob *__restrict__ jobs, int *mx)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const ContractJob j = jobs[i];
+    if (*j.infeasible) return;
+    const int nc = j.m - 1;
+    long long best = 1;
+    for (int si = 0; si < j.nsteps; ++si) {
+        const ContractStep &st = j.steps[si];
+        long long ns = 1;
+        for (int q = 0; q < st.n_new; ++q) {
+            const int v = st.new_vars[q];
+            const int t = j.var_time[v], r = j.var_cut[v];
+            const long long rad = j.hi[t * nc + r] - j.lo[t * nc + r] + 1;
+            ns *= rad > 0 ? rad : 0;
+        }
+        if (ns > best) best = ns;
+    }
+    atomicMax(mx, best > (1 << 22) ? (1 << 22) + 1 : (int)best);
+}
+
+hipError_t launch_multi_sizes(int count, const ContractJob *jobs, int *mx, hipStream_t stream)
+{
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_multi_sizes, dim3((count + 63) / 64), dim3(64), 0, stream, count, jobs, mx);
+    return hipGetLastError();
+}
+
+// Hull of the member patterns' intervals, one block per key.
+__global__ void k_hull(int nkeys, const int32_t *__restrict__ key_off, const int32_t *__restrict__ members,
+                       const int32_t *__restrict__ infeasible, int span, const int16_t *__restrict__ lo,
+                       const int16_t *__restrict__ hi, int16_t *__restrict__ klo, int16_t *__restrict__ khi)
+{
+    const int k = blockIdx.x;
+    const int b = key_off[k], e = key_off[k + 1];
+    for (int i = threadIdx.x; i < span; i += blockDim.x) {
+        int l = 1 << 14, h = -1;
+        for (int q = b; q < e; ++q) {
+            const int p = members[q];
+            if (infeasible[p]) continue;
+            const int pl = lo[(int64_t)p * span + i], ph = hi[(int64_t)p * span + i];
+            l = pl < l ? pl : l;
+            h = ph > h ? ph : h;
+        }
+        if (h < 0) { l = 1; h = 0; }
+        klo[(int64_t)k * span + i] = (int16_t)l;
+        khi[(int64_t)k * span + i] = (int16_t)h;
+    }
+}
+
+hipError_t launch_hull(int nkeys, const int32_t *key_off, const int32_t *members, const int32_t *infeasible,
+                       int span, const int16_t *lo, const int16_t *hi, int16_t *klo, int16_t *khi,
+                       hipStream_t stream)
+{
+    if (nkeys == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hull, dim3(nkeys), dim3(64), 0, stream, nkeys, key_off, members, infeasible, span, lo, hi,
+                       klo, khi);
+    return hipGetLastError();
+}
+
+// Join of a split contraction, one wave per pattern: the sum over the
+// pattern's own box of crossing versions of TOP(versions) * BOT(versions),
+// each state addressed by value through its key's interval layout.
+__global__ __launch_bounds__(64) void k_join(JoinArgs g)
+{
+    const int p = blockIdx.x;
+    const int nc = g.m - 1, span = (g.D + 1) * nc;
+    if (g.infeasible[p]) {
+        if (threadIdx.x == 0) g.out[p] = make_double2(0.0, 0.0);
+        return;
+    }
+    const int tk = g.top_of[p], bk = g.bot_of[p];
+    const int16_t *plo = g.lo + (int64_t)p * span, *phi = g.hi + (int64_t)p * span;
+    const int16_t *tlo = g.tlo + (int64_t)tk * span, *thi = g.thi + (int64_t)tk * span;
+    const int16_t *blo = g.blo + (int64_t)bk * span, *bhi = g.bhi + (int64_t)bk * span;
+    // per crossing variable (top order): pattern box, top stride/offset, bottom stride/offset
+    int prad[kMaxActive], pstr[kMaxActive], toff[kMaxActive], tstr[kMaxActive], boff[kMaxActive], bstr[kMaxActive];
+    float pinv[kMaxActive];
+    int box = 1, ts = 1;
+#pragma unroll
+    for (int q = 0; q < kMaxActive; ++q) {
+        prad[q] = 1; pstr[q] = box; pinv[q] = 1.0f / (float)box; toff[q] = 0; tstr[q] = 0; boff[q] = 0; bstr[q] = 0;
+        if (q < g.nshared) {
+            const int v = g.top_live[q];
+            const int i = g.var_time[v] * nc + g.var_cut[v];
+            prad[q] = phi[i] - plo[i] + 1;
+            toff[q] = plo[i] - tlo[i];          // top digit = pattern digit + toff
+            tstr[q] = ts;
+            ts *= thi[i] - tlo[i] + 1;
+            box *= prad[q] > 0 ? prad[q] : 0;
+        }
+    }
+    // bottom strides follow the bottom state's own order
+    {
+        int bs = 1;
+#pragma unroll
+        for (int q2 = 0; q2 < kMaxActive; ++q2) {
+            if (q2 < g.nshared) {
+                const int v = g.bot_live[q2];
+                const int i = g.var_time[v] * nc + g.var_cut[v];
+#pragma unroll
+                for (int q = 0; q < kMaxActive; ++q) {
+                    if (q < g.nshared && g.top_live[q] == v) {
+                        bstr[q] = bs;
+                        boff[q] = plo[i] - blo[i];
+                    }
+                }
+                bs *= bhi[i] - blo[i] + 1;
+            }
+        }
+    }
+    const double2 *TS = g.top_state + (int64_t)tk * g.state_cap;
+    const double2 *BS_ = g.bot_state + (int64_t)bk * g.state_cap;
+    CSum sr{0.0, 0.0}, si{0.0, 0.0};
+    for (int e = threadIdx.x; e < box; e += 64) {
+        int rem = e, ti = 0, bi = 0;
+#pragma unroll
+        for (int q = kMaxActive - 1; q >= 0; --q) {
+            if (q < g.nshared) {
+                const int d = qdiv(rem, pstr[q], pinv[q]);
+                rem -= d * pstr[q];
+                ti += (d + toff[q]) * tstr[q];
+                bi += (d + boff[q]) * bstr[q];
+            }
+        }
+        const double2 c = cmul(TS[ti], BS_[bi]);
+        csum_add(sr, c.x);
+        csum_add(si, c.y);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        CSum b{__shfl_xor(sr.s, off, 64), __shfl_xor(sr.c, off, 64)};
+        CSum c{__shfl_xor(si.s, off, 64), __shfl_xor(si.c, off, 64)};
+        if (threadIdx.x & off) { CSum t = sr; sr = b; b = t; t = si; si = c; c = t; }
+        csum_merge(sr, b);
+        csum_merge(si, c);
+    }
+    if (threadIdx.x == 0) g.out[p] = make_double2(sr.s + sr.c, si.s + si.c);
+}
+
+hipError_t launch_join(const JoinArgs &a, hipStream_t stream)
+{
+    if (a.B == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_join, dim3(a.B), dim3(64), 0, stream, a);
+    return hipGetLastError();
 }
 
 // Largest state of the step program for each pattern (one thread per pattern).
@@ -327,26 +497,27 @@ hipError_t launch_contract(const ContractArgs &a, hipStream_t stream)
 
 template <bool F32, bool LDS_STATE>
 static void launch_multi_t(int count, const ContractJob *jobs, size_t dyn, int max_states,
-                           unsigned long long *st, int32_t *ov, hipStream_t stream)
+                           unsigned long long *st, int32_t *ov, MultiOverride o, hipStream_t stream)
 {
     if (max_states <= 512)
-        hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 64>), dim3(count), dim3(64), dyn, stream, jobs, st, ov);
+        hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 64>), dim3(count), dim3(64), dyn, stream, jobs, st, ov, o);
     else
-        hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 256>), dim3(count), dim3(256), dyn, stream, jobs, st, ov);
+        hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 256>), dim3(count), dim3(256), dyn, stream, jobs, st, ov, o);
 }
 
 hipError_t launch_contract_multi(int count, const ContractJob *jobs, size_t lds_bytes, int max_states,
                                  bool state_in_lds, bool fp32, unsigned long long *stat_transitions,
-                                 int32_t *overflow, hipStream_t stream)
+                                 int32_t *overflow, hipStream_t stream, MultiOverride o)
 {
     if (count == 0) return hipSuccess;
     if (lds_bytes > 64 * 1024) return hipErrorInvalidValue;
+    unsigned long long *st = stat_transitions;
     if (fp32) {
-        if (state_in_lds) launch_multi_t<true, true>(count, jobs, lds_bytes, max_states, stat_transitions, overflow, stream);
-        else launch_multi_t<true, false>(count, jobs, lds_bytes, max_states, stat_transitions, overflow, stream);
+        if (state_in_lds) launch_multi_t<true, true>(count, jobs, lds_bytes, max_states, st, overflow, o, stream);
+        else launch_multi_t<true, false>(count, jobs, lds_bytes, max_states, st, overflow, o, stream);
     } else {
-        if (state_in_lds) launch_multi_t<false, true>(count, jobs, lds_bytes, max_states, stat_transitions, overflow, stream);
-        else launch_multi_t<false, false>(count, jobs, lds_bytes, max_states, stat_transitions, overflow, stream);
+        if (state_in_lds) launch_multi_t<false, true>(count, jobs, lds_bytes, max_states, st, overflow, o, stream);
+        else launch_multi_t<false, false>(count, jobs, lds_bytes, max_states, st, overflow, o, stream);
     }
     return hipGetLastError();
 }

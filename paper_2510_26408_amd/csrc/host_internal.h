@@ -3,6 +3,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <array>
+#include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -62,6 +65,32 @@ hipError_t upload(DevBuf &b, const std::vector<T> &v, hipStream_t s)
     return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
 }
 
+// A factor reference: kind = CREF_* with arg = cut, or kind = -1 with arg =
+// variable id.
+struct FRef {
+    int kind, arg;
+};
+
+struct Schedule {
+    std::vector<lofp::ContractStep> steps;
+    std::vector<int> live_out;   // live variables after the last step
+    std::string error;
+};
+
+struct SplitProgram {
+    int rs = 0;
+    Schedule top, bot;
+    DevBuf d_top, d_bot, d_top_live, d_bot_live;
+    bool on_device = false;
+    ~SplitProgram()
+    {
+        release(d_top);
+        release(d_bot);
+        release(d_top_live);
+        release(d_bot_live);
+    }
+};
+
 }  // namespace host
 }  // namespace lofp
 
@@ -87,6 +116,10 @@ struct lofp_circuit_s {
     int nvars = 0;
     std::vector<int32_t> var_cut, var_time;
     std::vector<lofp::ContractStep> steps;
+    std::vector<std::vector<int>> var_of;                    // [cut][version] -> variable or -1
+    std::vector<std::array<lofp::host::FRef, 4>> fac;       // factors in cut-major order
+    std::vector<int> fgate, fcut;
+    std::map<int, std::unique_ptr<lofp::host::SplitProgram>> splits;
     std::mutex mu;
 
     // device state (lazy)
@@ -98,6 +131,7 @@ struct lofp_circuit_s {
     // per-call workspace
     DevBuf d_S, d_lo, d_hi, d_inf, d_C, d_E, d_count, d_slot_stage, d_off, d_coff, d_fa, d_fb, d_ba, d_bb;
     DevBuf d_levels, d_tab_mid, d_counters, d_T, d_out, d_ws, d_cfg, d_rankb;
+    DevBuf d_keys, d_klohi, d_kinf, d_jobs, d_kstate;
 };
 
 
@@ -137,6 +171,7 @@ void s_only_bounds(const lofp_circuit_s &c, const int32_t *S, int n, std::vector
 lofp_status device_init(lofp_circuit_s &c, int n, hipStream_t s);
 lofp_status prepare_program(lofp_circuit_s &c, hipStream_t s);
 void build_program(lofp_circuit_s &c);
+SplitProgram *get_split(lofp_circuit_s &c, int rs);
 // Record or wait for the circuit's device set-up so that `s` sees it.
 lofp_status ready_on_stream(lofp_circuit_s &c, hipStream_t s);
 int64_t program_state_bound(const lofp_circuit_s &c, const std::vector<int16_t> &lo, const std::vector<int16_t> &hi);

@@ -190,6 +190,17 @@ struct ContractJob {
     const int32_t *infeasible;   // this job's flag
     double2 *out;                // this job's amplitude
     double2 *ws;                 // 2 * max_states entries, or nullptr (state in LDS)
+    double2 *state_out;          // if set: write the final state here instead of summing it
+    int state_cap;               // entries available at state_out
+};
+// Per-launch overrides for key jobs of a split contraction (0 / nullptr: use
+// the job's own fields): one state size for every job, and per-job slices of
+// a workspace and of a state output buffer.
+struct MultiOverride {
+    int max_states;
+    double2 *ws_base;            // job i uses ws_base + i * 2 * max_states
+    double2 *state_base;         // job i writes state_base + i * state_cap
+    int state_cap;
 };
 struct BoundsJob {
     int m, D, n;
@@ -203,7 +214,30 @@ hipError_t launch_bounds_multi(int count, const BoundsJob *jobs, hipStream_t str
 // lds_bytes: dynamic LDS per block (max over jobs); max_states: max over jobs
 hipError_t launch_contract_multi(int count, const ContractJob *jobs, size_t lds_bytes, int max_states,
                                  bool state_in_lds, bool fp32, unsigned long long *stat_transitions,
-                                 int32_t *overflow, hipStream_t stream);
+                                 int32_t *overflow, hipStream_t stream, MultiOverride ov = MultiOverride{0, nullptr, nullptr, 0});
+// Largest state over the jobs (one thread per job), atomically maxed into *mx.
+hipError_t launch_multi_sizes(int count, const ContractJob *jobs, int *mx, hipStream_t stream);
+
+// Split contraction: per key, the hull of its member patterns' intervals.
+hipError_t launch_hull(int nkeys, const int32_t *key_off, const int32_t *members, const int32_t *infeasible,
+                       int span, const int16_t *lo, const int16_t *hi, int16_t *klo, int16_t *khi,
+                       hipStream_t stream);
+struct JoinArgs {
+    int B, m, n, D;
+    const int16_t *lo, *hi;          // per pattern [B][span]
+    const int32_t *infeasible;
+    const int32_t *top_of, *bot_of;  // key of each pattern
+    const int16_t *tlo, *thi;        // per top key [ntop][span]
+    const int16_t *blo, *bhi;        // per bottom key [nbot][span]
+    int nshared;
+    const int32_t *top_live;         // crossing variables in the top state's order
+    const int32_t *bot_live;         // the same variables in the bottom state's order
+    const int32_t *var_cut, *var_time;
+    const double2 *top_state, *bot_state;
+    int state_cap;
+    double2 *out;
+};
+hipError_t launch_join(const JoinArgs &a, hipStream_t stream);
 size_t contract_job_lds_bytes(int nvars, int m, int max_states, bool state_in_lds);
 hipError_t launch_contract_sizes(const ContractArgs &a, int *max_size, hipStream_t stream);
 // dynamic LDS of the contraction kernel (state buffers included when in LDS)

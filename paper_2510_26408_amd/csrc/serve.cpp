@@ -184,6 +184,8 @@ lofp_status launch_batch(Batch &b, int fp32)
         K.S = J.S; K.T = J.T; K.lo = J.lo; K.hi = J.hi; K.infeasible = J.infeasible;
         K.out = b.d_out.as<double2>() + i;
         K.ws = in_lds ? nullptr : b.d_ws.as<double2>() + ws_off;
+        K.state_out = nullptr;
+        K.state_cap = 0;
         ws_off += (size_t)2 * r.est;
     }
     HIPCHK(upload(b.d_bj, b.bj, s));

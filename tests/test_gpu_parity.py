@@ -287,3 +287,43 @@ def test_server_results_same_alone_and_in_mix():
         assert amp == alone[i]
         assert lat >= 0
     assert st["completed"] == len(items) and st["launches"] >= 3
+
+
+# ------------------------------------------------------ split contraction
+def test_split_contraction_full_c2_batch():
+    """The 4096-pattern batch shares S: the contraction runs once per distinct
+    top and bottom half of T and joins per pattern.  Checked against the
+    oracle on a sample and against the unsplit contraction (batches below the
+    split threshold) on every pattern."""
+    wl = workloads.make("c2", seed=0)
+    c = lofp.Circuit(wl.m, wl.layers)
+    st = lofp.Stats()
+    got = c.amplitudes(wl.S, wl.Ts, lofp.make_opts(method=lofp.METHOD_CONTRACT), st)
+    assert st.split_top_keys > 0 and st.split_bottom_keys > 0
+    idx = np.random.default_rng(2).choice(wl.batch, 64, replace=False)
+    check(got[idx], oracle_amps(wl.m, wl.S, wl.Ts[idx], wl.layers))
+    ref = np.concatenate([c.amplitudes(wl.S, wl.Ts[i:i + 32], lofp.make_opts(method=lofp.METHOD_CONTRACT))
+                          for i in range(0, wl.batch, 32)])
+    check(got, ref, 1e-14)
+
+
+def test_split_contraction_invalid_rows_and_no_sharing():
+    wl = workloads.make("c2", seed=4, batch=1024)
+    Ts = wl.Ts.copy()
+    Ts[5, 0] += 1          # wrong photon number: exact 0
+    Ts[9] = 0
+    Ts[9, -1] = wl.n       # all photons in the last mode: infeasible at depth 8
+    c = lofp.Circuit(wl.m, wl.layers)
+    st = lofp.Stats()
+    got = c.amplitudes(wl.S, Ts, lofp.make_opts(method=lofp.METHOD_CONTRACT), st)
+    assert st.split_top_keys > 0
+    assert got[5] == 0 and got[9] == 0
+    ok = np.array([i for i in range(len(Ts)) if i not in (5, 9)])
+    check(got[ok[:128]], oracle_amps(wl.m, wl.S, Ts[ok[:128]], wl.layers))
+    # bunched patterns share no halves: the call falls back to one contraction per pattern
+    wl3 = workloads.make("c3", seed=4, batch=256)
+    c3 = lofp.Circuit(wl3.m, wl3.layers)
+    st3 = lofp.Stats()
+    got3 = c3.amplitudes(wl3.S, wl3.Ts, lofp.make_opts(method=lofp.METHOD_CONTRACT), st3)
+    assert st3.split_top_keys == 0
+    check(got3[:64], oracle_amps(wl3.m, wl3.S, wl3.Ts[:64], wl3.layers))
