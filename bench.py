@@ -214,12 +214,12 @@ def pathsum_roofline(s0, avg):
             "algorithmic": "32 B per frontier state (one 16 B write, one 16 B read)"}
 
 
-def run_variant(lofp, workloads, torch, dev, stream, name, method, steps=5):
+def run_variant(lofp, workloads, torch, dev, stream, name, method, steps=5, fwd=-1, bwd=-1):
     wl = workloads.make(name, seed=0)
     circ = lofp.Circuit(wl.m, wl.layers)
     T = torch.from_numpy(wl.Ts).to(dev)
     o = torch.zeros(wl.batch, dtype=torch.complex128, device=dev)
-    opts = lofp.make_opts(method=method, record_timing=True)
+    opts = lofp.make_opts(method=method, record_timing=True, fwd_layer=fwd, bwd_layer=bwd)
     for _ in range(2):
         circ.amplitudes_device(wl.S, T, o, opts, stream=stream, stats=lofp.Stats())
     torch.cuda.synchronize()
@@ -252,6 +252,8 @@ def variants(lofp, workloads, torch, dev, stream):
     """The depth-first path-sum form on the same batch, the contraction on the
     m=32, n=16 workload, and the served mixed-request workload."""
     return {"pathsum_c2": run_variant(lofp, workloads, torch, dev, stream, "c2", lofp.METHOD_PATHSUM, steps=3),
+            "pathsum_dfs_c2": run_variant(lofp, workloads, torch, dev, stream, "c2", lofp.METHOD_PATHSUM, steps=2,
+                                          fwd=5, bwd=6),
             "contract_c5": run_variant(lofp, workloads, torch, dev, stream, "c5", lofp.METHOD_CONTRACT, steps=20),
             "served_c4": serve_variant(lofp, workloads)}
 

@@ -82,7 +82,13 @@ typedef struct {
                               (-1 = planner); fwd_layer <= bwd_layer          */
     int32_t record_timing; /* 1: time each phase with HIP events (adds a
                               stream synchronisation at the end of the call) */
-    int32_t reserved[3];
+    int32_t frontier_budget_kb; /* path sum with fwd_layer = -1: the forward
+                              frontier is merged up to the latest layer whose
+                              frontier fits this many KiB (0 = a quarter of
+                              the free device memory); the splitters between
+                              the frontiers (at most 16) are enumerated
+                              depth-first                                  */
+    int32_t reserved[2];
 } lofp_opts;
 
 /* Per-call statistics (filled when a non-null pointer is passed). */

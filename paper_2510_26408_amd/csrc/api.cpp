@@ -157,7 +157,7 @@ lofp_status device_init(lofp_circuit_s &c, int n, hipStream_t s)
         HIPCHK(upload(c.d_cut_ngates, c.cut_ngates, s));
         HIPCHK(upload(c.d_cut_gates, c.cut_gates, s));
         HIPCHK(upload(c.d_ver_at, c.ver_at, s));
-        HIPCHK(ensure(c.d_counters, 8 * sizeof(unsigned long long)));
+        HIPCHK(ensure(c.d_counters, 16 * sizeof(unsigned long long)));
         c.dev_ready = true;
         c.pending_init = true;
     }
@@ -648,14 +648,18 @@ lofp_status run_pathsum(lofp_circuit_s &c, const int32_t *S, int n, int B, const
     // path is unique given the configuration before them, Eq. (10)), forward
     // frontier one layer earlier; the layers in between are enumerated
     int bl = o.bwd_layer, fl = o.fwd_layer;
-    if (bl < 0) bl = std::max(0, D - 2);
-    if (fl < 0) fl = std::max(0, bl - 1);
-    if (fl > bl || bl > D || fl < 0) return fail(LOFP_EINVAL, "need 0 <= fwd_layer <= bwd_layer <= depth");
-    const int sf = c.layer_start[fl], sb = c.layer_start[bl];
-    // stage slots: forward stages 0..sf, backward stages sb..G
+    if (bl < 0) bl = std::min(D, std::max({0, D - 2, fl}));
+    if (bl < 0 || bl > D) return fail(LOFP_EINVAL, "need 0 <= bwd_layer <= depth");
+    if (fl > bl) return fail(LOFP_EINVAL, "need fwd_layer <= bwd_layer");
+    const bool auto_fwd = fl < 0;
+    const int sb = c.layer_start[bl];
+    // stage slots: with an automatic forward cut every stage up to the
+    // backward frontier is counted first, so the cut can be chosen from the
+    // exact frontier sizes
     std::vector<int32_t> slot_stage;
     std::vector<int> slot_of(G + 1, -1);
-    for (int st_ = 0; st_ <= sf; ++st_) { slot_of[st_] = (int)slot_stage.size(); slot_stage.push_back(st_); }
+    const int s_last_fwd = auto_fwd ? sb : c.layer_start[fl];
+    for (int st_ = 0; st_ <= s_last_fwd; ++st_) { slot_of[st_] = (int)slot_stage.size(); slot_stage.push_back(st_); }
     for (int st_ = sb; st_ <= G; ++st_)
         if (slot_of[st_] < 0) { slot_of[st_] = (int)slot_stage.size(); slot_stage.push_back(st_); }
     const int nslots = (int)slot_stage.size();
@@ -676,31 +680,86 @@ lofp_status run_pathsum(lofp_circuit_s &c, const int32_t *S, int n, int B, const
     std::vector<int32_t> cnt((size_t)nslots * B + 1);
     HIPCHK(hipMemcpyAsync(cnt.data(), c.d_count.p, cnt.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (cnt.back()) return fail(LOFP_ENOMEM, "a frontier state space exceeds 2^31 states");
+    // per-slot totals (a count of -1 marks a state space beyond 2^31)
+    std::vector<int64_t> tot(nslots, 0);
+    std::vector<char> over(nslots, 0);
+    for (int k = 0; k < nslots; ++k)
+        for (int p = 0; p < B; ++p) {
+            const int32_t v = cnt[(size_t)k * B + p];
+            if (v < 0) over[k] = 1; else tot[k] += v;
+        }
+    if (auto_fwd) {
+        // Schroedinger-Feynman trade-off: merge forward as far as the frontier
+        // fits the memory budget; the layers left between the frontiers are
+        // enumerated depth-first (at most kMaxDfsGates splitters, for the
+        // LDS stack)
+        size_t budget = (size_t)std::max(o.frontier_budget_kb, 0) << 10;
+        if (budget == 0) {
+            size_t fr = 0, total = 0;
+            budget = hipMemGetInfo(&fr, &total) == hipSuccess ? fr / 4 : ((size_t)8 << 30);
+        }
+        fl = -1;
+        for (int cand = bl; cand >= 0; --cand) {
+            const int sf_c = c.layer_start[cand];
+            if (sb - sf_c > kMaxDfsGates) break;
+            bool ok = true;
+            int64_t mx = 0;
+            for (int st_ = 0; st_ <= sf_c && ok; ++st_) {
+                const int k = slot_of[st_];
+                if (over[k]) ok = false;
+                mx = std::max(mx, tot[k]);
+            }
+            if (ok && (size_t)mx * 2 * sizeof(double2) <= budget) { fl = cand; break; }
+        }
+        if (fl < 0) return fail(LOFP_ENOMEM, "no forward frontier fits the memory budget within the depth-first limit");
+    }
+    const int sf = c.layer_start[fl];
+    for (int st_ = 0; st_ <= sf; ++st_)
+        if (over[slot_of[st_]]) return fail(LOFP_ENOMEM, "a frontier state space exceeds 2^31 states");
+    for (int st_ = sb; st_ <= G; ++st_)
+        if (over[slot_of[st_]]) return fail(LOFP_ENOMEM, "a frontier state space exceeds 2^31 states");
     std::vector<int64_t> off((size_t)nslots * (B + 1));
     std::vector<int32_t> coff((size_t)nslots * (B + 1));   // chunk offsets (kGateChunk)
-    std::vector<int64_t> tot(nslots);
     std::vector<int32_t> nch(nslots);
     static_assert(kGateChunk == kDfsChunk, "one chunk size for frontier and depth-first kernels");
     for (int k = 0; k < nslots; ++k) {
         int64_t acc = 0, ca = 0;
         for (int p = 0; p < B; ++p) {
+            const int64_t v = std::max<int32_t>(0, cnt[(size_t)k * B + p]);
             off[(size_t)k * (B + 1) + p] = acc;
-            coff[(size_t)k * (B + 1) + p] = (int32_t)ca;
-            acc += cnt[(size_t)k * B + p];
-            ca += (cnt[(size_t)k * B + p] + kGateChunk - 1) / kGateChunk;
+            coff[(size_t)k * (B + 1) + p] = (int32_t)std::min<int64_t>(ca, 0x7fffffff);
+            acc += v;
+            ca += (v + kGateChunk - 1) / kGateChunk;
         }
-        if (ca > 0x7fffffffLL) return fail(LOFP_ENOMEM, "too many frontier chunks");
         off[(size_t)k * (B + 1) + B] = acc;
-        coff[(size_t)k * (B + 1) + B] = (int32_t)ca;
-        tot[k] = acc;
-        nch[k] = (int32_t)ca;
+        coff[(size_t)k * (B + 1) + B] = (int32_t)std::min<int64_t>(ca, 0x7fffffff);
+        nch[k] = (int32_t)std::min<int64_t>(ca, 0x7fffffff);
+    }
+    // per-XCD chunk lists: patterns x, x+8, x+16, ... for XCD x
+    const int nbx = (B + kXcds - 1) / kXcds;
+    std::vector<int32_t> xoff((size_t)nslots * kXcds * (nbx + 1));
+    std::vector<int32_t> xgrid(nslots);
+    for (int k = 0; k < nslots; ++k) {
+        int longest = 0;
+        for (int x = 0; x < kXcds; ++x) {
+            int32_t *xo = xoff.data() + ((size_t)k * kXcds + x) * (nbx + 1);
+            int64_t acc = 0;
+            for (int i = 0; i < nbx; ++i) {
+                xo[i] = (int32_t)acc;
+                const int p = x + kXcds * i;
+                if (p < B) acc += (std::max<int32_t>(0, cnt[(size_t)k * B + p]) + kGateChunk - 1) / kGateChunk;
+            }
+            xo[nbx] = (int32_t)std::min<int64_t>(acc, 0x7fffffff);
+            longest = std::max(longest, xo[nbx]);
+        }
+        xgrid[k] = (int)std::min<int64_t>((int64_t)longest * kXcds, 0x7fffffff);
     }
     HIPCHK(upload(c.d_off, off, s));
-    HIPCHK(upload(c.d_coff, coff, s));
+    HIPCHK(upload(c.d_coff, xoff, s));
+    (void)coff;
     const int64_t *d_off = c.d_off.as<int64_t>();
-    auto coffp = [&](int stage) { return c.d_coff.as<int32_t>() + (size_t)slot_of[stage] * (B + 1); };
-    auto nchp = [&](int stage) { return nch[slot_of[stage]]; };
+    auto xoffp = [&](int stage) { return c.d_coff.as<int32_t>() + (size_t)slot_of[stage] * kXcds * (nbx + 1); };
+    auto gridp = [&](int stage) { return xgrid[slot_of[stage]]; };
     auto offp = [&](int stage) { return d_off + (size_t)slot_of[stage] * (B + 1); };
     auto Cp = [&](int stage) { return c.d_C.as<int32_t>() + (size_t)slot_of[stage] * B * tsz; };
     auto Ep = [&](int stage) { return c.d_E.as<int32_t>() + (size_t)slot_of[stage] * B * tsz; };
@@ -728,7 +787,7 @@ lofp_status run_pathsum(lofp_circuit_s &c, const int32_t *S, int n, int B, const
         a.off_tgt = offp(g + 1); a.off_src = offp(g);
         a.W = c.d_table.as<double2>() + (size_t)g * c.tab_stride;
         a.src = F; a.dst = Fn; a.total_tgt = totp(g + 1);
-        a.chunk_off = coffp(g + 1); a.nchunks = nchp(g + 1);
+        a.xoff = xoffp(g + 1); a.nbx = nbx; a.grid = gridp(g + 1);
         HIPCHK(launch_gate(a, true, s));
         std::swap(F, Fn);
     }
@@ -746,14 +805,14 @@ lofp_status run_pathsum(lofp_circuit_s &c, const int32_t *S, int n, int B, const
         a.off_tgt = offp(g); a.off_src = offp(g + 1);
         a.W = c.d_table.as<double2>() + (size_t)g * c.tab_stride;
         a.src = Bv; a.dst = Bn; a.total_tgt = totp(g);
-        a.chunk_off = coffp(g); a.nchunks = nchp(g);
+        a.xoff = xoffp(g); a.nbx = nbx; a.grid = gridp(g);
         HIPCHK(launch_gate(a, false, s));
         std::swap(Bv, Bn);
     }
     tm.mark();  // 3
     (void)span;
     unsigned long long *ctr = c.d_counters.as<unsigned long long>();
-    HIPCHK(hipMemsetAsync(ctr, 0, 8 * sizeof(unsigned long long), s));
+    HIPCHK(hipMemsetAsync(ctr, 0, 16 * sizeof(unsigned long long), s));
     const int levels = sb - sf;
     if (levels > 0 && totp(sf) > 0) {
         // compact image of the middle gates' tables: sectors up to the largest
@@ -786,7 +845,7 @@ lofp_status run_pathsum(lofp_circuit_s &c, const int32_t *S, int n, int B, const
         an.lo = c.d_lo.as<int16_t>(); an.hi = c.d_hi.as<int16_t>();
         an.C_front = Cp(sf); an.E_back = Ep(sb);
         an.off_front = offp(sf);
-        an.chunk_off = coffp(sf); an.nchunks = nchp(sf);
+        an.xoff = xoffp(sf); an.nbx = nbx; an.nchunks = gridp(sf);
         an.cfg_words = words;
         an.cfg = c.d_cfg.as<uint32_t>();
         an.rank_back = c.d_rankb.as<int32_t>();
@@ -805,9 +864,9 @@ lofp_status run_pathsum(lofp_circuit_s &c, const int32_t *S, int n, int B, const
         a.off_front = offp(sf); a.off_back = offp(sb);
         a.front = F; a.back = Bv;
         a.total = totp(sf);
-        a.chunk_off = coffp(sf);
-        a.nchunks = nchp(sf);
-        a.work_counter = ctr;
+        a.xoff = xoffp(sf);
+        a.nbx = nbx;
+        a.work_counter = ctr + 8;
         a.stat_leaves = ctr + 1;
         a.stat_edges = ctr + 2;
         a.fp32_products = o.precision == LOFP_PREC_FP32;
@@ -822,7 +881,7 @@ lofp_status run_pathsum(lofp_circuit_s &c, const int32_t *S, int n, int B, const
                 ncu = prop.multiProcessorCount;
         }
         const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / std::max<size_t>(lds, 1)));
-        const int64_t grid = std::min<int64_t>((int64_t)ncu * per_cu, a.nchunks);
+        const int64_t grid = std::min<int64_t>((int64_t)ncu * per_cu, std::max(gridp(sf), 1));
         tm.mark();  // 4
         HIPCHK(launch_dfs(a, (int)std::max<int64_t>(grid, 1), s));
         tm.mark();  // 5

@@ -49,18 +49,17 @@ __global__ __launch_bounds__(kDfsChunk) void k_annotate(AnnotateArgs g)
 {
     __shared__ int32_t sC[kTabMax], sE[kTabMax];
     __shared__ int16_t sL[kMaxCuts], sH[kMaxCuts];
-    __shared__ int s_p;
+    __shared__ int s_p, s_ch;
     const int nc = g.m - 1, W = table_cols(g.n), span = (g.D + 1) * nc, tsz = nc * W;
     if (threadIdx.x == 0) {
-        int lo = 0, hi = g.B - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (g.chunk_off[mid] <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
-        }
-        s_p = lo;
+        int pp = -1, ch = 0;
+        if (!xcd_chunk(g.xoff, g.nbx, g.B, blockIdx.x, pp, ch)) pp = -1;
+        s_p = pp;
+        s_ch = ch;
     }
     __syncthreads();
     const int p = s_p;
+    if (p < 0) return;
     const int16_t *lo = g.lo + (int64_t)p * span, *hi = g.hi + (int64_t)p * span;
     for (int i = threadIdx.x; i < tsz; i += blockDim.x) {
         sC[i] = g.C_front[(int64_t)p * tsz + i];
@@ -72,7 +71,7 @@ __global__ __launch_bounds__(kDfsChunk) void k_annotate(AnnotateArgs g)
         sH[r] = hi[t * nc + r];
     }
     __syncthreads();
-    const int64_t i = (int64_t)(blockIdx.x - g.chunk_off[p]) * kDfsChunk + threadIdx.x;
+    const int64_t i = (int64_t)s_ch * kDfsChunk + threadIdx.x;
     const int64_t base = g.off_front[p];
     if (i >= g.off_front[p + 1] - base) return;
     int64_t rem = i;
@@ -141,7 +140,7 @@ __global__ __launch_bounds__(kDfsBlock) void k_dfs(DfsArgs g)
     int2 *stM = reinterpret_cast<int2 *>(smem + Ly.stM);
     int32_t *sE = reinterpret_cast<int32_t *>(smem + Ly.E);
     int2 *sLH = reinterpret_cast<int2 *>(smem + Ly.LH);
-    __shared__ int s_chunk, s_p, s_cnt, s_beg, s_end;
+    __shared__ int s_p, s_cnt, s_beg, s_end;
     const int tid = threadIdx.x, bd = kDfsBlock;
 
     if (TAB_LDS)
@@ -153,24 +152,39 @@ __global__ __launch_bounds__(kDfsBlock) void k_dfs(DfsArgs g)
     unsigned long long leaves = 0, edges = 0;
     int cur_p = -1;
 
+    // blocks take chunks from their own XCD's list first (patterns p with
+    // p % 8 == XCD share its L2), then help the other lists
+    const int home = blockIdx.x % kXcds;
+    int lst = 0;
     while (true) {
-        if (tid == 0) s_chunk = (int)atomicAdd(g.work_counter, 1ull);
-        __syncthreads();
-        const int c = s_chunk;
-        if (c >= g.nchunks) break;
         if (tid == 0) {
-            int lo = 0, hi = g.B - 1;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (g.chunk_off[mid] <= c) lo = mid; else hi = mid - 1;
+            int pp = -1, beg = 0, end = 0;
+            while (lst < kXcds) {
+                const int x = (home + lst) % kXcds;
+                const int32_t *xo = g.xoff + (size_t)x * (g.nbx + 1);
+                const int j = (int)atomicAdd(g.work_counter + x, 1ull);
+                if (j < xo[g.nbx]) {
+                    int lo = 0, hi = g.nbx - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (xo[mid] <= j) lo = mid; else hi = mid - 1;
+                    }
+                    pp = x + kXcds * lo;
+                    const int64_t cnt = g.off_front[pp + 1] - g.off_front[pp];
+                    const int64_t b = (int64_t)(j - xo[lo]) * kDfsChunk;
+                    beg = (int)b;
+                    end = (int)(b + kDfsChunk < cnt ? b + kDfsChunk : cnt);
+                    break;
+                }
+                ++lst;
             }
-            s_p = lo;
+            s_p = pp;
+            s_beg = beg;
+            s_end = end;
             s_cnt = 0;
-            const int64_t cnt = g.off_front[lo + 1] - g.off_front[lo];
-            const int64_t b = (int64_t)(c - g.chunk_off[lo]) * kDfsChunk;
-            s_beg = (int)b;
-            s_end = (int)(b + kDfsChunk < cnt ? b + kDfsChunk : cnt);
         }
+        __syncthreads();
+        if (s_p < 0) break;
         __syncthreads();
         const int p = s_p;
         if (p != cur_p) {
@@ -323,7 +337,7 @@ static void launch_dfs_t(const DfsArgs &a, dim3 gr, size_t lds, hipStream_t stre
 
 hipError_t launch_dfs(const DfsArgs &a, int grid, hipStream_t stream)
 {
-    if (a.total == 0 || a.levels == 0 || a.nchunks == 0) return hipSuccess;
+    if (a.total == 0 || a.levels == 0) return hipSuccess;
     if (a.levels > kMaxLevels) return hipErrorInvalidValue;
     const size_t lds = dfs_lds_bytes(a);
     if (lds > 64 * 1024) return hipErrorInvalidValue;

@@ -31,18 +31,17 @@ __global__ __launch_bounds__(kGateChunk) void k_gate(GateArgs g)
 {
     __shared__ int32_t sC[kTabMax], sE[kTabMax];
     __shared__ int16_t sL[kMaxCuts], sH[kMaxCuts];
-    __shared__ int s_p, s_Ls, s_Hs;
+    __shared__ int s_p, s_ch, s_Ls, s_Hs;
     const int nc = g.m - 1, W = table_cols(g.n), span = (g.D + 1) * nc, tsz = nc * W;
     if (threadIdx.x == 0) {
-        int lo = 0, hi = g.B - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (g.chunk_off[mid] <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
-        }
-        s_p = lo;
+        int pp = -1, ch = 0;
+        if (!xcd_chunk(g.xoff, g.nbx, g.B, blockIdx.x, pp, ch)) pp = -1;
+        s_p = pp;
+        s_ch = ch;
     }
     __syncthreads();
     const int p = s_p;
+    if (p < 0) return;
     const int16_t *lo = g.lo + (int64_t)p * span, *hi = g.hi + (int64_t)p * span;
     const int32_t *Ct = g.C_tgt + (int64_t)p * tsz;
     const int32_t *Es = g.E_src + (int64_t)p * tsz;
@@ -59,7 +58,7 @@ __global__ __launch_bounds__(kGateChunk) void k_gate(GateArgs g)
         s_Hs = hi[ts * nc + a];
     }
     __syncthreads();
-    const int64_t i = (int64_t)(blockIdx.x - g.chunk_off[p]) * kGateChunk + threadIdx.x;
+    const int64_t i = (int64_t)s_ch * kGateChunk + threadIdx.x;
     const int64_t base_t = g.off_tgt[p];
     if (i >= g.off_tgt[p + 1] - base_t) return;
 
@@ -100,9 +99,10 @@ __global__ __launch_bounds__(kGateChunk) void k_gate(GateArgs g)
 
 hipError_t launch_gate(const GateArgs &a, bool forward, hipStream_t stream)
 {
-    if (a.total_tgt == 0 || a.nchunks == 0) return hipSuccess;
+    if (a.total_tgt == 0) return hipSuccess;
     const int block = kGateChunk;
-    const dim3 grid((unsigned)a.nchunks);
+    if (a.grid <= 0) return hipSuccess;
+    const dim3 grid((unsigned)a.grid);
     const int nc = a.m - 1;
     if (nc <= 15) {
         if (forward) hipLaunchKernelGGL((k_gate<15, true>), grid, dim3(block), 0, stream, a);

@@ -85,10 +85,30 @@ struct GateArgs {
     const double2 *src;
     double2 *dst;
     int64_t total_tgt;
-    const int32_t *chunk_off;  // [B+1] prefix of ceil(count_tgt[p] / kGateChunk)
-    int nchunks;
+    const int32_t *xoff;       // [8][nbx+1] per-XCD chunk prefix over patterns x, x+8, ...
+    int nbx;                   // ceil(B / 8)
+    int grid;                  // 8 x the longest per-XCD chunk list
 };
 constexpr int kGateChunk = 256;
+constexpr int kXcds = 8;       // workgroup b runs on XCD b % 8 (round-robin dispatch)
+
+// Map a workgroup to (pattern, chunk within the pattern) so that all chunks
+// of pattern p run on XCD p % 8 and share that XCD's L2.  Returns false for
+// workgroups past the end of their XCD's list.
+__device__ __forceinline__ bool xcd_chunk(const int32_t *xoff, int nbx, int B, int block, int &p, int &chunk)
+{
+    const int x = block % kXcds, j = block / kXcds;
+    const int32_t *xo = xoff + (size_t)x * (nbx + 1);
+    if (j >= xo[nbx]) return false;
+    int lo = 0, hi = nbx - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (xo[mid] <= j) lo = mid; else hi = mid - 1;
+    }
+    p = x + kXcds * lo;
+    chunk = j - xo[lo];
+    return p < B;
+}
 hipError_t launch_gate(const GateArgs &a, bool forward, hipStream_t stream);
 
 // a4: depth-first enumeration of the middle beam splitters.
@@ -108,14 +128,15 @@ struct DfsArgs {
     double2 *front;           // frontier values; overwritten by value * suffix sum
     const double2 *back;      // backward frontier values
     int64_t total;            // frontier entries
-    const int32_t *chunk_off; // [B+1] prefix of ceil(count_front[p] / kDfsChunk)
-    int nchunks;
-    unsigned long long *work_counter;
+    const int32_t *xoff;      // [8][nbx+1] per-XCD chunk prefix (see xcd_chunk)
+    int nbx;
+    unsigned long long *work_counter;   // [8] one counter per XCD list
     unsigned long long *stat_leaves;
     unsigned long long *stat_edges;
     int fp32_products;        // 1: running products in FP32
 };
 constexpr int kDfsChunk = 256;
+constexpr int kMaxDfsGates = 16;   // splitters enumerated depth-first (LDS stack depth)
 constexpr int kDfsBlock = 128;
 hipError_t launch_dfs(const DfsArgs &a, int grid, hipStream_t stream);
 size_t dfs_lds_bytes(const DfsArgs &a);
@@ -128,8 +149,9 @@ struct AnnotateArgs {
     const int16_t *lo, *hi;
     const int32_t *C_front, *E_back;
     const int64_t *off_front;
-    const int32_t *chunk_off;
-    int nchunks;
+    const int32_t *xoff;
+    int nbx;
+    int nchunks;               // grid size (8 x the longest per-XCD list)
     int cfg_words;
     uint32_t *cfg;
     int32_t *rank_back;

@@ -84,7 +84,7 @@ __global__ void k_stage_tables(int B, int m, int D, int n, int nslots, const int
     }
     const int64_t c = build_stage_tables(m, n, stage_time + (int64_t)s * nc, lo + (int64_t)p * span,
                                          hi + (int64_t)p * span, Cp, Ep);
-    if (c < 0) { atomicOr(overflow, 1); count[k] = 0; return; }
+    if (c < 0) { atomicOr(overflow, 1); count[k] = -1; return; }
     count[k] = (int32_t)c;
 }
 

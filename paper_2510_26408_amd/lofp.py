@@ -45,7 +45,7 @@ class C128(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("precision", ctypes.c_int32), ("fwd_layer", ctypes.c_int32),
                 ("bwd_layer", ctypes.c_int32), ("record_timing", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("frontier_budget_kb", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class Stats(ctypes.Structure):
@@ -137,10 +137,11 @@ def _ip(a: np.ndarray):
 
 
 def make_opts(method: int = METHOD_AUTO, precision: int = PREC_FP64, fwd_layer: int = -1, bwd_layer: int = -1,
-              record_timing: bool = False) -> Opts:
+              record_timing: bool = False, frontier_budget_kb: int = 0) -> Opts:
     o = Opts()
     o.method, o.precision, o.fwd_layer, o.bwd_layer = method, precision, fwd_layer, bwd_layer
     o.record_timing = 1 if record_timing else 0
+    o.frontier_budget_kb = frontier_budget_kb
     return o
 
 

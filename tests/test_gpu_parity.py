@@ -171,7 +171,7 @@ def test_c2_full_batch_sampled():
     T = torch.from_numpy(wl.Ts).cuda()
     out = torch.zeros(wl.batch, dtype=torch.complex128, device="cuda")
     st = lofp.Stats()
-    c.amplitudes_device(wl.S, T, out, lofp.make_opts(method=lofp.METHOD_PATHSUM), stats=st)
+    c.amplitudes_device(wl.S, T, out, lofp.make_opts(method=lofp.METHOD_PATHSUM, fwd_layer=5, bwd_layer=6), stats=st)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
     idx = np.random.default_rng(0).choice(wl.batch, 64, replace=False)
@@ -223,6 +223,21 @@ def test_fp32_products_within_bound():
     # products of at most `levels` FP32 factors: relative error per path
     # <= (2 levels + 2) 2^-24; summed paths of magnitude <= 1 each
     assert err.max() < 1e-5
+
+
+def test_frontier_budget_moves_the_cut_to_depth_first():
+    """A small frontier budget makes the planner stop merging earlier and
+    enumerate more splitters depth-first; the result does not change."""
+    wl = workloads.make("c1", seed=6)
+    pats = np.array(oracle.all_patterns(wl.m, wl.n), dtype=np.int32)
+    c = lofp.Circuit(wl.m, wl.layers)
+    st_big, st_small = lofp.Stats(), lofp.Stats()
+    a = c.amplitudes(wl.S, pats, lofp.make_opts(method=lofp.METHOD_PATHSUM), st_big)
+    b = c.amplitudes(wl.S, pats, lofp.make_opts(method=lofp.METHOD_PATHSUM, frontier_budget_kb=40), st_small)
+    assert st_big.fwd_layer == st_big.bwd_layer == wl.depth - 2
+    assert st_small.fwd_layer < st_small.bwd_layer and st_small.dfs_leaves > 0
+    check(a, b)
+    check(a, oracle_amps(wl.m, wl.S, pats, wl.layers))
 
 
 def test_pathsum_state_space_overflow_is_reported():
