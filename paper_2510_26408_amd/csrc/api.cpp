@@ -352,7 +352,25 @@ SplitProgram *get_split(lofp_circuit_s &c, int rs)
     return raw;
 }
 
-// Largest contraction state of the program under the given per-time bounds.
+// Largest contraction state of a step list under the given per-time bounds.
+int64_t steps_state_bound(const lofp_circuit_s &c, const std::vector<ContractStep> &steps,
+                          const std::vector<int16_t> &lo, const std::vector<int16_t> &hi)
+{
+    int64_t mx = 1;
+    for (const ContractStep &st : steps) {
+        int64_t ns = 1;
+        for (int q = 0; q < st.n_new; ++q) {
+            const int v = st.new_vars[q];
+            const size_t i = (size_t)c.var_time[v] * c.nc + c.var_cut[v];
+            ns *= std::max(1, hi[i] - lo[i] + 1);
+            if (ns > (1LL << 40)) return ns;
+        }
+        mx = std::max(mx, ns);
+    }
+    return mx;
+}
+
+// Largest contraction state of the full program under the given per-time bounds.
 int64_t program_state_bound(const lofp_circuit_s &c, const std::vector<int16_t> &lo, const std::vector<int16_t> &hi)
 {
     int64_t mx = 1;
@@ -396,8 +414,8 @@ lofp_status ready_on_stream(lofp_circuit_s &c, hipStream_t s)
     return LOFP_OK;
 }
 
-lofp_status run_contract_split(lofp_circuit_s &c, int n, int B, const int32_t *T_dev, lofp_c128 *out_dev, int fp32,
-                               hipStream_t s, lofp_stats *st, Timer &tm, bool &used);
+lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
+                               lofp_c128 *out_dev, int fp32, hipStream_t s, lofp_stats *st, Timer &tm, bool &used);
 
 lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
                          lofp_c128 *out_dev, int count_only, int fp32, hipStream_t s, lofp_stats *st, Timer &tm,
@@ -409,7 +427,7 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
     if (rc != LOFP_OK) return rc;
     if (!count_only && allow_split && B >= 64) {
         bool used = false;
-        rc = run_contract_split(c, n, B, T_dev, out_dev, fp32, s, st, tm, used);
+        rc = run_contract_split(c, S, n, B, T_dev, out_dev, fp32, s, st, tm, used);
         if (rc != LOFP_OK || used) return rc;
     }
     tm.mark();
@@ -523,8 +541,8 @@ static void group_rows(const std::vector<int32_t> &T, int B, int m, int n, int c
     for (int p = 0; p < B; ++p) km.members[fill[km.of[p]]++] = p;
 }
 
-lofp_status run_contract_split(lofp_circuit_s &c, int n, int B, const int32_t *T_dev, lofp_c128 *out_dev, int fp32,
-                               hipStream_t s, lofp_stats *st, Timer &tm, bool &used)
+lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
+                               lofp_c128 *out_dev, int fp32, hipStream_t s, lofp_stats *st, Timer &tm, bool &used)
 {
     used = false;
     const int m = c.m, nc = c.nc, span = (c.D + 1) * nc;
@@ -594,24 +612,35 @@ lofp_status run_contract_split(lofp_circuit_s &c, int n, int B, const int32_t *T
     HIPCHK(upload(c.d_jobs, jobs, s));
     unsigned long long *ctr = c.d_counters.as<unsigned long long>();
     HIPCHK(hipMemsetAsync(ctr, 0, 8 * sizeof(unsigned long long), s));
-    int *d_max = reinterpret_cast<int *>(ctr + 5);
-    HIPCHK(launch_multi_sizes(nj, c.d_jobs.as<ContractJob>(), d_max, s));
-    int mx = 0;
-    HIPCHK(hipMemcpyAsync(&mx, d_max, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (mx > (1 << 22)) return fail(LOFP_ENOMEM, "contraction state exceeds 2^22 entries");
-    mx = std::max(mx, 1);
-    const bool in_lds = contract_job_lds_bytes(c.nvars, m, mx, true) <= 64 * 1024;
-    MultiOverride ov{mx, nullptr, nullptr, mx};
-    if (!in_lds) {
+    // capacity from the S-side intervals (they contain every key's hull), so
+    // no device round trip is needed; each job keeps its state in LDS when its
+    // own largest state fits the launch's LDS, else in its workspace slice
+    std::vector<int16_t> slo, shi;
+    s_only_bounds(c, S, n, slo, shi);
+    int64_t cap = std::max(steps_state_bound(c, sp->top.steps, slo, shi), steps_state_bound(c, sp->bot.steps, slo, shi));
+    int mx;
+    if (cap <= (1 << 20)) {
+        mx = (int)std::max<int64_t>(cap, 1);
+    } else {
+        int *d_max = reinterpret_cast<int *>(ctr + 5);
+        HIPCHK(launch_multi_sizes(nj, c.d_jobs.as<ContractJob>(), d_max, s));
+        HIPCHK(hipMemcpyAsync(&mx, d_max, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (mx > (1 << 22)) return fail(LOFP_ENOMEM, "contraction state exceeds 2^22 entries");
+        mx = std::max(mx, 1);
+    }
+    // LDS budget of the launch: up to 48 KiB of state (two buffers)
+    const int lds_states = (int)std::min<int64_t>(mx, (48 * 1024) / (2 * (int)sizeof(double2)));
+    MultiOverride ov{mx, nullptr, nullptr, mx, lds_states};
+    if (lds_states < mx) {
         HIPCHK(ensure(c.d_ws, (size_t)nj * 2 * mx * sizeof(double2)));
         ov.ws_base = c.d_ws.as<double2>();
     }
     HIPCHK(ensure(c.d_kstate, (size_t)nj * mx * sizeof(double2)));
     ov.state_base = c.d_kstate.as<double2>();
     tm.mark();
-    HIPCHK(launch_contract_multi(nj, c.d_jobs.as<ContractJob>(), contract_job_lds_bytes(c.nvars, m, mx, in_lds), mx,
-                                 in_lds, fp32 != 0, ctr + 3, reinterpret_cast<int32_t *>(ctr + 4), s, ov));
+    HIPCHK(launch_contract_multi(nj, c.d_jobs.as<ContractJob>(), contract_job_lds_bytes(c.nvars, m, lds_states, true),
+                                 lds_states, true, fp32 != 0, ctr + 3, reinterpret_cast<int32_t *>(ctr + 4), s, ov));
     JoinArgs ja{};
     ja.B = B; ja.m = m; ja.n = n; ja.D = c.D;
     ja.lo = c.d_lo.as<int16_t>(); ja.hi = c.d_hi.as<int16_t>();

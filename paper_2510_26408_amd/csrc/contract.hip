@@ -258,6 +258,25 @@ __global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
 }
 
 // Many circuits, one block per job.
+// largest state of one job's program under its own intervals
+__device__ inline int job_max_state(const ContractJob &j)
+{
+    const int nc = j.m - 1;
+    long long best = 1;
+    for (int si = 0; si < j.nsteps; ++si) {
+        const ContractStep &st = j.steps[si];
+        long long ns = 1;
+        for (int q = 0; q < st.n_new; ++q) {
+            const int v = st.new_vars[q];
+            const int t = j.var_time[v], r = j.var_cut[v];
+            const long long rad = j.hi[t * nc + r] - j.lo[t * nc + r] + 1;
+            ns *= rad > 0 ? rad : 0;
+        }
+        if (ns > best) best = ns;
+    }
+    return best > (1 << 22) ? (1 << 22) + 1 : (int)best;
+}
+
 template <bool F32, bool LDS_STATE, int BS>
 __global__ __launch_bounds__(BS) void k_contract_multi(const ContractJob *__restrict__ jobs,
                                                        unsigned long long *stat_transitions, int32_t *overflow,
@@ -272,6 +291,17 @@ __global__ __launch_bounds__(BS) void k_contract_multi(const ContractJob *__rest
             j.state_out = ov.state_base + (int64_t)blockIdx.x * ov.state_cap;
             j.state_cap = ov.state_cap;
         }
+    }
+    if (ov.lds_states > 0) {
+        // per-job choice: the state in LDS when this job's largest state fits
+        const int own = job_max_state(j);
+        if (own <= ov.lds_states) {
+            j.max_states = ov.lds_states;
+            contract_one<false, F32, true, BS>(j, smem, stat_transitions, overflow);
+        } else {
+            contract_one<false, F32, false, BS>(j, smem, stat_transitions, overflow);
+        }
+        return;
     }
     contract_one<false, F32, LDS_STATE, BS>(j, smem, stat_transitions, overflow);
 }
@@ -306,14 +336,17 @@ hipError_t launch_multi_sizes(int count, const ContractJob *jobs, int *mx, hipSt
     return hipGetLastError();
 }
 
-// Hull of the member patterns' intervals, one block per key.
+// Hull of the member patterns' intervals, one thread per (key, entry).
 __global__ void k_hull(int nkeys, const int32_t *__restrict__ key_off, const int32_t *__restrict__ members,
                        const int32_t *__restrict__ infeasible, int span, const int16_t *__restrict__ lo,
                        const int16_t *__restrict__ hi, int16_t *__restrict__ klo, int16_t *__restrict__ khi)
 {
-    const int k = blockIdx.x;
+    const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= (int64_t)nkeys * span) return;
+    const int k = (int)(gi / span);
     const int b = key_off[k], e = key_off[k + 1];
-    for (int i = threadIdx.x; i < span; i += blockDim.x) {
+    {
+        const int i = (int)(gi - (int64_t)k * span);
         int l = 1 << 14, h = -1;
         for (int q = b; q < e; ++q) {
             const int p = members[q];
@@ -333,8 +366,9 @@ hipError_t launch_hull(int nkeys, const int32_t *key_off, const int32_t *members
                        hipStream_t stream)
 {
     if (nkeys == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_hull, dim3(nkeys), dim3(64), 0, stream, nkeys, key_off, members, infeasible, span, lo, hi,
-                       klo, khi);
+    const int64_t total = (int64_t)nkeys * span;
+    hipLaunchKernelGGL(k_hull, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, nkeys, key_off, members,
+                       infeasible, span, lo, hi, klo, khi);
     return hipGetLastError();
 }
 

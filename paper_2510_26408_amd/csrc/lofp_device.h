@@ -223,6 +223,8 @@ struct MultiOverride {
     double2 *ws_base;            // job i uses ws_base + i * 2 * max_states
     double2 *state_base;         // job i writes state_base + i * state_cap
     int state_cap;
+    int lds_states;              // > 0: a job whose own largest state fits this
+                                 // many entries keeps it in LDS, others in ws
 };
 struct BoundsJob {
     int m, D, n;
@@ -236,7 +238,8 @@ hipError_t launch_bounds_multi(int count, const BoundsJob *jobs, hipStream_t str
 // lds_bytes: dynamic LDS per block (max over jobs); max_states: max over jobs
 hipError_t launch_contract_multi(int count, const ContractJob *jobs, size_t lds_bytes, int max_states,
                                  bool state_in_lds, bool fp32, unsigned long long *stat_transitions,
-                                 int32_t *overflow, hipStream_t stream, MultiOverride ov = MultiOverride{0, nullptr, nullptr, 0});
+                                 int32_t *overflow, hipStream_t stream,
+                                 MultiOverride ov = MultiOverride{0, nullptr, nullptr, 0, 0});
 // Largest state over the jobs (one thread per job), atomically maxed into *mx.
 hipError_t launch_multi_sizes(int count, const ContractJob *jobs, int *mx, hipStream_t stream);
 

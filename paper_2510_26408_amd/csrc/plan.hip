@@ -4,12 +4,101 @@
 
 namespace lofp {
 
-// One thread per pattern.
-__global__ void k_bounds(int B, int m, int D, int n, const int32_t *__restrict__ S,
-                         const int32_t *__restrict__ T, const int8_t *__restrict__ fr_lo,
-                         const int8_t *__restrict__ fr_hi, const int8_t *__restrict__ br_lo,
-                         const int8_t *__restrict__ br_hi, const uint8_t *__restrict__ cut_gate,
-                         int16_t *__restrict__ lo, int16_t *__restrict__ hi, int32_t *__restrict__ infeasible)
+// One wave per pattern.  The light-cone intervals of every (time, cut) are
+// computed in parallel into LDS; the propagation then alternates row passes
+// (order between neighbouring cuts: prefix max / suffix min, one lane per
+// time) and column passes (equality across layers without a splitter on the
+// cut, one lane per cut) until nothing changes.
+constexpr int kBoundsLds = 4096;   // int16 entries per array: (D+1)(m-1) <= 4096
+
+__global__ __launch_bounds__(64) void k_bounds(int B, int m, int D, int n, const int32_t *__restrict__ S,
+                                               const int32_t *__restrict__ T, const int8_t *__restrict__ fr_lo,
+                                               const int8_t *__restrict__ fr_hi, const int8_t *__restrict__ br_lo,
+                                               const int8_t *__restrict__ br_hi, const uint8_t *__restrict__ cut_gate,
+                                               int16_t *__restrict__ lo, int16_t *__restrict__ hi,
+                                               int32_t *__restrict__ infeasible)
+{
+    __shared__ int16_t L[kBoundsLds], H[kBoundsLds];
+    __shared__ int sS[kMaxModes], sT[kMaxModes];
+    __shared__ int s_bad;
+    const int p = blockIdx.x, tid = threadIdx.x;
+    const int nc = m - 1, span = (D + 1) * nc;
+    const int32_t *Tp = T + (int64_t)p * m;
+    int16_t *Lg = lo + (int64_t)p * span, *Hg = hi + (int64_t)p * span;
+    if (tid == 0) {
+        int nT = 0, bad = 0;
+        for (int i = 0; i < m; ++i) { nT += Tp[i]; bad |= Tp[i] < 0; sS[i] = S[i]; sT[i] = Tp[i]; }
+        s_bad = bad || nT != n;
+    }
+    __syncthreads();
+    if (s_bad) {
+        for (int i = tid; i < span; i += 64) { Lg[i] = 1; Hg[i] = 0; }
+        if (tid == 0) infeasible[p] = 1;
+        return;
+    }
+    for (int i = tid; i < span; i += 64) {
+        const int t = i / nc, r = i - t * nc;
+        int ls = 0, hs = 0, lt = 0, ht = 0;
+        for (int s = 0; s < m; ++s) {
+            const int x = sS[s], y = sT[s];
+            ls += fr_hi[t * m + s] <= r ? x : 0;
+            hs += fr_lo[t * m + s] <= r ? x : 0;
+            lt += br_hi[t * m + s] <= r ? y : 0;
+            ht += br_lo[t * m + s] <= r ? y : 0;
+        }
+        int l = ls > lt ? ls : lt, h = hs < ht ? hs : ht;
+        l = l < 0 ? 0 : l;
+        h = h > n ? n : h;
+        L[i] = (int16_t)l;
+        H[i] = (int16_t)h;
+    }
+    __syncthreads();
+    for (int it = 0; it < 4 * (D + m) + 8; ++it) {
+        int ch = 0;
+        for (int t = tid; t <= D; t += 64) {          // rows: order between cuts
+            int16_t *Lr = L + t * nc, *Hr = H + t * nc;
+            for (int r = 1; r < nc; ++r)
+                if (Lr[r] < Lr[r - 1]) { Lr[r] = Lr[r - 1]; ch = 1; }
+            for (int r = nc - 2; r >= 0; --r)
+                if (Hr[r] > Hr[r + 1]) { Hr[r] = Hr[r + 1]; ch = 1; }
+        }
+        __syncthreads();
+        for (int r = tid; r < nc; r += 64) {          // columns: no splitter, no change
+            for (int t = 0; t < D; ++t) {
+                if (cut_gate[t * nc + r]) continue;
+                const int a = t * nc + r, b = a + nc;
+                const int16_t l = L[a] > L[b] ? L[a] : L[b], h = H[a] < H[b] ? H[a] : H[b];
+                if (l != L[a] || l != L[b] || h != H[a] || h != H[b]) { L[a] = L[b] = l; H[a] = H[b] = h; ch = 1; }
+            }
+            for (int t = D - 1; t >= 0; --t) {
+                if (cut_gate[t * nc + r]) continue;
+                const int a = t * nc + r, b = a + nc;
+                const int16_t l = L[a] > L[b] ? L[a] : L[b], h = H[a] < H[b] ? H[a] : H[b];
+                if (l != L[a] || l != L[b] || h != H[a] || h != H[b]) { L[a] = L[b] = l; H[a] = H[b] = h; ch = 1; }
+            }
+        }
+        __syncthreads();
+        // the block is one wave: a wave vote gives every lane the same answer
+        if (!__any(ch)) break;
+    }
+    int bad = 0;
+    for (int i = tid; i < span; i += 64) {
+        Lg[i] = L[i];
+        Hg[i] = H[i];
+        bad |= L[i] > H[i];
+    }
+    if (bad) atomicOr(&s_bad, 1);
+    __syncthreads();
+    if (tid == 0) infeasible[p] = s_bad;
+}
+
+// Fallback for circuits with more than 4096 (time, cut) entries: one thread
+// per pattern on global memory.
+__global__ void k_bounds_big(int B, int m, int D, int n, const int32_t *__restrict__ S,
+                             const int32_t *__restrict__ T, const int8_t *__restrict__ fr_lo,
+                             const int8_t *__restrict__ fr_hi, const int8_t *__restrict__ br_lo,
+                             const int8_t *__restrict__ br_hi, const uint8_t *__restrict__ cut_gate,
+                             int16_t *__restrict__ lo, int16_t *__restrict__ hi, int32_t *__restrict__ infeasible)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= B) return;
@@ -33,9 +122,13 @@ hipError_t launch_bounds(int B, int m, int D, int n, const int32_t *S, const int
                          int32_t *infeasible, hipStream_t stream)
 {
     if (B == 0) return hipSuccess;
-    const int block = 64;
-    hipLaunchKernelGGL(k_bounds, dim3((B + block - 1) / block), dim3(block), 0, stream, B, m, D, n, S, T,
-                       fr_lo, fr_hi, br_lo, br_hi, cut_gate, lo, hi, infeasible);
+    if ((D + 1) * (m - 1) <= kBoundsLds) {
+        hipLaunchKernelGGL(k_bounds, dim3(B), dim3(64), 0, stream, B, m, D, n, S, T, fr_lo, fr_hi, br_lo, br_hi,
+                           cut_gate, lo, hi, infeasible);
+    } else {
+        hipLaunchKernelGGL(k_bounds_big, dim3((B + 63) / 64), dim3(64), 0, stream, B, m, D, n, S, T, fr_lo, fr_hi,
+                           br_lo, br_hi, cut_gate, lo, hi, infeasible);
+    }
     return hipGetLastError();
 }
 
