@@ -113,7 +113,7 @@ typedef struct {
     int32_t method_used;      /* LOFP_METHOD_PATHSUM or LOFP_METHOD_CONTRACT   */
     int32_t split_top_keys;   /* contraction split across the batch: distinct  */
     int32_t split_bottom_keys;/*   top / bottom halves of T (0 if not split)   */
-    int32_t reserved_;
+    int32_t max_state;        /* contraction: entries of the largest state     */
 } lofp_stats;
 
 /* Message for the last non-OK status on this thread ("" if none). */

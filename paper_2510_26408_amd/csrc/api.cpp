@@ -481,6 +481,7 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
         HIPCHK(hipStreamSynchronize(s));
         if (h[4]) return fail(LOFP_ENOMEM, "contraction workspace overflow");
         st->transitions = (int64_t)h[3];
+        st->max_state = a.max_states;
     }
     return LOFP_OK;
 }
@@ -629,8 +630,11 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
         if (mx > (1 << 22)) return fail(LOFP_ENOMEM, "contraction state exceeds 2^22 entries");
         mx = std::max(mx, 1);
     }
-    // LDS budget of the launch: up to 48 KiB of state (two buffers)
-    const int lds_states = (int)std::min<int64_t>(mx, (48 * 1024) / (2 * (int)sizeof(double2)));
+    // LDS budget of a job (a few jobs per CU), of which what the step tables
+    // and interval arrays leave holds the two state buffers
+    const size_t lds_job = std::min<size_t>(max_lds_per_block(), (size_t)LOFP_SPLIT_LDS_KB * 1024);
+    const size_t lds_fixed = contract_job_lds_bytes(c.nvars, m, 0, true);
+    const int lds_states = (int)std::min<int64_t>(mx, (int64_t)((lds_job - lds_fixed) / (2 * sizeof(double2))));
     MultiOverride ov{mx, nullptr, nullptr, mx, lds_states};
     if (lds_states < mx) {
         HIPCHK(ensure(c.d_ws, (size_t)nj * 2 * mx * sizeof(double2)));
@@ -663,6 +667,7 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
         HIPCHK(hipStreamSynchronize(s));
         if (h[4]) return fail(LOFP_ENOMEM, "contraction workspace overflow");
         st->transitions = (int64_t)h[3];
+        st->max_state = mx;
         st->split_top_keys = ntop;
         st->split_bottom_keys = nbot;
     }

@@ -43,147 +43,175 @@ __device__ __forceinline__ int qdiv(int a, int d, float inv)
 
 enum { RK_CONST = 0, RK_NEW = 1, RK_SUM = 2 };
 
-// The contraction of one pattern by one block.  F32: each transition product
-// prev * W is formed in FP32 (the path-product precision of the FP32 form);
-// states and sums stay FP64.
-template <bool COUNT, bool F32, bool LDS_STATE, int BS>
-__device__ void contract_one(const ContractJob &g, unsigned char *smem, unsigned long long *stat_transitions,
-                             int32_t *overflow)
+// Range of table entries a step can read: N = (cut above) - (cut below) runs
+// over the differences of the two references' value ranges, and the sectors
+// N are contiguous in the gate's table.
+__device__ __forceinline__ void tab_window(const ContractStep &st, const int *vlo, const int *vrad, const int *spre,
+                                           const int *tpre, int n, int &off, int &cnt)
 {
-    const int nc = g.m - 1;
-    int *vlo = reinterpret_cast<int *>(smem);                 // [nvars]
-    int *vrad = vlo + g.nvars;                                // [nvars]
-    int *spre = vrad + g.nvars;                               // [nc]
-    int *tpre = spre + nc;                                    // [nc]
-    double2 *bufA, *bufB;
-    if (LDS_STATE) {
-        size_t off = (size_t)(2 * g.nvars + 2 * nc) * sizeof(int);
-        off = (off + 15) & ~(size_t)15;
-        bufA = reinterpret_cast<double2 *>(smem + off);
-    } else {
-        bufA = g.ws;
-    }
-    bufB = bufA + g.max_states;
-    if (*g.infeasible) {
-        if (threadIdx.x == 0 && g.out) *g.out = make_double2(0.0, 0.0);
-        return;
-    }
-    if (threadIdx.x == 0) {
-        int s = 0, t = 0;
-        for (int r = 0; r < nc; ++r) { s += g.S[r]; t += g.T[r]; spre[r] = s; tpre[r] = t; }
-    }
-    for (int v = threadIdx.x; v < g.nvars; v += BS) {
-        const int t = g.var_time[v], r = g.var_cut[v];
-        const int L = g.lo[t * nc + r], H = g.hi[t * nc + r];
-        vlo[v] = L;
-        vrad[v] = H - L + 1;
-    }
-    if (threadIdx.x == 0) bufA[0] = make_double2(1.0, 0.0);
-    __syncthreads();
-    unsigned long long trans = 0;
-    int cur_size = 1;
-
-    for (int si = 0; si < g.nsteps; ++si) {
-        const ContractStep &st = g.steps[si];
-        const int n_new = st.n_new, n_old = st.n_old;
-        // old-layout strides
-        int ostr[kMaxActive];
-        {
-            int os = 1;
+    int lo[2], hi[2];
 #pragma unroll
-            for (int q = 0; q < kMaxActive; ++q) {
-                ostr[q] = os;
-                if (q < n_old) os *= vrad[st.old_vars[q]];
-            }
+    for (int k = 0; k < 2; ++k) {
+        const int kind = st.ref_kind[2 + k], arg = st.ref_arg[2 + k];
+        if (kind == CREF_NEW || kind == CREF_SUM) {
+            const int v = kind == CREF_NEW ? st.new_vars[arg] : st.sum_vars[arg];
+            lo[k] = vlo[v];
+            hi[k] = vlo[v] + vrad[v] - 1;
+        } else {
+            const int c = kind == CREF_ZERO ? 0 : kind == CREF_N ? n : kind == CREF_SPRE ? spre[arg] : tpre[arg];
+            lo[k] = c;
+            hi[k] = c;
         }
-        // new-layout strides and, per new variable, its stride in the old layout
-        int nstr[kMaxActive], mstr[kMaxActive];
-        float ninv[kMaxActive];
-        int ns = 1;
-        int nlo4[4] = {0, 0, 0, 0};
+    }
+    const int Nlo = max(0, lo[1] - hi[0]), Nhi = min(n, hi[1] - lo[0]);
+    if (Nhi < Nlo) {
+        off = 0;
+        cnt = 0;
+    } else {
+        off = sector_offset(Nlo);
+        cnt = sector_offset(Nhi + 1) - off;
+    }
+}
+
+// Per-step layout, built once per job from the step program and the job's
+// intervals (all values uniform over the block).  New entry e decodes into
+// digits d_q = (e / nstr[q]) mod rad_q; the old entry it reads sits at
+// sum_q d_q * mstr[q] + i0 * sstr0 + i1 * sstr1 over the summed versions.
+struct StepDesc {
+    int new_size, n_new, gate, toff, tcnt;
+    int srad0, srad1, slo0, slo1, sstr0, sstr1;
+    int rk[4], ra[4], nlo[4];
+    int nstr[kMaxActive], mstr[kMaxActive];
+    float ninv[kMaxActive];
+};
+constexpr int kDescChunk = 16;   // descriptors built per pass (plus the next one)
+
+__device__ inline void build_desc(const ContractStep &st, const int *vlo, const int *vrad, const int *spre,
+                                  const int *tpre, int n, StepDesc &d)
+{
+    const int n_new = st.n_new, n_old = st.n_old;
+    int ostr[kMaxActive];
+    {
+        int os = 1;
 #pragma unroll
         for (int q = 0; q < kMaxActive; ++q) {
-            nstr[q] = ns;
-            ninv[q] = 1.0f / (float)ns;
-            mstr[q] = 0;
-            if (q < n_new) {
-                const int v = st.new_vars[q];
-                const int src = st.new_to_old[q];
-                int ms = 0;
+            ostr[q] = os;
+            if (q < n_old) os *= vrad[st.old_vars[q]];
+        }
+    }
+    long long ns = 1;
 #pragma unroll
-                for (int q2 = 0; q2 < kMaxActive; ++q2) ms = (q2 == src) ? ostr[q2] : ms;
-                mstr[q] = ms;
-                if (q < 4) nlo4[q] = vlo[v];
-                ns *= vrad[v];
+    for (int q = 0; q < kMaxActive; ++q) {
+        int ms = 0;
+        if (q < n_new) {
+            const int v = st.new_vars[q], src = st.new_to_old[q];
+#pragma unroll
+            for (int q2 = 0; q2 < kMaxActive; ++q2) ms = (q2 == src) ? ostr[q2] : ms;
+        }
+        const int nsi = ns < (1 << 30) ? (int)ns : (1 << 30);
+        d.nstr[q] = nsi;
+        d.ninv[q] = 1.0f / (float)nsi;
+        d.mstr[q] = ms;
+        if (q < 4) d.nlo[q] = q < n_new ? vlo[st.new_vars[q]] : 0;
+        if (q < n_new) ns *= vrad[st.new_vars[q]];
+    }
+    d.new_size = ns < (1 << 30) ? (int)ns : (1 << 30);
+    d.n_new = n_new;
+    d.gate = st.gate;
+    d.srad0 = 1; d.srad1 = 1; d.slo0 = 0; d.slo1 = 0; d.sstr0 = 0; d.sstr1 = 0;
+    if (st.n_sum > 0) {
+        const int v = st.sum_vars[0], src = st.sum_to_old[0];
+        int ss = 0;
+#pragma unroll
+        for (int q2 = 0; q2 < kMaxActive; ++q2) ss = (q2 == src) ? ostr[q2] : ss;
+        d.srad0 = vrad[v]; d.slo0 = vlo[v]; d.sstr0 = ss;
+    }
+    if (st.n_sum > 1) {
+        const int v = st.sum_vars[1], src = st.sum_to_old[1];
+        int ss = 0;
+#pragma unroll
+        for (int q2 = 0; q2 < kMaxActive; ++q2) ss = (q2 == src) ? ostr[q2] : ss;
+        d.srad1 = vrad[v]; d.slo1 = vlo[v]; d.sstr1 = ss;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int kind = st.ref_kind[k], arg = st.ref_arg[k];
+        if (kind == CREF_NEW) { d.rk[k] = RK_NEW; d.ra[k] = arg; }
+        else if (kind == CREF_SUM) { d.rk[k] = RK_SUM; d.ra[k] = arg; }
+        else {
+            d.rk[k] = RK_CONST;
+            d.ra[k] = kind == CREF_ZERO ? 0 : kind == CREF_N ? n : kind == CREF_SPRE ? spre[arg] : tpre[arg];
+        }
+    }
+    tab_window(st, vlo, vrad, spre, tpre, n, d.toff, d.tcnt);
+}
+
+// Entries of a new state for one step: each entry gathers its summed
+// versions in a fixed order (i1 outer, i0 inner).  Loads carry no branch so
+// the visits of an entry overlap; an invalid visit reads a harmless slot and
+// adds nothing.
+template <bool COUNT, bool F32, int BS>
+__device__ __forceinline__ void step_entries(const StepDesc &d, const double2 *__restrict__ bufA,
+                                             double2 *__restrict__ bufB, const double2 *__restrict__ W, int wbase,
+                                             unsigned long long &trans)
+{
+    const int n_new = d.n_new, new_size = d.new_size;
+    int nstr[kMaxActive], mstr[kMaxActive];
+    float ninv[kMaxActive];
+#pragma unroll
+    for (int q = 0; q < kMaxActive; ++q) {
+        nstr[q] = d.nstr[q];
+        mstr[q] = d.mstr[q];
+        ninv[q] = d.ninv[q];
+    }
+    const int srad0 = d.srad0, srad1 = d.srad1, slo0 = d.slo0, slo1 = d.slo1, sstr0 = d.sstr0, sstr1 = d.sstr1;
+    int rk[4], ra[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { rk[k] = d.rk[k]; ra[k] = d.ra[k]; }
+    const int nlo0 = d.nlo[0], nlo1 = d.nlo[1], nlo2 = d.nlo[2], nlo3 = d.nlo[3];
+    for (int e = threadIdx.x; e < new_size; e += BS) {
+        int rem = e, base_old = 0;
+        int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
+#pragma unroll
+        for (int q = kMaxActive - 1; q >= 0; --q) {
+            if (q < n_new) {
+                const int dq = qdiv(rem, nstr[q], ninv[q]);
+                rem -= dq * nstr[q];
+                base_old += dq * mstr[q];
+                if (q == 0) d0 = dq;
+                if (q == 1) d1 = dq;
+                if (q == 2) d2 = dq;
+                if (q == 3) d3 = dq;
             }
         }
-        const int new_size = ns;
-        if (new_size > g.max_states) {
-            if (threadIdx.x == 0) atomicOr(overflow, 1);
-            return;
-        }
-        int srad0 = 1, srad1 = 1, slo0 = 0, slo1 = 0, sstr0 = 0, sstr1 = 0;
-        if (st.n_sum > 0) {
-            const int v = st.sum_vars[0], src = st.sum_to_old[0];
-            srad0 = vrad[v]; slo0 = vlo[v];
-#pragma unroll
-            for (int q2 = 0; q2 < kMaxActive; ++q2) sstr0 = (q2 == src) ? ostr[q2] : sstr0;
-        }
-        if (st.n_sum > 1) {
-            const int v = st.sum_vars[1], src = st.sum_to_old[1];
-            srad1 = vrad[v]; slo1 = vlo[v];
-#pragma unroll
-            for (int q2 = 0; q2 < kMaxActive; ++q2) sstr1 = (q2 == src) ? ostr[q2] : sstr1;
-        }
-        int rk[4], ra[4];
+        const int nv0 = nlo0 + d0, nv1 = nlo1 + d1, nv2 = nlo2 + d2, nv3 = nlo3 + d3;
+        // values of the four references that do not depend on the summed versions
+        int cv[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int kind = st.ref_kind[k], arg = st.ref_arg[k];
-            if (kind == CREF_NEW) { rk[k] = RK_NEW; ra[k] = arg; }
-            else if (kind == CREF_SUM) { rk[k] = RK_SUM; ra[k] = arg; }
-            else {
-                rk[k] = RK_CONST;
-                ra[k] = kind == CREF_ZERO ? 0 : kind == CREF_N ? g.n : kind == CREF_SPRE ? spre[arg] : tpre[arg];
-            }
+            const int a = ra[k];
+            cv[k] = rk[k] == RK_NEW ? (a == 0 ? nv0 : a == 1 ? nv1 : a == 2 ? nv2 : nv3) : a;
         }
-        const double2 *Wg = g.table + (int64_t)st.gate * g.tab_stride;
-        for (int e = threadIdx.x; e < new_size; e += BS) {
-            int rem = e, base_old = 0;
-            int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int i1 = 0; i1 < srad1; ++i1) {
+            const int ob = base_old + i1 * sstr1;
+#pragma unroll 2
+            for (int i0 = 0; i0 < srad0; ++i0) {
+                const double2 prev = bufA[ob + i0 * sstr0];
+                int val[4];
 #pragma unroll
-            for (int q = kMaxActive - 1; q >= 0; --q) {
-                if (q < n_new) {
-                    const int d = qdiv(rem, nstr[q], ninv[q]);
-                    rem -= d * nstr[q];
-                    base_old += d * mstr[q];
-                    if (q == 0) d0 = d;
-                    if (q == 1) d1 = d;
-                    if (q == 2) d2 = d;
-                    if (q == 3) d3 = d;
-                }
-            }
-            const int nv0 = nlo4[0] + d0, nv1 = nlo4[1] + d1, nv2 = nlo4[2] + d2, nv3 = nlo4[3] + d3;
-            double2 acc = make_double2(0.0, 0.0);
-            for (int i1 = 0; i1 < srad1; ++i1) {
-                for (int i0 = 0; i0 < srad0; ++i0) {
-                    const int oi = base_old + i0 * sstr0 + i1 * sstr1;
-                    const double2 prev = bufA[oi];
-                    if (prev.x == 0.0 && prev.y == 0.0) continue;
-                    int val[4];
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int a = ra[k];
-                        const int vn = a == 0 ? nv0 : a == 1 ? nv1 : a == 2 ? nv2 : nv3;
-                        const int vs = a == 0 ? slo0 + i0 : slo1 + i1;
-                        val[k] = rk[k] == RK_NEW ? vn : rk[k] == RK_SUM ? vs : a;
-                    }
-                    const int N = val[3] - val[2], x1 = val[0] - val[2], y1 = val[1] - val[2];
-                    if (x1 < 0 || y1 < 0 || x1 > N || y1 > N) continue;
-                    ++trans;
-                    if (COUNT) {
-                        acc.x += prev.x;
-                    } else {
-                        const double2 w = Wg[sector_offset(N) + x1 * (N + 1) + y1];
+                for (int k = 0; k < 4; ++k)
+                    val[k] = rk[k] == RK_SUM ? (ra[k] == 0 ? slo0 + i0 : slo1 + i1) : cv[k];
+                const int N = val[3] - val[2], x1 = val[0] - val[2], y1 = val[1] - val[2];
+                const bool ok = x1 >= 0 && y1 >= 0 && x1 <= N && y1 <= N;
+                const bool nz = prev.x != 0.0 || prev.y != 0.0;
+                if (COUNT) {
+                    if (ok && nz) { ++trans; acc.x += prev.x; }
+                } else {
+                    const int wi = ok ? sector_offset(N) + x1 * (N + 1) + y1 - wbase : 0;
+                    const double2 w = W[wi];
+                    if (ok && nz) {
+                        ++trans;
                         if (F32) {
                             const float px = (float)prev.x, py = (float)prev.y, wx = (float)w.x, wy = (float)w.y;
                             acc.x += (double)(px * wx - py * wy);
@@ -194,14 +222,161 @@ __device__ void contract_one(const ContractJob &g, unsigned char *smem, unsigned
                     }
                 }
             }
-            bufB[e] = acc;
+        }
+        bufB[e] = acc;
+    }
+}
+
+// LDS of one job: [vlo | vrad | spre | tpre | scratch int] [descriptors]
+// [staged tables (2)] [state buffers (2), when in LDS]
+__host__ __device__ inline size_t job_lds_head(int nvars, int nc)
+{
+    size_t off = (size_t)(2 * nvars + 2 * nc + 4) * sizeof(int);
+    off = (off + 15) & ~(size_t)15;
+    off += (size_t)(kDescChunk + 1) * sizeof(StepDesc);
+    off = (off + 15) & ~(size_t)15;
+    return off;
+}
+
+// Intervals of the job's versions and prefix sums of S and T into LDS.
+// Returns false (after writing a zero amplitude) when the job has no path.
+template <int BS>
+__device__ bool contract_setup(const ContractJob &g, unsigned char *smem)
+{
+    if (*g.infeasible) {
+        if (threadIdx.x == 0 && g.out) *g.out = make_double2(0.0, 0.0);
+        return false;
+    }
+    const int nc = g.m - 1;
+    int *vlo = reinterpret_cast<int *>(smem);
+    int *vrad = vlo + g.nvars;
+    int *spre = vrad + g.nvars;
+    int *tpre = spre + nc;
+    for (int r = threadIdx.x; r < nc; r += BS) {
+        int s = 0, t = 0;
+        for (int i = 0; i <= r; ++i) { s += g.S[i]; t += g.T[i]; }
+        spre[r] = s;
+        tpre[r] = t;
+    }
+    for (int v = threadIdx.x; v < g.nvars; v += BS) {
+        const int t = g.var_time[v], r = g.var_cut[v];
+        const int L = g.lo[t * nc + r], H = g.hi[t * nc + r];
+        vlo[v] = L;
+        vrad[v] = H - L + 1;
+    }
+    __syncthreads();
+    return true;
+}
+
+// Largest state of the job's program (after contract_setup), by threads over steps.
+template <int BS>
+__device__ int job_max_state(const ContractJob &g, unsigned char *smem)
+{
+    const int nc = g.m - 1;
+    const int *vrad = reinterpret_cast<const int *>(smem) + g.nvars;
+    int *red = const_cast<int *>(vrad) + g.nvars + 2 * nc;
+    if (threadIdx.x == 0) *red = 1;
+    __syncthreads();
+    int best = 1;
+    for (int si = threadIdx.x; si < g.nsteps; si += BS) {
+        const ContractStep &st = g.steps[si];
+        long long ns = 1;
+        for (int q = 0; q < st.n_new; ++q) ns *= vrad[st.new_vars[q]];
+        const int s = ns > (1 << 22) ? (1 << 22) + 1 : (int)ns;
+        best = s > best ? s : best;
+    }
+    atomicMax(red, best);
+    __syncthreads();
+    const int r = *red;
+    __syncthreads();
+    return r;
+}
+
+// The contraction of one pattern by one block (after contract_setup).  F32:
+// each transition product prev * W is formed in FP32 (the path-product
+// precision of the FP32 form); states and sums stay FP64.
+template <bool COUNT, bool F32, bool LDS_STATE, int BS>
+__device__ void contract_run(const ContractJob &g, unsigned char *smem, unsigned long long *stat_transitions,
+                             int32_t *overflow)
+{
+    const int nc = g.m - 1;
+    const int *vlo = reinterpret_cast<const int *>(smem);
+    const int *vrad = vlo + g.nvars;
+    const int *spre = vrad + g.nvars;
+    const int *tpre = spre + nc;
+    size_t off = (size_t)(2 * g.nvars + 2 * nc + 4) * sizeof(int);
+    off = (off + 15) & ~(size_t)15;
+    StepDesc *desc = reinterpret_cast<StepDesc *>(smem + off);
+    double2 *tabs = reinterpret_cast<double2 *>(smem + job_lds_head(g.nvars, nc));  // [2][kTabStage]
+    double2 *bufA, *bufB;
+    if (LDS_STATE) bufA = tabs + 2 * kTabStage;
+    else bufA = g.ws;
+    bufB = bufA + g.max_states;
+    // descriptors of the first steps
+    for (int k = threadIdx.x; k <= kDescChunk && k < g.nsteps; k += BS)
+        build_desc(g.steps[k], vlo, vrad, spre, tpre, g.n, desc[k]);
+    if (threadIdx.x == 0) bufA[0] = make_double2(1.0, 0.0);
+    __syncthreads();
+    unsigned long long trans = 0;
+    int cur_size = 1;
+    // the transition table of the current step sits in LDS (entries
+    // [toff, toff + tcnt) of the gate's table) when it fits; the next step's
+    // part is fetched into registers while the current step runs
+    constexpr int TPT = kTabStage > 0 ? (kTabStage + BS - 1) / BS : 1;
+    if (!COUNT && kTabStage > 0 && g.nsteps > 0 && desc[0].tcnt <= kTabStage) {
+        const double2 *W0 = g.table + (int64_t)desc[0].gate * g.tab_stride + desc[0].toff;
+        for (int i = threadIdx.x; i < desc[0].tcnt; i += BS) tabs[i] = W0[i];
+        __syncthreads();
+    }
+
+    for (int si = 0; si < g.nsteps; ++si) {
+        const int slot = si % kDescChunk;
+        if (slot == 0 && si > 0) {
+            for (int k = threadIdx.x; k <= kDescChunk && si + k < g.nsteps; k += BS)
+                build_desc(g.steps[si + k], vlo, vrad, spre, tpre, g.n, desc[k]);
+            __syncthreads();
+        }
+        const StepDesc &d = desc[slot];
+        const int new_size = d.new_size;
+        if (new_size > g.max_states) {
+            if (threadIdx.x == 0) atomicOr(overflow, 1);
+            return;
+        }
+        const bool staged = kTabStage > 0 && d.tcnt <= kTabStage;
+        double2 nreg[TPT];
+#pragma unroll
+        for (int j = 0; j < TPT; ++j) nreg[j] = make_double2(0.0, 0.0);
+        int ncnt = kTabStage + 1;
+        if (!COUNT && kTabStage > 0 && si + 1 < g.nsteps) {
+            const StepDesc &dn = desc[slot + 1];
+            ncnt = dn.tcnt;
+            if (ncnt <= kTabStage) {
+                const double2 *Wn = g.table + (int64_t)dn.gate * g.tab_stride + dn.toff;
+#pragma unroll
+                for (int j = 0; j < TPT; ++j) {
+                    const int i = threadIdx.x + j * BS;
+                    if (i < ncnt) nreg[j] = Wn[i];
+                }
+            }
+        }
+        if (staged)
+            step_entries<COUNT, F32, BS>(d, bufA, bufB, tabs + (si & 1) * kTabStage, d.toff, trans);
+        else
+            step_entries<COUNT, F32, BS>(d, bufA, bufB, g.table + (int64_t)d.gate * g.tab_stride, 0, trans);
+        if (!COUNT && kTabStage > 0 && ncnt <= kTabStage) {
+            double2 *Wd = tabs + ((si + 1) & 1) * kTabStage;
+#pragma unroll
+            for (int j = 0; j < TPT; ++j) {
+                const int i = threadIdx.x + j * BS;
+                if (i < ncnt) Wd[i] = nreg[j];
+            }
         }
         __syncthreads();
         double2 *t = bufA; bufA = bufB; bufB = t;
         cur_size = new_size;
     }
     if (g.state_out) {
-        // half of a split contraction: hand the state over instead of summing
+        // half of a split contraction: hand the state over instead of summing it
         if (cur_size > g.state_cap) {
             if (threadIdx.x == 0) atomicOr(overflow, 1);
             return;
@@ -218,10 +393,10 @@ __device__ void contract_one(const ContractJob &g, unsigned char *smem, unsigned
         csum_add(si, x.y);
     }
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        CSum b{__shfl_xor(sr.s, off, 64), __shfl_xor(sr.c, off, 64)};
-        CSum c{__shfl_xor(si.s, off, 64), __shfl_xor(si.c, off, 64)};
-        if (threadIdx.x & off) { CSum t = sr; sr = b; b = t; t = si; si = c; c = t; }
+    for (int off2 = 32; off2 >= 1; off2 >>= 1) {
+        CSum b{__shfl_xor(sr.s, off2, 64), __shfl_xor(sr.c, off2, 64)};
+        CSum c{__shfl_xor(si.s, off2, 64), __shfl_xor(si.c, off2, 64)};
+        if (threadIdx.x & off2) { CSum t = sr; sr = b; b = t; t = si; si = c; c = t; }
         csum_merge(sr, b);
         csum_merge(si, c);
     }
@@ -254,29 +429,11 @@ __global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
     j.ws = LDS_STATE ? nullptr : g.ws + (int64_t)p * 2 * g.max_states;
     j.state_out = nullptr;
     j.state_cap = 0;
-    contract_one<COUNT, F32, LDS_STATE, BS>(j, smem, g.stat_transitions, g.overflow);
+    if (!contract_setup<BS>(j, smem)) return;
+    contract_run<COUNT, F32, LDS_STATE, BS>(j, smem, g.stat_transitions, g.overflow);
 }
 
 // Many circuits, one block per job.
-// largest state of one job's program under its own intervals
-__device__ inline int job_max_state(const ContractJob &j)
-{
-    const int nc = j.m - 1;
-    long long best = 1;
-    for (int si = 0; si < j.nsteps; ++si) {
-        const ContractStep &st = j.steps[si];
-        long long ns = 1;
-        for (int q = 0; q < st.n_new; ++q) {
-            const int v = st.new_vars[q];
-            const int t = j.var_time[v], r = j.var_cut[v];
-            const long long rad = j.hi[t * nc + r] - j.lo[t * nc + r] + 1;
-            ns *= rad > 0 ? rad : 0;
-        }
-        if (ns > best) best = ns;
-    }
-    return best > (1 << 22) ? (1 << 22) + 1 : (int)best;
-}
-
 template <bool F32, bool LDS_STATE, int BS>
 __global__ __launch_bounds__(BS) void k_contract_multi(const ContractJob *__restrict__ jobs,
                                                        unsigned long long *stat_transitions, int32_t *overflow,
@@ -292,18 +449,18 @@ __global__ __launch_bounds__(BS) void k_contract_multi(const ContractJob *__rest
             j.state_cap = ov.state_cap;
         }
     }
+    if (!contract_setup<BS>(j, smem)) return;
     if (ov.lds_states > 0) {
         // per-job choice: the state in LDS when this job's largest state fits
-        const int own = job_max_state(j);
-        if (own <= ov.lds_states) {
+        if (job_max_state<BS>(j, smem) <= ov.lds_states) {
             j.max_states = ov.lds_states;
-            contract_one<false, F32, true, BS>(j, smem, stat_transitions, overflow);
+            contract_run<false, F32, true, BS>(j, smem, stat_transitions, overflow);
         } else {
-            contract_one<false, F32, false, BS>(j, smem, stat_transitions, overflow);
+            contract_run<false, F32, false, BS>(j, smem, stat_transitions, overflow);
         }
         return;
     }
-    contract_one<false, F32, LDS_STATE, BS>(j, smem, stat_transitions, overflow);
+    contract_run<false, F32, LDS_STATE, BS>(j, smem, stat_transitions, overflow);
 }
 
 // Largest state of each job's program under its intervals.
@@ -489,9 +646,18 @@ hipError_t launch_contract_sizes(const ContractArgs &a, int *max_size, hipStream
 
 size_t contract_job_lds_bytes(int nvars, int m, int max_states, bool state_in_lds)
 {
-    size_t off = (size_t)(2 * nvars + 2 * (m - 1)) * sizeof(int);
-    off = (off + 15) & ~(size_t)15;
+    size_t off = job_lds_head(nvars, m - 1);
+    off += (size_t)2 * kTabStage * sizeof(double2);
     return off + (state_in_lds ? (size_t)2 * max_states * sizeof(double2) : 0);
+}
+
+size_t max_lds_per_block()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 64 * 1024;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+        return 64 * 1024;
+    return (size_t)v;
 }
 
 size_t contract_lds_bytes(const ContractArgs &a, bool state_in_lds)
@@ -533,10 +699,14 @@ template <bool F32, bool LDS_STATE>
 static void launch_multi_t(int count, const ContractJob *jobs, size_t dyn, int max_states,
                            unsigned long long *st, int32_t *ov, MultiOverride o, hipStream_t stream)
 {
+    // few large jobs (split halves) get wide blocks so a step's entries spread
+    // over more lanes; many small jobs get one wave each
     if (max_states <= 512)
         hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 64>), dim3(count), dim3(64), dyn, stream, jobs, st, ov, o);
-    else
+    else if (count >= 2048 || max_states <= 2048)
         hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 256>), dim3(count), dim3(256), dyn, stream, jobs, st, ov, o);
+    else
+        hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 512>), dim3(count), dim3(512), dyn, stream, jobs, st, ov, o);
 }
 
 hipError_t launch_contract_multi(int count, const ContractJob *jobs, size_t lds_bytes, int max_states,
@@ -544,7 +714,7 @@ hipError_t launch_contract_multi(int count, const ContractJob *jobs, size_t lds_
                                  int32_t *overflow, hipStream_t stream, MultiOverride o)
 {
     if (count == 0) return hipSuccess;
-    if (lds_bytes > 64 * 1024) return hipErrorInvalidValue;
+    if (lds_bytes > max_lds_per_block()) return hipErrorInvalidValue;
     unsigned long long *st = stat_transitions;
     if (fp32) {
         if (state_in_lds) launch_multi_t<true, true>(count, jobs, lds_bytes, max_states, st, overflow, o, stream);

@@ -166,6 +166,15 @@ hipError_t launch_reduce(int B, const int64_t *off, const double2 *vec, const do
 // a6: mode-axis contraction, one splitter per step.
 constexpr int kMaxActive = 16;         // live versions in a contraction state
 constexpr int kMaxContractVars = 1024; // free versions in a circuit
+// table entries of one contraction step staged in LDS (two buffers; 0: none)
+#ifndef LOFP_TAB_STAGE
+#define LOFP_TAB_STAGE 320
+#endif
+constexpr int kTabStage = LOFP_TAB_STAGE;
+// LDS of one key job of a split contraction (KiB): three jobs share a CU
+#ifndef LOFP_SPLIT_LDS_KB
+#define LOFP_SPLIT_LDS_KB 52
+#endif
 enum { CREF_ZERO = 0, CREF_N = 1, CREF_SPRE = 2, CREF_TPRE = 3, CREF_NEW = 4, CREF_SUM = 5 };
 struct ContractStep {
     int gate;
@@ -264,6 +273,8 @@ struct JoinArgs {
 };
 hipError_t launch_join(const JoinArgs &a, hipStream_t stream);
 size_t contract_job_lds_bytes(int nvars, int m, int max_states, bool state_in_lds);
+// LDS a block may allocate on the current device (64 KiB if the query fails)
+size_t max_lds_per_block();
 hipError_t launch_contract_sizes(const ContractArgs &a, int *max_size, hipStream_t stream);
 // dynamic LDS of the contraction kernel (state buffers included when in LDS)
 size_t contract_lds_bytes(const ContractArgs &a, bool state_in_lds);

@@ -57,7 +57,7 @@ class Stats(ctypes.Structure):
                 ("ms_dfs", ctypes.c_double), ("ms_reduce", ctypes.c_double), ("ms_contract", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("method_used", ctypes.c_int32),
                 ("split_top_keys", ctypes.c_int32), ("split_bottom_keys", ctypes.c_int32),
-                ("reserved_", ctypes.c_int32)]
+                ("max_state", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("reserved")}
