@@ -103,11 +103,13 @@ typedef struct {
     int64_t dfs_leaves;       /* complete middle paths evaluated               */
     int64_t dfs_edges;        /* depth-first tree edges taken (incl. leaves)   */
     int64_t transitions;      /* contraction: cut-to-cut state transitions     */
-    double ms_plan;           /* record_timing: bounds + state-space tables    */
+    double ms_plan;           /* record_timing: bounds + state-space tables
+                                 (contraction: bounds and key hulls)         */
     double ms_forward;        /*   forward frontier expansion                  */
     double ms_backward;       /*   backward frontier expansion                 */
     double ms_dfs;            /*   depth-first kernel                          */
-    double ms_reduce;         /*   final compensated reduction                 */
+    double ms_reduce;         /*   final compensated reduction (contraction
+                                   split across the batch: the join)         */
     double ms_contract;       /*   contraction kernel                          */
     double ms_total;          /*   whole call on the stream                    */
     int32_t method_used;      /* LOFP_METHOD_PATHSUM or LOFP_METHOD_CONTRACT   */

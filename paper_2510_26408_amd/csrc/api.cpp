@@ -163,7 +163,7 @@ lofp_status device_init(lofp_circuit_s &c, int n, hipStream_t s)
     }
     if (c.n_tab < n) {
         const int nt = std::max(n, 4);
-        const int stride = sector_offset(nt + 1);
+        const int stride = sector_offset(nt + 1) + 1;   // sectors N = 0..nt, then a zero slot
         HIPCHK(ensure(c.d_table, (size_t)std::max(c.G, 1) * stride * sizeof(double2)));
         HIPCHK(launch_build_tables(c.G, nt, c.d_theta.as<double>(), c.d_phi.as<double>(),
                                    c.d_table.as<double2>(), s));
@@ -452,6 +452,7 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
     a.fp32 = fp32;
     a.stat_transitions = ctr + 3;
     a.overflow = reinterpret_cast<int32_t *>(ctr + 4);
+    a.stats = st != nullptr;
     // state size: the S-side bound holds for every pattern; only when it is too
     // large for LDS ask the device for this batch's exact maximum
     std::vector<int16_t> slo, shi;
@@ -609,6 +610,7 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
         J.hi = (top ? thi : bhi) + (size_t)k * span;
         J.infeasible = c.d_kinf.as<int32_t>() + j;
         J.out = nullptr;
+        J.stats = st != nullptr;
     }
     HIPCHK(upload(c.d_jobs, jobs, s));
     unsigned long long *ctr = c.d_counters.as<unsigned long long>();
@@ -645,6 +647,7 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     tm.mark();
     HIPCHK(launch_contract_multi(nj, c.d_jobs.as<ContractJob>(), contract_job_lds_bytes(c.nvars, m, lds_states, true),
                                  lds_states, true, fp32 != 0, ctr + 3, reinterpret_cast<int32_t *>(ctr + 4), s, ov));
+    tm.mark();
     JoinArgs ja{};
     ja.B = B; ja.m = m; ja.n = n; ja.D = c.D;
     ja.lo = c.d_lo.as<int16_t>(); ja.hi = c.d_hi.as<int16_t>();
@@ -1149,8 +1152,10 @@ lofp_status lofp_amplitudes_device(lofp_circuit c, const int32_t *S, int32_t bat
         inner.s = s;
         rc = run_contract(*c, S, n, batch, T_dev, out_dev, 0, o.precision == LOFP_PREC_FP32, s, stats, inner);
         if (rc == LOFP_OK && stats && tm.on) {
+            // bounds (and key hulls), contraction kernel, join of split halves
             stats->ms_plan = inner.ms(0, 1);
             stats->ms_contract = inner.ms(1, 2);
+            stats->ms_reduce = inner.ms(2, 3);
         }
     } else {
         Timer inner;

@@ -43,48 +43,18 @@ __device__ __forceinline__ int qdiv(int a, int d, float inv)
 
 enum { RK_CONST = 0, RK_NEW = 1, RK_SUM = 2 };
 
-// Range of table entries a step can read: N = (cut above) - (cut below) runs
-// over the differences of the two references' value ranges, and the sectors
-// N are contiguous in the gate's table.
-__device__ __forceinline__ void tab_window(const ContractStep &st, const int *vlo, const int *vrad, const int *spre,
-                                           const int *tpre, int n, int &off, int &cnt)
-{
-    int lo[2], hi[2];
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const int kind = st.ref_kind[2 + k], arg = st.ref_arg[2 + k];
-        if (kind == CREF_NEW || kind == CREF_SUM) {
-            const int v = kind == CREF_NEW ? st.new_vars[arg] : st.sum_vars[arg];
-            lo[k] = vlo[v];
-            hi[k] = vlo[v] + vrad[v] - 1;
-        } else {
-            const int c = kind == CREF_ZERO ? 0 : kind == CREF_N ? n : kind == CREF_SPRE ? spre[arg] : tpre[arg];
-            lo[k] = c;
-            hi[k] = c;
-        }
-    }
-    const int Nlo = max(0, lo[1] - hi[0]), Nhi = min(n, hi[1] - lo[0]);
-    if (Nhi < Nlo) {
-        off = 0;
-        cnt = 0;
-    } else {
-        off = sector_offset(Nlo);
-        cnt = sector_offset(Nhi + 1) - off;
-    }
-}
-
 // Per-step layout, built once per job from the step program and the job's
 // intervals (all values uniform over the block).  New entry e decodes into
 // digits d_q = (e / nstr[q]) mod rad_q; the old entry it reads sits at
 // sum_q d_q * mstr[q] + i0 * sstr0 + i1 * sstr1 over the summed versions.
 struct StepDesc {
-    int new_size, n_new, gate, toff, tcnt;
+    int new_size, n_new, gate;
     int srad0, srad1, slo0, slo1, sstr0, sstr1;
     int rk[4], ra[4], nlo[4];
     int nstr[kMaxActive], mstr[kMaxActive];
     float ninv[kMaxActive];
 };
-constexpr int kDescChunk = 16;   // descriptors built per pass (plus the next one)
+constexpr int kDescChunk = 16;   // descriptors built per pass
 
 __device__ inline void build_desc(const ContractStep &st, const int *vlo, const int *vrad, const int *spre,
                                   const int *tpre, int n, StepDesc &d)
@@ -143,17 +113,17 @@ __device__ inline void build_desc(const ContractStep &st, const int *vlo, const 
             d.ra[k] = kind == CREF_ZERO ? 0 : kind == CREF_N ? n : kind == CREF_SPRE ? spre[arg] : tpre[arg];
         }
     }
-    tab_window(st, vlo, vrad, spre, tpre, n, d.toff, d.tcnt);
 }
 
 // Entries of a new state for one step: each entry gathers its summed
-// versions in a fixed order (i1 outer, i0 inner).  Loads carry no branch so
-// the visits of an entry overlap; an invalid visit reads a harmless slot and
-// adds nothing.
+// versions in a fixed order (i1 outer, i0 inner).  Loads and products carry
+// no branch, so the visits of an entry overlap: an invalid visit reads the
+// gate table's zero slot and adds an exact zero.  count: also count the
+// transitions with a nonzero source (statistics only).
 template <bool COUNT, bool F32, int BS>
 __device__ __forceinline__ void step_entries(const StepDesc &d, const double2 *__restrict__ bufA,
-                                             double2 *__restrict__ bufB, const double2 *__restrict__ W, int wbase,
-                                             unsigned long long &trans)
+                                             double2 *__restrict__ bufB, const double2 *__restrict__ W, int zslot,
+                                             bool count, unsigned long long &trans)
 {
     const int n_new = d.n_new, new_size = d.new_size;
     int nstr[kMaxActive], mstr[kMaxActive];
@@ -204,21 +174,17 @@ __device__ __forceinline__ void step_entries(const StepDesc &d, const double2 *_
                     val[k] = rk[k] == RK_SUM ? (ra[k] == 0 ? slo0 + i0 : slo1 + i1) : cv[k];
                 const int N = val[3] - val[2], x1 = val[0] - val[2], y1 = val[1] - val[2];
                 const bool ok = x1 >= 0 && y1 >= 0 && x1 <= N && y1 <= N;
-                const bool nz = prev.x != 0.0 || prev.y != 0.0;
+                if (count && ok && (prev.x != 0.0 || prev.y != 0.0)) ++trans;
                 if (COUNT) {
-                    if (ok && nz) { ++trans; acc.x += prev.x; }
+                    acc.x += ok ? prev.x : 0.0;
                 } else {
-                    const int wi = ok ? sector_offset(N) + x1 * (N + 1) + y1 - wbase : 0;
-                    const double2 w = W[wi];
-                    if (ok && nz) {
-                        ++trans;
-                        if (F32) {
-                            const float px = (float)prev.x, py = (float)prev.y, wx = (float)w.x, wy = (float)w.y;
-                            acc.x += (double)(px * wx - py * wy);
-                            acc.y += (double)(px * wy + py * wx);
-                        } else {
-                            acc = cfma(prev, w, acc);
-                        }
+                    const double2 w = W[ok ? sector_offset(N) + x1 * (N + 1) + y1 : zslot];
+                    if (F32) {
+                        const float px = (float)prev.x, py = (float)prev.y, wx = (float)w.x, wy = (float)w.y;
+                        acc.x += (double)(px * wx - py * wy);
+                        acc.y += (double)(px * wy + py * wx);
+                    } else {
+                        acc = cfma(prev, w, acc);
                     }
                 }
             }
@@ -228,12 +194,12 @@ __device__ __forceinline__ void step_entries(const StepDesc &d, const double2 *_
 }
 
 // LDS of one job: [vlo | vrad | spre | tpre | scratch int] [descriptors]
-// [staged tables (2)] [state buffers (2), when in LDS]
+// [state buffers (2), when in LDS]
 __host__ __device__ inline size_t job_lds_head(int nvars, int nc)
 {
     size_t off = (size_t)(2 * nvars + 2 * nc + 4) * sizeof(int);
     off = (off + 15) & ~(size_t)15;
-    off += (size_t)(kDescChunk + 1) * sizeof(StepDesc);
+    off += (size_t)kDescChunk * sizeof(StepDesc);
     off = (off + 15) & ~(size_t)15;
     return off;
 }
@@ -307,32 +273,19 @@ __device__ void contract_run(const ContractJob &g, unsigned char *smem, unsigned
     size_t off = (size_t)(2 * g.nvars + 2 * nc + 4) * sizeof(int);
     off = (off + 15) & ~(size_t)15;
     StepDesc *desc = reinterpret_cast<StepDesc *>(smem + off);
-    double2 *tabs = reinterpret_cast<double2 *>(smem + job_lds_head(g.nvars, nc));  // [2][kTabStage]
     double2 *bufA, *bufB;
-    if (LDS_STATE) bufA = tabs + 2 * kTabStage;
+    if (LDS_STATE) bufA = reinterpret_cast<double2 *>(smem + job_lds_head(g.nvars, nc));
     else bufA = g.ws;
     bufB = bufA + g.max_states;
-    // descriptors of the first steps
-    for (int k = threadIdx.x; k <= kDescChunk && k < g.nsteps; k += BS)
-        build_desc(g.steps[k], vlo, vrad, spre, tpre, g.n, desc[k]);
     if (threadIdx.x == 0) bufA[0] = make_double2(1.0, 0.0);
-    __syncthreads();
     unsigned long long trans = 0;
     int cur_size = 1;
-    // the transition table of the current step sits in LDS (entries
-    // [toff, toff + tcnt) of the gate's table) when it fits; the next step's
-    // part is fetched into registers while the current step runs
-    constexpr int TPT = kTabStage > 0 ? (kTabStage + BS - 1) / BS : 1;
-    if (!COUNT && kTabStage > 0 && g.nsteps > 0 && desc[0].tcnt <= kTabStage) {
-        const double2 *W0 = g.table + (int64_t)desc[0].gate * g.tab_stride + desc[0].toff;
-        for (int i = threadIdx.x; i < desc[0].tcnt; i += BS) tabs[i] = W0[i];
-        __syncthreads();
-    }
-
+    const bool count = g.stats != 0;
     for (int si = 0; si < g.nsteps; ++si) {
         const int slot = si % kDescChunk;
-        if (slot == 0 && si > 0) {
-            for (int k = threadIdx.x; k <= kDescChunk && si + k < g.nsteps; k += BS)
+        if (slot == 0) {
+            // layouts of the next steps, one thread per step
+            for (int k = threadIdx.x; k < kDescChunk && si + k < g.nsteps; k += BS)
                 build_desc(g.steps[si + k], vlo, vrad, spre, tpre, g.n, desc[k]);
             __syncthreads();
         }
@@ -342,35 +295,8 @@ __device__ void contract_run(const ContractJob &g, unsigned char *smem, unsigned
             if (threadIdx.x == 0) atomicOr(overflow, 1);
             return;
         }
-        const bool staged = kTabStage > 0 && d.tcnt <= kTabStage;
-        double2 nreg[TPT];
-#pragma unroll
-        for (int j = 0; j < TPT; ++j) nreg[j] = make_double2(0.0, 0.0);
-        int ncnt = kTabStage + 1;
-        if (!COUNT && kTabStage > 0 && si + 1 < g.nsteps) {
-            const StepDesc &dn = desc[slot + 1];
-            ncnt = dn.tcnt;
-            if (ncnt <= kTabStage) {
-                const double2 *Wn = g.table + (int64_t)dn.gate * g.tab_stride + dn.toff;
-#pragma unroll
-                for (int j = 0; j < TPT; ++j) {
-                    const int i = threadIdx.x + j * BS;
-                    if (i < ncnt) nreg[j] = Wn[i];
-                }
-            }
-        }
-        if (staged)
-            step_entries<COUNT, F32, BS>(d, bufA, bufB, tabs + (si & 1) * kTabStage, d.toff, trans);
-        else
-            step_entries<COUNT, F32, BS>(d, bufA, bufB, g.table + (int64_t)d.gate * g.tab_stride, 0, trans);
-        if (!COUNT && kTabStage > 0 && ncnt <= kTabStage) {
-            double2 *Wd = tabs + ((si + 1) & 1) * kTabStage;
-#pragma unroll
-            for (int j = 0; j < TPT; ++j) {
-                const int i = threadIdx.x + j * BS;
-                if (i < ncnt) Wd[i] = nreg[j];
-            }
-        }
+        step_entries<COUNT, F32, BS>(d, bufA, bufB, g.table + (int64_t)d.gate * g.tab_stride, g.tab_stride - 1,
+                                     count, trans);
         __syncthreads();
         double2 *t = bufA; bufA = bufB; bufB = t;
         cur_size = new_size;
@@ -429,6 +355,7 @@ __global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
     j.ws = LDS_STATE ? nullptr : g.ws + (int64_t)p * 2 * g.max_states;
     j.state_out = nullptr;
     j.state_cap = 0;
+    j.stats = g.stats;
     if (!contract_setup<BS>(j, smem)) return;
     contract_run<COUNT, F32, LDS_STATE, BS>(j, smem, g.stat_transitions, g.overflow);
 }
@@ -647,7 +574,6 @@ hipError_t launch_contract_sizes(const ContractArgs &a, int *max_size, hipStream
 size_t contract_job_lds_bytes(int nvars, int m, int max_states, bool state_in_lds)
 {
     size_t off = job_lds_head(nvars, m - 1);
-    off += (size_t)2 * kTabStage * sizeof(double2);
     return off + (state_in_lds ? (size_t)2 * max_states * sizeof(double2) : 0);
 }
 

@@ -166,11 +166,6 @@ hipError_t launch_reduce(int B, const int64_t *off, const double2 *vec, const do
 // a6: mode-axis contraction, one splitter per step.
 constexpr int kMaxActive = 16;         // live versions in a contraction state
 constexpr int kMaxContractVars = 1024; // free versions in a circuit
-// table entries of one contraction step staged in LDS (two buffers; 0: none)
-#ifndef LOFP_TAB_STAGE
-#define LOFP_TAB_STAGE 320
-#endif
-constexpr int kTabStage = LOFP_TAB_STAGE;
 // LDS of one key job of a split contraction (KiB): three jobs share a CU
 #ifndef LOFP_SPLIT_LDS_KB
 #define LOFP_SPLIT_LDS_KB 52
@@ -206,6 +201,7 @@ struct ContractArgs {
     int max_states;           // entries per state buffer
     double2 *ws;              // [B][2][max_states] when the state does not fit LDS
     int32_t *overflow;
+    int stats;                // count transitions into stat_transitions
 };
 hipError_t launch_contract(const ContractArgs &a, hipStream_t stream);
 
@@ -223,6 +219,7 @@ struct ContractJob {
     double2 *ws;                 // 2 * max_states entries, or nullptr (state in LDS)
     double2 *state_out;          // if set: write the final state here instead of summing it
     int state_cap;               // entries available at state_out
+    int stats;                   // count transitions into the statistics counter
 };
 // Per-launch overrides for key jobs of a split contraction (0 / nullptr: use
 // the job's own fields): one state size for every job, and per-job slices of

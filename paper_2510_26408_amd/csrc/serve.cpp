@@ -186,6 +186,7 @@ lofp_status launch_batch(Batch &b, int fp32)
         K.ws = in_lds ? nullptr : b.d_ws.as<double2>() + ws_off;
         K.state_out = nullptr;
         K.state_cap = 0;
+        K.stats = 0;
         ws_off += (size_t)2 * r.est;
     }
     HIPCHK(upload(b.d_bj, b.bj, s));

@@ -14,6 +14,10 @@ __global__ void k_build_tables(int G, int n_tab, int stride, const double *__res
     if (k >= (int64_t)G * stride) return;
     const int g = (int)(k / stride);
     const int idx = (int)(k - (int64_t)g * stride);
+    if (idx >= sector_offset(n_tab + 1)) {   // the zero slot that ends each gate's table
+        table[k] = make_double2(0.0, 0.0);
+        return;
+    }
     int N = 0;
     while (N < n_tab && sector_offset(N + 1) <= idx) ++N;
     const int rem = idx - sector_offset(N);
@@ -39,7 +43,7 @@ __global__ void k_build_tables(int G, int n_tab, int stride, const double *__res
 hipError_t launch_build_tables(int G, int n_tab, const double *theta, const double *phi,
                                double2 *table, hipStream_t stream)
 {
-    const int stride = sector_offset(n_tab + 1);
+    const int stride = sector_offset(n_tab + 1) + 1;
     const int64_t total = (int64_t)G * stride;
     if (total == 0) return hipSuccess;
     const int block = 256;
