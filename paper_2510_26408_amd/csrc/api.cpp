@@ -415,7 +415,8 @@ lofp_status ready_on_stream(lofp_circuit_s &c, hipStream_t s)
 }
 
 lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
-                               lofp_c128 *out_dev, int fp32, hipStream_t s, lofp_stats *st, Timer &tm, bool &used);
+                               lofp_c128 *out_dev, int fp32, hipStream_t s, lofp_stats *st, Timer &tm, bool &used,
+                               bool &bounds_done);
 
 lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
                          lofp_c128 *out_dev, int count_only, int fp32, hipStream_t s, lofp_stats *st, Timer &tm,
@@ -425,14 +426,17 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
     if (rc != LOFP_OK) return rc;
     rc = ready_on_stream(c, s);
     if (rc != LOFP_OK) return rc;
+    bool bounds_done = false;
     if (!count_only && allow_split && B >= 64) {
         bool used = false;
-        rc = run_contract_split(c, S, n, B, T_dev, out_dev, fp32, s, st, tm, used);
+        rc = run_contract_split(c, S, n, B, T_dev, out_dev, fp32, s, st, tm, used, bounds_done);
         if (rc != LOFP_OK || used) return rc;
     }
-    tm.mark();
-    rc = run_bounds(c, B, n, T_dev, s);
-    if (rc != LOFP_OK) return rc;
+    if (!bounds_done) {
+        tm.mark();
+        rc = run_bounds(c, B, n, T_dev, s);
+        if (rc != LOFP_OK) return rc;
+    }
     unsigned long long *ctr = c.d_counters.as<unsigned long long>();
     HIPCHK(hipMemsetAsync(ctr, 0, 8 * sizeof(unsigned long long), s));
     ContractArgs a{};
@@ -491,77 +495,19 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
 // top half of the contraction depends on T only through T's modes 0..rs+1, the
 // bottom half only through modes rs+1..m-1, so each distinct top (bottom) part
 // is contracted once and every pattern is finished by a dot product of its two
-// halves over the crossing versions.
-struct KeyMap {
-    std::vector<int32_t> of;                  // key of each pattern
-    std::vector<int32_t> off, members, rep;   // CSR of members per key; representative
-};
-
-static void group_rows(const std::vector<int32_t> &T, int B, int m, int n, int c0, int c1, KeyMap &km)
-{
-    // open addressing on a 64-bit hash of modes [c0, c1], full compare on hit
-    size_t cap = 1;
-    while (cap < (size_t)B * 2 + 2) cap <<= 1;
-    std::vector<int32_t> slot(cap, -1);
-    km.of.assign(B, 0);
-    km.rep.clear();
-    for (int p = 0; p < B; ++p) {
-        const int32_t *row = T.data() + (size_t)p * m;
-        uint64_t h = 1469598103934665603ULL;
-        for (int i = c0; i <= c1; ++i) { h ^= (uint64_t)(uint32_t)row[i]; h *= 1099511628211ULL; }
-        size_t j = (size_t)(h ^ (h >> 29)) & (cap - 1);
-        for (;;) {
-            if (slot[j] < 0) {
-                slot[j] = (int32_t)km.rep.size();
-                km.of[p] = slot[j];
-                km.rep.push_back(p);
-                break;
-            }
-            const int32_t *o = T.data() + (size_t)km.rep[slot[j]] * m;
-            bool eq = true;
-            for (int i = c0; i <= c1 && eq; ++i) eq = o[i] == row[i];
-            if (eq) { km.of[p] = slot[j]; break; }
-            j = (j + 1) & (cap - 1);
-        }
-    }
-    const int nk = (int)km.rep.size();
-    // representative: a member whose photon number is right (its prefix sums
-    // then give the key's fixed versions)
-    std::vector<char> good(nk, 0);
-    for (int p = 0; p < B; ++p) {
-        const int k = km.of[p];
-        if (good[k]) continue;
-        int tot = 0;
-        for (int i = 0; i < m; ++i) tot += T[(size_t)p * m + i];
-        if (tot == n) { km.rep[k] = p; good[k] = 1; }
-    }
-    km.off.assign(nk + 1, 0);
-    for (int p = 0; p < B; ++p) km.off[km.of[p] + 1]++;
-    for (int k = 0; k < nk; ++k) km.off[k + 1] += km.off[k];
-    km.members.assign(B, 0);
-    std::vector<int32_t> fill(km.off.begin(), km.off.end() - 1);
-    for (int p = 0; p < B; ++p) km.members[fill[km.of[p]]++] = p;
-}
-
+// halves over the crossing versions.  The grouping runs on the device; the
+// host reads back the two key counts (one synchronisation) to size the launch.
 lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
-                               lofp_c128 *out_dev, int fp32, hipStream_t s, lofp_stats *st, Timer &tm, bool &used)
+                               lofp_c128 *out_dev, int fp32, hipStream_t s, lofp_stats *st, Timer &tm, bool &used,
+                               bool &bounds_done)
 {
     used = false;
+    bounds_done = false;
     const int m = c.m, nc = c.nc, span = (c.D + 1) * nc;
     if (nc < 4 || c.D < 2) return LOFP_OK;
     const int rs = (nc - 1) / 2;
     SplitProgram *sp = get_split(c, rs);
     if (!sp->top.error.empty() || !sp->bot.error.empty()) return LOFP_OK;
-    // pattern keys (T to the host once)
-    std::vector<int32_t> hT((size_t)B * m);
-    HIPCHK(hipMemcpyAsync(hT.data(), T_dev, hT.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    KeyMap tk, bk;
-    group_rows(hT, B, m, n, 0, rs + 1, tk);
-    group_rows(hT, B, m, n, rs + 1, m - 1, bk);
-    const int ntop = (int)tk.rep.size(), nbot = (int)bk.rep.size();
-    if ((int64_t)(ntop + nbot) * 4 > (int64_t)B * 3) return LOFP_OK;   // little sharing: contract per pattern
-    used = true;
     if (!sp->on_device) {
         HIPCHK(upload(sp->d_top, sp->top.steps, s));
         HIPCHK(upload(sp->d_bot, sp->bot.steps, s));
@@ -569,91 +515,97 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
         HIPCHK(upload(sp->d_bot_live, sp->bot.live_out, s));
         sp->on_device = true;
     }
+    if (!c.h_pin) HIPCHK(hipHostMalloc((void **)&c.h_pin, 64, hipHostMallocDefault));
     tm.mark();
     lofp_status rc = run_bounds(c, B, n, T_dev, s);
     if (rc != LOFP_OK) return rc;
-    // key tables: [of_top | of_bot | off_top | mem_top | off_bot | mem_bot]
-    std::vector<int32_t> kt;
-    auto put = [&](const std::vector<int32_t> &v) { size_t o = kt.size(); kt.insert(kt.end(), v.begin(), v.end()); return o; };
-    const size_t o_of_t = put(tk.of), o_of_b = put(bk.of), o_off_t = put(tk.off), o_mem_t = put(tk.members);
-    const size_t o_off_b = put(bk.off), o_mem_b = put(bk.members);
-    HIPCHK(upload(c.d_keys, kt, s));
-    const int32_t *dk = c.d_keys.as<int32_t>();
-    HIPCHK(ensure(c.d_klohi, (size_t)2 * (ntop + nbot) * span * sizeof(int16_t)));
-    int16_t *tlo = c.d_klohi.as<int16_t>(), *thi = tlo + (size_t)ntop * span;
-    int16_t *blo = thi + (size_t)ntop * span, *bhi = blo + (size_t)nbot * span;
-    HIPCHK(launch_hull(ntop, dk + o_off_t, dk + o_mem_t, c.d_inf.as<int32_t>(), span, c.d_lo.as<int16_t>(),
-                       c.d_hi.as<int16_t>(), tlo, thi, s));
-    HIPCHK(launch_hull(nbot, dk + o_off_b, dk + o_mem_b, c.d_inf.as<int32_t>(), span, c.d_lo.as<int16_t>(),
-                       c.d_hi.as<int16_t>(), blo, bhi, s));
-    // one job per key: top keys first, then bottom keys
-    const int nj = ntop + nbot;
-    std::vector<ContractJob> jobs(nj);
-    HIPCHK(ensure(c.d_kinf, (size_t)nj * sizeof(int32_t)));
-    HIPCHK(hipMemsetAsync(c.d_kinf.p, 0, (size_t)nj * sizeof(int32_t), s));
-    for (int j = 0; j < nj; ++j) {
-        const bool top = j < ntop;
-        const int k = top ? j : j - ntop;
-        ContractJob &J = jobs[j];
-        std::memset(&J, 0, sizeof(J));
-        J.m = m; J.n = n; J.D = c.D; J.nvars = c.nvars;
-        J.nsteps = (int)(top ? sp->top.steps.size() : sp->bot.steps.size());
-        J.tab_stride = c.tab_stride;
-        J.fp32 = fp32;
-        J.steps = (top ? sp->d_top : sp->d_bot).as<ContractStep>();
-        J.var_cut = c.d_var_cut.as<int32_t>();
-        J.var_time = c.d_var_time.as<int32_t>();
-        J.table = c.d_table.as<double2>();
-        J.S = c.d_S.as<int32_t>();
-        J.T = T_dev + (size_t)(top ? tk.rep[k] : bk.rep[k]) * m;
-        J.lo = (top ? tlo : blo) + (size_t)k * span;
-        J.hi = (top ? thi : bhi) + (size_t)k * span;
-        J.infeasible = c.d_kinf.as<int32_t>() + j;
-        J.out = nullptr;
-        J.stats = st != nullptr;
-    }
-    HIPCHK(upload(c.d_jobs, jobs, s));
-    unsigned long long *ctr = c.d_counters.as<unsigned long long>();
-    HIPCHK(hipMemsetAsync(ctr, 0, 8 * sizeof(unsigned long long), s));
-    // capacity from the S-side intervals (they contain every key's hull), so
-    // no device round trip is needed; each job keeps its state in LDS when its
-    // own largest state fits the launch's LDS, else in its workspace slice
+    bounds_done = true;
+    // group the patterns by their two halves of T
+    int cap = 1;
+    while (cap < 2 * B) cap <<= 1;
+    HIPCHK(ensure(c.d_ktab, (size_t)2 * cap * sizeof(int)));
+    HIPCHK(ensure(c.d_kslot, (size_t)2 * B * sizeof(int)));
+    HIPCHK(ensure(c.d_kof, (size_t)2 * B * sizeof(int)));
+    HIPCHK(ensure(c.d_krep, (size_t)2 * B * sizeof(int)));
+    HIPCHK(ensure(c.d_kcnt, 2 * sizeof(int)));
+    HIPCHK(ensure(c.d_khull, (size_t)2 * 2 * B * span * sizeof(int)));
+    HIPCHK(ensure(c.d_klohi, (size_t)2 * 2 * B * span * sizeof(int16_t)));
+    HIPCHK(hipMemsetAsync(c.d_ktab.p, 0xFF, (size_t)2 * cap * sizeof(int), s));
+    KeyArgs ka{};
+    ka.B = B; ka.m = m; ka.n = n; ka.rs = rs; ka.cap = cap; ka.span = span;
+    ka.T = T_dev;
+    ka.lo = c.d_lo.as<int16_t>(); ka.hi = c.d_hi.as<int16_t>();
+    ka.infeasible = c.d_inf.as<int32_t>();
+    ka.table = c.d_ktab.as<int>(); ka.slot = c.d_kslot.as<int>();
+    ka.key_of = c.d_kof.as<int>(); ka.rep_of = c.d_krep.as<int>(); ka.count = c.d_kcnt.as<int>();
+    ka.hlo = c.d_khull.as<int>(); ka.hhi = ka.hlo + (size_t)2 * B * span;
+    ka.klo = c.d_klohi.as<int16_t>(); ka.khi = ka.klo + (size_t)2 * B * span;
+    HIPCHK(launch_keys(ka, s));
+    HIPCHK(hipMemcpyAsync(c.h_pin, c.d_kcnt.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const int ntop = c.h_pin[0], nbot = c.h_pin[1];
+    if ((int64_t)(ntop + nbot) * 4 > (int64_t)B * 3) return LOFP_OK;   // little sharing: contract per pattern
+    used = true;
+    // state capacity from the S-side intervals (they contain every key's
+    // hull); the device is asked only when that bound is too large
     std::vector<int16_t> slo, shi;
     s_only_bounds(c, S, n, slo, shi);
-    int64_t cap = std::max(steps_state_bound(c, sp->top.steps, slo, shi), steps_state_bound(c, sp->bot.steps, slo, shi));
+    const int64_t cap_s = std::max(steps_state_bound(c, sp->top.steps, slo, shi),
+                                   steps_state_bound(c, sp->bot.steps, slo, shi));
+    const int nj = ntop + nbot;
+    ContractJob tj{};
+    tj.m = m; tj.n = n; tj.D = c.D; tj.nvars = c.nvars; tj.tab_stride = c.tab_stride; tj.fp32 = fp32;
+    tj.var_cut = c.d_var_cut.as<int32_t>(); tj.var_time = c.d_var_time.as<int32_t>();
+    tj.table = c.d_table.as<double2>(); tj.S = c.d_S.as<int32_t>();
+    tj.stats = st != nullptr;
+    ContractJob bj = tj;
+    tj.nsteps = (int)sp->top.steps.size(); tj.steps = sp->d_top.as<ContractStep>();
+    bj.nsteps = (int)sp->bot.steps.size(); bj.steps = sp->d_bot.as<ContractStep>();
+    HIPCHK(ensure(c.d_jobs, (size_t)std::max(nj, 1) * sizeof(ContractJob)));
+    HIPCHK(ensure(c.d_kinf, (size_t)std::max(nj, 1) * sizeof(int32_t)));
+    HIPCHK(launch_key_jobs(ka, tj, bj, c.d_jobs.as<ContractJob>(), c.d_kinf.as<int32_t>(), s));
+    unsigned long long *ctr = c.d_counters.as<unsigned long long>();
+    HIPCHK(hipMemsetAsync(ctr, 0, 8 * sizeof(unsigned long long), s));
     int mx;
-    if (cap <= (1 << 20)) {
-        mx = (int)std::max<int64_t>(cap, 1);
+    if (cap_s <= (1 << 20)) {
+        mx = (int)std::max<int64_t>(cap_s, 1);
     } else {
         int *d_max = reinterpret_cast<int *>(ctr + 5);
         HIPCHK(launch_multi_sizes(nj, c.d_jobs.as<ContractJob>(), d_max, s));
-        HIPCHK(hipMemcpyAsync(&mx, d_max, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(c.h_pin + 2, d_max, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        mx = c.h_pin[2];
         if (mx > (1 << 22)) return fail(LOFP_ENOMEM, "contraction state exceeds 2^22 entries");
         mx = std::max(mx, 1);
     }
-    // LDS budget of a job (a few jobs per CU), of which what the step tables
-    // and interval arrays leave holds the two state buffers
+    // LDS budget of a job (a few jobs per CU), of which what the descriptors
+    // and interval arrays leave holds the two state buffers; a job whose own
+    // largest state does not fit keeps them in its workspace slice
     const size_t lds_job = std::min<size_t>(max_lds_per_block(), (size_t)LOFP_SPLIT_LDS_KB * 1024);
     const size_t lds_fixed = contract_job_lds_bytes(c.nvars, m, 0, true);
-    const int lds_states = (int)std::min<int64_t>(mx, (int64_t)((lds_job - lds_fixed) / (2 * sizeof(double2))));
+    const int64_t room = lds_job > lds_fixed ? (int64_t)((lds_job - lds_fixed) / (2 * sizeof(double2))) : 0;
+    const int lds_states = (int)std::min<int64_t>(mx, room);
     MultiOverride ov{mx, nullptr, nullptr, mx, lds_states};
     if (lds_states < mx) {
         HIPCHK(ensure(c.d_ws, (size_t)nj * 2 * mx * sizeof(double2)));
         ov.ws_base = c.d_ws.as<double2>();
     }
-    HIPCHK(ensure(c.d_kstate, (size_t)nj * mx * sizeof(double2)));
+    HIPCHK(ensure(c.d_kstate, (size_t)std::max(nj, 1) * mx * sizeof(double2)));
     ov.state_base = c.d_kstate.as<double2>();
     tm.mark();
-    HIPCHK(launch_contract_multi(nj, c.d_jobs.as<ContractJob>(), contract_job_lds_bytes(c.nvars, m, lds_states, true),
-                                 lds_states, true, fp32 != 0, ctr + 3, reinterpret_cast<int32_t *>(ctr + 4), s, ov));
+    const bool any_lds = lds_states > 0;
+    HIPCHK(launch_contract_multi(nj, c.d_jobs.as<ContractJob>(),
+                                 contract_job_lds_bytes(c.nvars, m, any_lds ? lds_states : 0, any_lds),
+                                 any_lds ? lds_states : mx, any_lds, fp32 != 0, ctr + 3,
+                                 reinterpret_cast<int32_t *>(ctr + 4), s, ov));
     tm.mark();
     JoinArgs ja{};
     ja.B = B; ja.m = m; ja.n = n; ja.D = c.D;
     ja.lo = c.d_lo.as<int16_t>(); ja.hi = c.d_hi.as<int16_t>();
     ja.infeasible = c.d_inf.as<int32_t>();
-    ja.top_of = dk + o_of_t; ja.bot_of = dk + o_of_b;
-    ja.tlo = tlo; ja.thi = thi; ja.blo = blo; ja.bhi = bhi;
+    ja.top_of = ka.key_of; ja.bot_of = ka.key_of + B;
+    ja.tlo = ka.klo; ja.thi = ka.khi;
+    ja.blo = ka.klo + (size_t)B * span; ja.bhi = ka.khi + (size_t)B * span;
     ja.nshared = (int)sp->top.live_out.size();
     ja.top_live = sp->d_top_live.as<int32_t>();
     ja.bot_live = sp->d_bot_live.as<int32_t>();
@@ -1035,9 +987,11 @@ lofp_status lofp_circuit_destroy(lofp_circuit c)
                       &c->d_cut_gates, &c->d_ver_at, &c->d_var_cut, &c->d_var_time, &c->d_steps, &c->d_S, &c->d_lo, &c->d_hi, &c->d_inf, &c->d_C, &c->d_E,
                       &c->d_count, &c->d_slot_stage, &c->d_off, &c->d_coff, &c->d_fa, &c->d_fb, &c->d_ba, &c->d_bb,
                       &c->d_levels, &c->d_tab_mid, &c->d_counters, &c->d_T, &c->d_out, &c->d_ws,
-                      &c->d_cfg, &c->d_rankb, &c->d_keys, &c->d_klohi, &c->d_kinf, &c->d_jobs, &c->d_kstate};
+                      &c->d_cfg, &c->d_rankb, &c->d_ktab, &c->d_kslot, &c->d_kof, &c->d_krep, &c->d_kcnt,
+                      &c->d_khull, &c->d_klohi, &c->d_kinf, &c->d_jobs, &c->d_kstate};
     if (c->ready_ev) (void)hipStreamSynchronize(c->ready_stream);
     for (DevBuf *b : bufs) release(*b);
+    if (c->h_pin) (void)hipHostFree(c->h_pin);
     if (c->ready_ev) (void)hipEventDestroy(c->ready_ev);
     delete c;
     return LOFP_OK;

@@ -420,42 +420,6 @@ hipError_t launch_multi_sizes(int count, const ContractJob *jobs, int *mx, hipSt
     return hipGetLastError();
 }
 
-// Hull of the member patterns' intervals, one thread per (key, entry).
-__global__ void k_hull(int nkeys, const int32_t *__restrict__ key_off, const int32_t *__restrict__ members,
-                       const int32_t *__restrict__ infeasible, int span, const int16_t *__restrict__ lo,
-                       const int16_t *__restrict__ hi, int16_t *__restrict__ klo, int16_t *__restrict__ khi)
-{
-    const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gi >= (int64_t)nkeys * span) return;
-    const int k = (int)(gi / span);
-    const int b = key_off[k], e = key_off[k + 1];
-    {
-        const int i = (int)(gi - (int64_t)k * span);
-        int l = 1 << 14, h = -1;
-        for (int q = b; q < e; ++q) {
-            const int p = members[q];
-            if (infeasible[p]) continue;
-            const int pl = lo[(int64_t)p * span + i], ph = hi[(int64_t)p * span + i];
-            l = pl < l ? pl : l;
-            h = ph > h ? ph : h;
-        }
-        if (h < 0) { l = 1; h = 0; }
-        klo[(int64_t)k * span + i] = (int16_t)l;
-        khi[(int64_t)k * span + i] = (int16_t)h;
-    }
-}
-
-hipError_t launch_hull(int nkeys, const int32_t *key_off, const int32_t *members, const int32_t *infeasible,
-                       int span, const int16_t *lo, const int16_t *hi, int16_t *klo, int16_t *khi,
-                       hipStream_t stream)
-{
-    if (nkeys == 0) return hipSuccess;
-    const int64_t total = (int64_t)nkeys * span;
-    hipLaunchKernelGGL(k_hull, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, nkeys, key_off, members,
-                       infeasible, span, lo, hi, klo, khi);
-    return hipGetLastError();
-}
-
 // Join of a split contraction, one wave per pattern: the sum over the
 // pattern's own box of crossing versions of TOP(versions) * BOT(versions),
 // each state addressed by value through its key's interval layout.

@@ -1,0 +1,193 @@
+// keys.hip -- grouping of a batch's patterns by the halves of T that the two
+// halves of a split contraction depend on (Sec. II.C contracted from both
+// ends): the top half of the circuit sees T only through modes 0..rs+1, the
+// bottom half only through modes rs+1..m-1.  Patterns with equal halves share
+// one contraction of that half.
+//
+// Per half: an open-addressing hash table over the sub-rows of T (equal rows
+// found by comparing values), numbered in order of each group's
+// representative -- the lowest-indexed member whose photon number is right,
+// else the lowest member -- so key numbers do not depend on thread timing.
+// The group's cut intervals are the hull of its feasible members' intervals.
+#include "lofp_device.h"
+
+namespace lofp {
+
+__device__ __forceinline__ uint64_t row_hash(const int32_t *row, int c0, int c1)
+{
+    uint64_t h = 1469598103934665603ULL;
+    for (int i = c0; i <= c1; ++i) {
+        h ^= (uint64_t)(uint32_t)row[i];
+        h *= 1099511628211ULL;
+    }
+    return h ^ (h >> 29);
+}
+
+__device__ __forceinline__ bool rows_equal(const int32_t *a, const int32_t *b, int c0, int c1)
+{
+    for (int i = c0; i <= c1; ++i)
+        if (a[i] != b[i]) return false;
+    return true;
+}
+
+// One thread per (pattern, half).  A slot holds p (good photon number) or
+// p + B (otherwise); the minimum over a group is its representative.
+__global__ void k_key_insert(KeyArgs a)
+{
+    const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= 2 * (int64_t)a.B) return;
+    const int half = (int)(gi / a.B), p = (int)(gi - (int64_t)half * a.B);
+    const int c0 = half ? a.rs + 1 : 0, c1 = half ? a.m - 1 : a.rs + 1;
+    const int32_t *row = a.T + (int64_t)p * a.m;
+    int tot = 0;
+    for (int i = 0; i < a.m; ++i) tot += row[i];
+    const int v = tot == a.n ? p : p + a.B;
+    int *tab = a.table + (int64_t)half * a.cap;
+    uint32_t j = (uint32_t)row_hash(row, c0, c1) & (uint32_t)(a.cap - 1);
+    for (int probe = 0; probe < a.cap; ++probe) {
+        int cur = tab[j];
+        if (cur < 0) {
+            cur = atomicCAS(&tab[j], -1, v);
+            if (cur < 0) { a.slot[gi] = (int)j; return; }
+        }
+        const int occ = cur >= a.B ? cur - a.B : cur;
+        if (rows_equal(a.T + (int64_t)occ * a.m, row, c0, c1)) {
+            atomicMin(&tab[j], v);
+            a.slot[gi] = (int)j;
+            return;
+        }
+        j = (j + 1) & (uint32_t)(a.cap - 1);
+    }
+    a.slot[gi] = -1;   // unreachable: the table has twice as many slots as rows
+}
+
+// Representative of the group in table slot sl (a pattern that found no
+// slot, which a table twice the batch size rules out, stands alone).
+__device__ __forceinline__ int rep_of_slot(const int *tab, int sl, int p, int B)
+{
+    if (sl < 0) return p;
+    const int v = tab[sl];
+    return v >= B ? v - B : v;
+}
+
+// One block per half: number the groups in order of their representatives
+// (a block-wide scan over the patterns), then give every pattern its key and
+// every key its representative, and reset the key's hull rows.
+__global__ __launch_bounds__(1024) void k_key_number(KeyArgs a)
+{
+    const int half = blockIdx.x;
+    const int *tab = a.table + (int64_t)half * a.cap;
+    const int *slot = a.slot + (int64_t)half * a.B;
+    int *key_of = a.key_of + (int64_t)half * a.B;
+    int *rep_of = a.rep_of + (int64_t)half * a.B;
+    __shared__ int wsum[16];
+    __shared__ int base_s;
+    if (threadIdx.x == 0) base_s = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int c = 0; c < a.B; c += blockDim.x) {
+        const int p = c + threadIdx.x;
+        int is_rep = 0;
+        if (p < a.B) is_rep = rep_of_slot(tab, slot[p], p, a.B) == p;
+        // exclusive scan of is_rep over the block
+        int x = is_rep;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wid] = x;
+        __syncthreads();
+        int before = base_s;
+        for (int w = 0; w < wid; ++w) before += wsum[w];
+        if (is_rep) key_of[p] = before + x - 1;   // the representative's key number
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int t = 0;
+            for (int w = 0; w < nw; ++w) t += wsum[w];
+            base_s += t;
+        }
+        __syncthreads();
+    }
+    const int nkeys = base_s;
+    if (threadIdx.x == 0) a.count[half] = nkeys;
+    __syncthreads();
+    // representatives hold their key numbers; members copy theirs
+    for (int p = threadIdx.x; p < a.B; p += blockDim.x)
+        if (rep_of_slot(tab, slot[p], p, a.B) == p) rep_of[key_of[p]] = p;
+    __syncthreads();
+    for (int p = threadIdx.x; p < a.B; p += blockDim.x) {
+        const int r = rep_of_slot(tab, slot[p], p, a.B);
+        if (r != p) key_of[p] = key_of[r];
+    }
+    int *hlo = a.hlo + (int64_t)half * a.B * a.span, *hhi = a.hhi + (int64_t)half * a.B * a.span;
+    for (int64_t i = threadIdx.x; i < (int64_t)nkeys * a.span; i += blockDim.x) {
+        hlo[i] = 1 << 14;
+        hhi[i] = -1;
+    }
+}
+
+// Hull of the feasible members' intervals, one thread per (pattern, half, entry).
+__global__ void k_key_hull(KeyArgs a)
+{
+    const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)a.B * a.span;
+    if (gi >= 2 * per) return;
+    const int half = (int)(gi / per);
+    const int64_t r = gi - half * per;
+    const int p = (int)(r / a.span), i = (int)(r - (int64_t)p * a.span);
+    if (a.infeasible[p]) return;
+    const int k = a.key_of[(int64_t)half * a.B + p];
+    const int64_t o = ((int64_t)half * a.B + k) * a.span + i;
+    atomicMin(&a.hlo[o], (int)a.lo[(int64_t)p * a.span + i]);
+    atomicMax(&a.hhi[o], (int)a.hi[(int64_t)p * a.span + i]);
+}
+
+// One thread per key: its 16-bit interval rows and its contraction job (top
+// keys first, then bottom keys).
+__global__ void k_key_jobs(KeyArgs a, ContractJob top, ContractJob bot, ContractJob *jobs, int32_t *kinf)
+{
+    const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= 2 * (int64_t)a.B) return;
+    const int half = (int)(gi / a.B), k = (int)(gi - (int64_t)half * a.B);
+    const int ntop = a.count[0];
+    if (k >= a.count[half]) return;
+    const int64_t row = ((int64_t)half * a.B + k) * a.span;
+    for (int i = 0; i < a.span; ++i) {
+        int l = a.hlo[row + i], h = a.hhi[row + i];
+        if (h < 0) { l = 1; h = 0; }   // no feasible member: empty interval
+        a.klo[row + i] = (int16_t)l;
+        a.khi[row + i] = (int16_t)h;
+    }
+    const int j = half ? ntop + k : k;
+    ContractJob J = half ? bot : top;
+    J.T = a.T + (int64_t)a.rep_of[(int64_t)half * a.B + k] * a.m;
+    J.lo = a.klo + row;
+    J.hi = a.khi + row;
+    J.infeasible = kinf + j;
+    kinf[j] = 0;
+    J.out = nullptr;
+    jobs[j] = J;
+}
+
+hipError_t launch_keys(const KeyArgs &a, hipStream_t stream)
+{
+    if (a.B == 0) return hipSuccess;
+    const int64_t n2 = 2 * (int64_t)a.B;
+    hipLaunchKernelGGL(k_key_insert, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_key_number, dim3(2), dim3(1024), 0, stream, a);
+    const int64_t nh = n2 * a.span;
+    hipLaunchKernelGGL(k_key_hull, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_key_jobs(const KeyArgs &a, const ContractJob &top, const ContractJob &bot, ContractJob *jobs,
+                           int32_t *kinf, hipStream_t stream)
+{
+    const int64_t n2 = 2 * (int64_t)a.B;
+    hipLaunchKernelGGL(k_key_jobs, dim3((unsigned)((n2 + 127) / 128)), dim3(128), 0, stream, a, top, bot, jobs,
+                       kinf);
+    return hipGetLastError();
+}
+
+}  // namespace lofp

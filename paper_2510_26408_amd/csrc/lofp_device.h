@@ -250,9 +250,21 @@ hipError_t launch_contract_multi(int count, const ContractJob *jobs, size_t lds_
 hipError_t launch_multi_sizes(int count, const ContractJob *jobs, int *mx, hipStream_t stream);
 
 // Split contraction: per key, the hull of its member patterns' intervals.
-hipError_t launch_hull(int nkeys, const int32_t *key_off, const int32_t *members, const int32_t *infeasible,
-                       int span, const int16_t *lo, const int16_t *hi, int16_t *klo, int16_t *khi,
-                       hipStream_t stream);
+// Grouping of a batch by the halves of T (split contraction), per half h:
+// table [2][cap], slot/key_of/rep_of [2][B], count [2], hulls [2][B][span].
+struct KeyArgs {
+    int B, m, n, rs, cap, span;
+    const int32_t *T;              // [B][m]
+    const int16_t *lo, *hi;        // per pattern [B][span]
+    const int32_t *infeasible;     // [B]
+    int *table, *slot, *key_of, *rep_of, *count;
+    int *hlo, *hhi;                // int32 hull accumulators
+    int16_t *klo, *khi;            // per key intervals (top keys at 0, bottom at B)
+};
+hipError_t launch_keys(const KeyArgs &a, hipStream_t stream);
+// One contraction job per key from the two half templates; jobs[0, ntop) top.
+hipError_t launch_key_jobs(const KeyArgs &a, const ContractJob &top, const ContractJob &bot, ContractJob *jobs,
+                           int32_t *kinf, hipStream_t stream);
 struct JoinArgs {
     int B, m, n, D;
     const int16_t *lo, *hi;          // per pattern [B][span]
