@@ -597,7 +597,7 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     HIPCHK(launch_contract_multi(nj, c.d_jobs.as<ContractJob>(),
                                  contract_job_lds_bytes(c.nvars, m, any_lds ? lds_states : 0, any_lds),
                                  any_lds ? lds_states : mx, any_lds, fp32 != 0, ctr + 3,
-                                 reinterpret_cast<int32_t *>(ctr + 4), s, ov));
+                                 reinterpret_cast<int32_t *>(ctr + 4), s, ov, st != nullptr));
     tm.mark();
     JoinArgs ja{};
     ja.B = B; ja.m = m; ja.n = n; ja.D = c.D;

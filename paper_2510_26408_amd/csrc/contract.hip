@@ -43,6 +43,10 @@ __device__ __forceinline__ int qdiv(int a, int d, float inv)
 
 enum { RK_CONST = 0, RK_NEW = 1, RK_SUM = 2 };
 
+// a table in global memory, read as pairs of doubles (lets the compiler use
+// global loads with a 32-bit offset rather than flat ones)
+typedef const double __attribute__((address_space(1))) gdouble;
+
 // Per-step layout, built once per job from the step program and the job's
 // intervals (all values uniform over the block).  New entry e decodes into
 // digits d_q = (e / nstr[q]) mod rad_q; the old entry it reads sits at
@@ -120,10 +124,10 @@ __device__ inline void build_desc(const ContractStep &st, const int *vlo, const 
 // no branch, so the visits of an entry overlap: an invalid visit reads the
 // gate table's zero slot and adds an exact zero.  count: also count the
 // transitions with a nonzero source (statistics only).
-template <bool COUNT, bool F32, int BS>
+template <bool COUNT, bool F32, int BS, bool STATS>
 __device__ __forceinline__ void step_entries(const StepDesc &d, const double2 *__restrict__ bufA,
-                                             double2 *__restrict__ bufB, const double2 *__restrict__ W, int zslot,
-                                             bool count, unsigned long long &trans)
+                                             double2 *__restrict__ bufB, const gdouble *__restrict__ W,
+                                             unsigned zslot, unsigned long long &trans)
 {
     const int n_new = d.n_new, new_size = d.new_size;
     int nstr[kMaxActive], mstr[kMaxActive];
@@ -163,6 +167,23 @@ __device__ __forceinline__ void step_entries(const StepDesc &d, const double2 *_
             cv[k] = rk[k] == RK_NEW ? (a == 0 ? nv0 : a == 1 ? nv1 : a == 2 ? nv2 : nv3) : a;
         }
         double2 acc = make_double2(0.0, 0.0);
+        // one transition: acc += prev * W[wi] (an invalid one reads the zero slot)
+        auto visit = [&](const double2 prev, bool ok, unsigned wi) {
+            if (STATS && ok && (prev.x != 0.0 || prev.y != 0.0)) ++trans;
+            if (COUNT) {
+                acc.x += ok ? prev.x : 0.0;
+            } else {
+                const unsigned wo = 2u * (ok ? wi : zslot);
+                const double2 w = make_double2(W[wo], W[wo + 1]);
+                if (F32) {
+                    const float px = (float)prev.x, py = (float)prev.y, wx = (float)w.x, wy = (float)w.y;
+                    acc.x += (double)(px * wx - py * wy);
+                    acc.y += (double)(px * wy + py * wx);
+                } else {
+                    acc = cfma(prev, w, acc);
+                }
+            }
+        };
         for (int i1 = 0; i1 < srad1; ++i1) {
             const int ob = base_old + i1 * sstr1;
 #pragma unroll 2
@@ -174,19 +195,7 @@ __device__ __forceinline__ void step_entries(const StepDesc &d, const double2 *_
                     val[k] = rk[k] == RK_SUM ? (ra[k] == 0 ? slo0 + i0 : slo1 + i1) : cv[k];
                 const int N = val[3] - val[2], x1 = val[0] - val[2], y1 = val[1] - val[2];
                 const bool ok = x1 >= 0 && y1 >= 0 && x1 <= N && y1 <= N;
-                if (count && ok && (prev.x != 0.0 || prev.y != 0.0)) ++trans;
-                if (COUNT) {
-                    acc.x += ok ? prev.x : 0.0;
-                } else {
-                    const double2 w = W[ok ? sector_offset(N) + x1 * (N + 1) + y1 : zslot];
-                    if (F32) {
-                        const float px = (float)prev.x, py = (float)prev.y, wx = (float)w.x, wy = (float)w.y;
-                        acc.x += (double)(px * wx - py * wy);
-                        acc.y += (double)(px * wy + py * wx);
-                    } else {
-                        acc = cfma(prev, w, acc);
-                    }
-                }
+                visit(prev, ok, (unsigned)(sector_offset(N) + x1 * (N + 1) + y1));
             }
         }
         bufB[e] = acc;
@@ -260,8 +269,9 @@ __device__ int job_max_state(const ContractJob &g, unsigned char *smem)
 
 // The contraction of one pattern by one block (after contract_setup).  F32:
 // each transition product prev * W is formed in FP32 (the path-product
-// precision of the FP32 form); states and sums stay FP64.
-template <bool COUNT, bool F32, bool LDS_STATE, int BS>
+// precision of the FP32 form); states and sums stay FP64.  STATS: count the
+// transitions with a nonzero source into *stat_transitions.
+template <bool COUNT, bool F32, bool LDS_STATE, int BS, bool STATS>
 __device__ void contract_run(const ContractJob &g, unsigned char *smem, unsigned long long *stat_transitions,
                              int32_t *overflow)
 {
@@ -280,7 +290,6 @@ __device__ void contract_run(const ContractJob &g, unsigned char *smem, unsigned
     if (threadIdx.x == 0) bufA[0] = make_double2(1.0, 0.0);
     unsigned long long trans = 0;
     int cur_size = 1;
-    const bool count = g.stats != 0;
     for (int si = 0; si < g.nsteps; ++si) {
         const int slot = si % kDescChunk;
         if (slot == 0) {
@@ -295,8 +304,8 @@ __device__ void contract_run(const ContractJob &g, unsigned char *smem, unsigned
             if (threadIdx.x == 0) atomicOr(overflow, 1);
             return;
         }
-        step_entries<COUNT, F32, BS>(d, bufA, bufB, g.table + (int64_t)d.gate * g.tab_stride, g.tab_stride - 1,
-                                     count, trans);
+        step_entries<COUNT, F32, BS, STATS>(d, bufA, bufB, (const gdouble *)(g.table + (int64_t)d.gate * g.tab_stride),
+                                            (unsigned)(g.tab_stride - 1), trans);
         __syncthreads();
         double2 *t = bufA; bufA = bufB; bufB = t;
         cur_size = new_size;
@@ -308,7 +317,7 @@ __device__ void contract_run(const ContractJob &g, unsigned char *smem, unsigned
             return;
         }
         for (int i = threadIdx.x; i < cur_size; i += BS) g.state_out[i] = bufA[i];
-        atomicAdd(stat_transitions, trans);
+        if (STATS) atomicAdd(stat_transitions, trans);
         return;
     }
     // amplitude = sum of the final state (a single entry once every version is summed)
@@ -334,11 +343,11 @@ __device__ void contract_run(const ContractJob &g, unsigned char *smem, unsigned
         for (int w = 1; w < BS / 64; ++w) { csum_merge(a, part[0][w]); csum_merge(b, part[1][w]); }
         *g.out = make_double2(a.s + a.c, b.s + b.c);
     }
-    atomicAdd(stat_transitions, trans);
+    if (STATS) atomicAdd(stat_transitions, trans);
 }
 
 // Single circuit, one block per pattern.
-template <bool COUNT, bool F32, bool LDS_STATE, int BS>
+template <bool COUNT, bool F32, bool LDS_STATE, int BS, bool STATS>
 __global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -357,11 +366,11 @@ __global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
     j.state_cap = 0;
     j.stats = g.stats;
     if (!contract_setup<BS>(j, smem)) return;
-    contract_run<COUNT, F32, LDS_STATE, BS>(j, smem, g.stat_transitions, g.overflow);
+    contract_run<COUNT, F32, LDS_STATE, BS, STATS>(j, smem, g.stat_transitions, g.overflow);
 }
 
 // Many circuits, one block per job.
-template <bool F32, bool LDS_STATE, int BS>
+template <bool F32, bool LDS_STATE, int BS, bool STATS>
 __global__ __launch_bounds__(BS) void k_contract_multi(const ContractJob *__restrict__ jobs,
                                                        unsigned long long *stat_transitions, int32_t *overflow,
                                                        MultiOverride ov)
@@ -381,13 +390,13 @@ __global__ __launch_bounds__(BS) void k_contract_multi(const ContractJob *__rest
         // per-job choice: the state in LDS when this job's largest state fits
         if (job_max_state<BS>(j, smem) <= ov.lds_states) {
             j.max_states = ov.lds_states;
-            contract_run<false, F32, true, BS>(j, smem, stat_transitions, overflow);
+            contract_run<false, F32, true, BS, STATS>(j, smem, stat_transitions, overflow);
         } else {
-            contract_run<false, F32, false, BS>(j, smem, stat_transitions, overflow);
+            contract_run<false, F32, false, BS, STATS>(j, smem, stat_transitions, overflow);
         }
         return;
     }
-    contract_run<false, F32, LDS_STATE, BS>(j, smem, stat_transitions, overflow);
+    contract_run<false, F32, LDS_STATE, BS, STATS>(j, smem, stat_transitions, overflow);
 }
 
 // Largest state of each job's program under its intervals.
@@ -558,12 +567,14 @@ size_t contract_lds_bytes(const ContractArgs &a, bool state_in_lds)
 template <bool COUNT, bool F32, bool LDS_STATE>
 static void launch_contract_t(const ContractArgs &a, size_t dyn, hipStream_t stream)
 {
-    // small states: one wave per pattern keeps more patterns resident;
-    // large states: four waves share the pattern's LDS state
-    if (a.max_states <= 512)
-        hipLaunchKernelGGL((k_contract<COUNT, F32, LDS_STATE, 64>), dim3(a.B), dim3(64), dyn, stream, a);
-    else
-        hipLaunchKernelGGL((k_contract<COUNT, F32, LDS_STATE, 256>), dim3(a.B), dim3(256), dyn, stream, a);
+    const bool wide = contract_block_size(a.max_states) != 64;
+    if (a.stats) {
+        if (wide) hipLaunchKernelGGL((k_contract<COUNT, F32, LDS_STATE, 256, true>), dim3(a.B), dim3(256), dyn, stream, a);
+        else hipLaunchKernelGGL((k_contract<COUNT, F32, LDS_STATE, 64, true>), dim3(a.B), dim3(64), dyn, stream, a);
+    } else {
+        if (wide) hipLaunchKernelGGL((k_contract<COUNT, F32, LDS_STATE, 256, false>), dim3(a.B), dim3(256), dyn, stream, a);
+        else hipLaunchKernelGGL((k_contract<COUNT, F32, LDS_STATE, 64, false>), dim3(a.B), dim3(64), dyn, stream, a);
+    }
 }
 
 hipError_t launch_contract(const ContractArgs &a, hipStream_t stream)
@@ -587,31 +598,32 @@ hipError_t launch_contract(const ContractArgs &a, hipStream_t stream)
 
 template <bool F32, bool LDS_STATE>
 static void launch_multi_t(int count, const ContractJob *jobs, size_t dyn, int max_states,
-                           unsigned long long *st, int32_t *ov, MultiOverride o, hipStream_t stream)
+                           unsigned long long *st, int32_t *ov, MultiOverride o, bool stats, hipStream_t stream)
 {
-    // few large jobs (split halves) get wide blocks so a step's entries spread
-    // over more lanes; many small jobs get one wave each
-    if (max_states <= 512)
-        hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 64>), dim3(count), dim3(64), dyn, stream, jobs, st, ov, o);
-    else if (count >= 2048 || max_states <= 2048)
-        hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 256>), dim3(count), dim3(256), dyn, stream, jobs, st, ov, o);
-    else
-        hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 512>), dim3(count), dim3(512), dyn, stream, jobs, st, ov, o);
+    const bool wide = contract_block_size(max_states) != 64;
+    const dim3 g(count);
+    if (stats) {
+        if (wide) hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 256, true>), g, dim3(256), dyn, stream, jobs, st, ov, o);
+        else hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 64, true>), g, dim3(64), dyn, stream, jobs, st, ov, o);
+    } else {
+        if (wide) hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 256, false>), g, dim3(256), dyn, stream, jobs, st, ov, o);
+        else hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 64, false>), g, dim3(64), dyn, stream, jobs, st, ov, o);
+    }
 }
 
 hipError_t launch_contract_multi(int count, const ContractJob *jobs, size_t lds_bytes, int max_states,
                                  bool state_in_lds, bool fp32, unsigned long long *stat_transitions,
-                                 int32_t *overflow, hipStream_t stream, MultiOverride o)
+                                 int32_t *overflow, hipStream_t stream, MultiOverride o, bool stats)
 {
     if (count == 0) return hipSuccess;
     if (lds_bytes > max_lds_per_block()) return hipErrorInvalidValue;
     unsigned long long *st = stat_transitions;
     if (fp32) {
-        if (state_in_lds) launch_multi_t<true, true>(count, jobs, lds_bytes, max_states, st, overflow, o, stream);
-        else launch_multi_t<true, false>(count, jobs, lds_bytes, max_states, st, overflow, o, stream);
+        if (state_in_lds) launch_multi_t<true, true>(count, jobs, lds_bytes, max_states, st, overflow, o, stats, stream);
+        else launch_multi_t<true, false>(count, jobs, lds_bytes, max_states, st, overflow, o, stats, stream);
     } else {
-        if (state_in_lds) launch_multi_t<false, true>(count, jobs, lds_bytes, max_states, st, overflow, o, stream);
-        else launch_multi_t<false, false>(count, jobs, lds_bytes, max_states, st, overflow, o, stream);
+        if (state_in_lds) launch_multi_t<false, true>(count, jobs, lds_bytes, max_states, st, overflow, o, stats, stream);
+        else launch_multi_t<false, false>(count, jobs, lds_bytes, max_states, st, overflow, o, stats, stream);
     }
     return hipGetLastError();
 }

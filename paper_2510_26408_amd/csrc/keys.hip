@@ -143,23 +143,25 @@ __global__ void k_key_hull(KeyArgs a)
     atomicMax(&a.hhi[o], (int)a.hi[(int64_t)p * a.span + i]);
 }
 
-// One thread per key: its 16-bit interval rows and its contraction job (top
-// keys first, then bottom keys).
+// One thread per (key, interval entry): the key's 16-bit interval rows; the
+// thread of entry 0 also writes the key's contraction job (top keys first,
+// then bottom keys).
 __global__ void k_key_jobs(KeyArgs a, ContractJob top, ContractJob bot, ContractJob *jobs, int32_t *kinf)
 {
     const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gi >= 2 * (int64_t)a.B) return;
-    const int half = (int)(gi / a.B), k = (int)(gi - (int64_t)half * a.B);
-    const int ntop = a.count[0];
+    const int64_t per = (int64_t)a.B * a.span;
+    if (gi >= 2 * per) return;
+    const int half = (int)(gi / per);
+    const int64_t r = gi - half * per;
+    const int k = (int)(r / a.span), i = (int)(r - (int64_t)k * a.span);
     if (k >= a.count[half]) return;
     const int64_t row = ((int64_t)half * a.B + k) * a.span;
-    for (int i = 0; i < a.span; ++i) {
-        int l = a.hlo[row + i], h = a.hhi[row + i];
-        if (h < 0) { l = 1; h = 0; }   // no feasible member: empty interval
-        a.klo[row + i] = (int16_t)l;
-        a.khi[row + i] = (int16_t)h;
-    }
-    const int j = half ? ntop + k : k;
+    int l = a.hlo[row + i], h = a.hhi[row + i];
+    if (h < 0) { l = 1; h = 0; }   // no feasible member: empty interval
+    a.klo[row + i] = (int16_t)l;
+    a.khi[row + i] = (int16_t)h;
+    if (i != 0) return;
+    const int j = half ? a.count[0] + k : k;
     ContractJob J = half ? bot : top;
     J.T = a.T + (int64_t)a.rep_of[(int64_t)half * a.B + k] * a.m;
     J.lo = a.klo + row;
@@ -184,8 +186,8 @@ hipError_t launch_keys(const KeyArgs &a, hipStream_t stream)
 hipError_t launch_key_jobs(const KeyArgs &a, const ContractJob &top, const ContractJob &bot, ContractJob *jobs,
                            int32_t *kinf, hipStream_t stream)
 {
-    const int64_t n2 = 2 * (int64_t)a.B;
-    hipLaunchKernelGGL(k_key_jobs, dim3((unsigned)((n2 + 127) / 128)), dim3(128), 0, stream, a, top, bot, jobs,
+    const int64_t n2 = 2 * (int64_t)a.B * a.span;
+    hipLaunchKernelGGL(k_key_jobs, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, stream, a, top, bot, jobs,
                        kinf);
     return hipGetLastError();
 }

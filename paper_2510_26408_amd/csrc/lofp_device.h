@@ -245,7 +245,7 @@ hipError_t launch_bounds_multi(int count, const BoundsJob *jobs, hipStream_t str
 hipError_t launch_contract_multi(int count, const ContractJob *jobs, size_t lds_bytes, int max_states,
                                  bool state_in_lds, bool fp32, unsigned long long *stat_transitions,
                                  int32_t *overflow, hipStream_t stream,
-                                 MultiOverride ov = MultiOverride{0, nullptr, nullptr, 0, 0});
+                                 MultiOverride ov = MultiOverride{0, nullptr, nullptr, 0, 0}, bool stats = false);
 // Largest state over the jobs (one thread per job), atomically maxed into *mx.
 hipError_t launch_multi_sizes(int count, const ContractJob *jobs, int *mx, hipStream_t stream);
 
@@ -284,6 +284,9 @@ hipError_t launch_join(const JoinArgs &a, hipStream_t stream);
 size_t contract_job_lds_bytes(int nvars, int m, int max_states, bool state_in_lds);
 // LDS a block may allocate on the current device (64 KiB if the query fails)
 size_t max_lds_per_block();
+// Threads per contraction block for a largest state of max_states entries:
+// one wave for small states (more patterns resident), four for large.
+inline int contract_block_size(int max_states) { return max_states <= 512 ? 64 : 256; }
 hipError_t launch_contract_sizes(const ContractArgs &a, int *max_size, hipStream_t stream);
 // dynamic LDS of the contraction kernel (state buffers included when in LDS)
 size_t contract_lds_bytes(const ContractArgs &a, bool state_in_lds);
