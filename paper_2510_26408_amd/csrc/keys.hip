@@ -13,52 +13,61 @@
 
 namespace lofp {
 
-__device__ __forceinline__ uint64_t row_hash(const int32_t *row, int c0, int c1)
+// splitmix64 finalizer (Steele, Lea and Flood), used per row entry
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
 {
-    uint64_t h = 1469598103934665603ULL;
-    for (int i = c0; i <= c1; ++i) {
-        h ^= (uint64_t)(uint32_t)row[i];
-        h *= 1099511628211ULL;
-    }
-    return h ^ (h >> 29);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
 }
 
-__device__ __forceinline__ bool rows_equal(const int32_t *a, const int32_t *b, int c0, int c1)
+// One wave per (pattern, half); lane i holds row entry i (m <= 32).  The
+// hash is the XOR of per-entry mixes (order-free, so the same on every run);
+// equal hashes are confirmed by comparing the rows lane by lane.  A slot
+// holds p (right photon number) or p + B (otherwise); the minimum over a
+// group is its representative.
+__global__ __launch_bounds__(256) void k_key_insert(KeyArgs a)
 {
-    for (int i = c0; i <= c1; ++i)
-        if (a[i] != b[i]) return false;
-    return true;
-}
-
-// One thread per (pattern, half).  A slot holds p (good photon number) or
-// p + B (otherwise); the minimum over a group is its representative.
-__global__ void k_key_insert(KeyArgs a)
-{
-    const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gi >= 2 * (int64_t)a.B) return;
-    const int half = (int)(gi / a.B), p = (int)(gi - (int64_t)half * a.B);
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (gw >= 2 * (int64_t)a.B) return;
+    const int half = (int)(gw / a.B), p = (int)(gw - (int64_t)half * a.B);
     const int c0 = half ? a.rs + 1 : 0, c1 = half ? a.m - 1 : a.rs + 1;
-    const int32_t *row = a.T + (int64_t)p * a.m;
-    int tot = 0;
-    for (int i = 0; i < a.m; ++i) tot += row[i];
+    const bool mine = lane >= c0 && lane <= c1;
+    const int x = lane < a.m ? a.T[(int64_t)p * a.m + lane] : 0;
+    int tot = x;
+    uint64_t h = mine ? mix64((uint64_t)(uint32_t)x + 0x9E3779B97F4A7C15ULL * (uint64_t)(lane + 1)) : 0;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        tot += __shfl_xor(tot, o, 64);
+        h ^= __shfl_xor(h, o, 64);
+    }
     const int v = tot == a.n ? p : p + a.B;
     int *tab = a.table + (int64_t)half * a.cap;
-    uint32_t j = (uint32_t)row_hash(row, c0, c1) & (uint32_t)(a.cap - 1);
+    uint32_t j = (uint32_t)(h ^ (h >> 32)) & (uint32_t)(a.cap - 1);
     for (int probe = 0; probe < a.cap; ++probe) {
         int cur = tab[j];
         if (cur < 0) {
-            cur = atomicCAS(&tab[j], -1, v);
-            if (cur < 0) { a.slot[gi] = (int)j; return; }
+            int won = 0;
+            if (lane == 0) won = atomicCAS(&tab[j], -1, v);
+            cur = __shfl(won, 0, 64);
+            if (cur < 0) {
+                if (lane == 0) a.slot[gw] = (int)j;
+                return;
+            }
         }
         const int occ = cur >= a.B ? cur - a.B : cur;
-        if (rows_equal(a.T + (int64_t)occ * a.m, row, c0, c1)) {
-            atomicMin(&tab[j], v);
-            a.slot[gi] = (int)j;
+        const int y = mine ? a.T[(int64_t)occ * a.m + lane] : x;
+        if (__all(y == x)) {
+            if (lane == 0) {
+                atomicMin(&tab[j], v);
+                a.slot[gw] = (int)j;
+            }
             return;
         }
         j = (j + 1) & (uint32_t)(a.cap - 1);
     }
-    a.slot[gi] = -1;   // unreachable: the table has twice as many slots as rows
+    if (lane == 0) a.slot[gw] = -1;   // unreachable: the table has twice as many slots as rows
 }
 
 // Representative of the group in table slot sl (a pattern that found no
@@ -72,7 +81,7 @@ __device__ __forceinline__ int rep_of_slot(const int *tab, int sl, int p, int B)
 
 // One block per half: number the groups in order of their representatives
 // (a block-wide scan over the patterns), then give every pattern its key and
-// every key its representative, and reset the key's hull rows.
+// every key its representative.
 __global__ __launch_bounds__(1024) void k_key_number(KeyArgs a)
 {
     const int half = blockIdx.x;
@@ -119,11 +128,6 @@ __global__ __launch_bounds__(1024) void k_key_number(KeyArgs a)
     for (int p = threadIdx.x; p < a.B; p += blockDim.x) {
         const int r = rep_of_slot(tab, slot[p], p, a.B);
         if (r != p) key_of[p] = key_of[r];
-    }
-    int *hlo = a.hlo + (int64_t)half * a.B * a.span, *hhi = a.hhi + (int64_t)half * a.B * a.span;
-    for (int64_t i = threadIdx.x; i < (int64_t)nkeys * a.span; i += blockDim.x) {
-        hlo[i] = 1 << 14;
-        hhi[i] = -1;
     }
 }
 
@@ -176,7 +180,11 @@ hipError_t launch_keys(const KeyArgs &a, hipStream_t stream)
 {
     if (a.B == 0) return hipSuccess;
     const int64_t n2 = 2 * (int64_t)a.B;
-    hipLaunchKernelGGL(k_key_insert, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, stream, a);
+    // hull accumulators: lo starts above any value (bytes 0x7f), hi at -1
+    hipError_t e = hipMemsetAsync(a.hlo, 0x7f, (size_t)n2 * a.span * sizeof(int), stream);
+    if (e == hipSuccess) e = hipMemsetAsync(a.hhi, 0xff, (size_t)n2 * a.span * sizeof(int), stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_key_insert, dim3((unsigned)((n2 * 64 + 255) / 256)), dim3(256), 0, stream, a);
     hipLaunchKernelGGL(k_key_number, dim3(2), dim3(1024), 0, stream, a);
     const int64_t nh = n2 * a.span;
     hipLaunchKernelGGL(k_key_hull, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, stream, a);
