@@ -68,9 +68,6 @@ def main():
     wl = workloads.make(args.config, seed=0)
     circ = lofp.Circuit(wl.m, wl.layers)
     method = {"auto": lofp.METHOD_AUTO, "pathsum": lofp.METHOD_PATHSUM, "contract": lofp.METHOD_CONTRACT}[args.method]
-    opts = lofp.make_opts(method=method, fwd_layer=args.fwd_layer, bwd_layer=args.bwd_layer)
-    opts_timed = lofp.make_opts(method=method, fwd_layer=args.fwd_layer, bwd_layer=args.bwd_layer,
-                                record_timing=True)
     T = torch.from_numpy(wl.Ts).to(dev)
     out = torch.zeros(wl.batch, dtype=torch.complex128, device=dev)
     stream = torch.cuda.current_stream(dev)
@@ -79,26 +76,8 @@ def main():
     counts = circ.path_counts(wl.S, wl.Ts)
     paths_per_step = float(counts.sum())
 
-    def step(o=opts, stats=None):
-        circ.amplitudes_device(wl.S, T, out, o, stream=stream, stats=stats)
-
-    # the timed steps: the production call (no statistics, no event timing)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
-    amps = out.cpu().numpy()
-    # instrumented steps: per-phase HIP-event times and work counters
-    per_step = []
-    for _ in range(max(3, min(args.steps, 10))):
-        st = lofp.Stats()
-        step(opts_timed, st)
-        per_step.append(st.as_dict())
+    ms, per_step, s_work, amps = measure(lofp, circ, wl, T, out, stream, method, args.fwd_layer, args.bwd_layer,
+                                         args.steps, args.warmup)
 
     # parity on a sample (oracle = plain definition, CPU)
     import oracle
@@ -107,7 +86,7 @@ def main():
     ref, _ = oracle.amplitudes(wl.m, wl.S, wl.Ts[idx], wl.flat_circuit(), nthreads=host_threads())
     max_err = float(np.abs(amps[idx] - ref).max())
 
-    s0 = per_step[-1]
+    s0 = s_work
     avg = lambda k: float(np.mean([s[k] for s in per_step]))
     leaves, edges = s0["dfs_leaves"], s0["dfs_edges"]
     res = {
@@ -224,33 +203,51 @@ def pathsum_roofline(s0, avg):
             "algorithmic": "32 B per frontier state (one 16 B write, one 16 B read)"}
 
 
+def measure(lofp, circ, wl, T, out, stream, method, fwd, bwd, steps, warmup):
+    """Time `steps` production calls (no statistics, no event timing) after
+    `warmup`, then a few calls with HIP-event phase timing (the same kernels),
+    then one call that counts the work done (its kernels carry counters and
+    run slower; only its counts are used)."""
+    import torch
+
+    opts = lofp.make_opts(method=method, fwd_layer=fwd, bwd_layer=bwd)
+    for _ in range(warmup):
+        circ.amplitudes_device(wl.S, T, out, opts, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        circ.amplitudes_device(wl.S, T, out, opts, stream=stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    produced = out.cpu().numpy()   # the timed calls' output, for the parity check
+    timed = lofp.make_opts(method=method, fwd_layer=fwd, bwd_layer=bwd, record_timing=True)
+    per_step = []
+    for _ in range(max(3, min(steps, 10))):
+        st = lofp.Stats()
+        circ.amplitudes_device(wl.S, T, out, timed, stream=stream, stats=st)
+        per_step.append(st.as_dict())
+    work = lofp.make_opts(method=method, fwd_layer=fwd, bwd_layer=bwd, count_work=True)
+    st = lofp.Stats()
+    circ.amplitudes_device(wl.S, T, out, work, stream=stream, stats=st)
+    return ms, per_step, st.as_dict(), produced
+
+
 def run_variant(lofp, workloads, torch, dev, stream, name, method, steps=5, fwd=-1, bwd=-1):
     wl = workloads.make(name, seed=0)
     circ = lofp.Circuit(wl.m, wl.layers)
     T = torch.from_numpy(wl.Ts).to(dev)
     o = torch.zeros(wl.batch, dtype=torch.complex128, device=dev)
-    opts = lofp.make_opts(method=method, record_timing=True, fwd_layer=fwd, bwd_layer=bwd)
-    for _ in range(2):
-        circ.amplitudes_device(wl.S, T, o, opts, stream=stream, stats=lofp.Stats())
-    torch.cuda.synchronize()
-    sts = []
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        st = lofp.Stats()
-        circ.amplitudes_device(wl.S, T, o, opts, stream=stream, stats=st)
-        sts.append(st.as_dict())
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ms, sts, s0, _ = measure(lofp, circ, wl, T, o, stream, method, fwd, bwd, steps, 2)
     paths = float(circ.path_counts(wl.S, wl.Ts).sum())
     avg = lambda k: float(np.mean([s[k] for s in sts]))
-    s0 = sts[-1]
     out = {"workload": wl.note, "batch": wl.batch, "ms_per_step": ms, "amplitudes_per_s": wl.batch / (ms * 1e-3),
            "paths_per_s": paths / (ms * 1e-3),
            "phases_ms": {k: avg(k) for k in ("ms_plan", "ms_forward", "ms_backward", "ms_dfs", "ms_reduce",
                                              "ms_contract", "ms_total")}}
     if method == lofp.METHOD_CONTRACT:
         out["transitions"] = s0["transitions"]
-        out["roofline"] = contract_roofline(avg("ms_contract"), s0["transitions"])
+        kname = "k_contract_multi" if s0["split_top_keys"] > 0 else "k_contract"
+        out["roofline"] = contract_roofline(kname, avg("ms_contract"), s0["transitions"])
     else:
         out.update({k: s0[k] for k in ("fwd_layer", "bwd_layer", "dfs_levels", "frontier_states",
                                         "backward_states", "bfs_states", "dfs_leaves", "dfs_edges")})
@@ -338,7 +335,7 @@ def cpu_baseline(oracle, wl, paths_per_step, budget_s):
     _, used = oracle.amplitudes(wl.m, wl.S, wl.Ts[:probe], circ, nthreads=threads)
     dt = time.perf_counter() - t0
     per_pat = dt / probe
-    n_pat = int(min(wl.batch * 50, max(probe, budget_s / max(per_pat, 1e-9))))
+    n_pat = int(min(wl.batch * 20000, max(probe, budget_s / max(per_pat, 1e-9))))
     reps, rem = divmod(n_pat, wl.batch)
     t0 = time.perf_counter()
     done = 0

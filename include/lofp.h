@@ -88,7 +88,10 @@ typedef struct {
                               the free device memory); the splitters between
                               the frontiers (at most 16) are enumerated
                               depth-first                                  */
-    int32_t reserved[2];
+    int32_t count_work;       /* with stats: also count the work done
+                                 (stats->transitions); the counting kernels
+                                 run slower, so timed calls leave it 0       */
+    int32_t reserved;
 } lofp_opts;
 
 /* Per-call statistics (filled when a non-null pointer is passed). */
@@ -102,7 +105,8 @@ typedef struct {
     int64_t bfs_states;       /* states produced by all frontier expansions    */
     int64_t dfs_leaves;       /* complete middle paths evaluated               */
     int64_t dfs_edges;        /* depth-first tree edges taken (incl. leaves)   */
-    int64_t transitions;      /* contraction: cut-to-cut state transitions     */
+    int64_t transitions;      /* contraction (count_work): transitions with a
+                                 nonzero source state                        */
     double ms_plan;           /* record_timing: bounds + state-space tables
                                  (contraction: bounds and key hulls)         */
     double ms_forward;        /*   forward frontier expansion                  */

@@ -415,12 +415,12 @@ lofp_status ready_on_stream(lofp_circuit_s &c, hipStream_t s)
 }
 
 lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
-                               lofp_c128 *out_dev, int fp32, hipStream_t s, lofp_stats *st, Timer &tm, bool &used,
-                               bool &bounds_done);
+                               lofp_c128 *out_dev, int fp32, hipStream_t s, lofp_stats *st, bool count_work,
+                               Timer &tm, bool &used, bool &bounds_done);
 
 lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
-                         lofp_c128 *out_dev, int count_only, int fp32, hipStream_t s, lofp_stats *st, Timer &tm,
-                         bool allow_split = true)
+                         lofp_c128 *out_dev, int count_only, int fp32, hipStream_t s, lofp_stats *st,
+                         bool count_work, Timer &tm, bool allow_split = true)
 {
     lofp_status rc = prepare_program(c, s);
     if (rc != LOFP_OK) return rc;
@@ -429,7 +429,7 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
     bool bounds_done = false;
     if (!count_only && allow_split && B >= 64) {
         bool used = false;
-        rc = run_contract_split(c, S, n, B, T_dev, out_dev, fp32, s, st, tm, used, bounds_done);
+        rc = run_contract_split(c, S, n, B, T_dev, out_dev, fp32, s, st, count_work, tm, used, bounds_done);
         if (rc != LOFP_OK || used) return rc;
     }
     if (!bounds_done) {
@@ -456,7 +456,7 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
     a.fp32 = fp32;
     a.stat_transitions = ctr + 3;
     a.overflow = reinterpret_cast<int32_t *>(ctr + 4);
-    a.stats = st != nullptr;
+    a.stats = st != nullptr && count_work;
     // state size: the S-side bound holds for every pattern; only when it is too
     // large for LDS ask the device for this batch's exact maximum
     std::vector<int16_t> slo, shi;
@@ -498,8 +498,8 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
 // halves over the crossing versions.  The grouping runs on the device; the
 // host reads back the two key counts (one synchronisation) to size the launch.
 lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
-                               lofp_c128 *out_dev, int fp32, hipStream_t s, lofp_stats *st, Timer &tm, bool &used,
-                               bool &bounds_done)
+                               lofp_c128 *out_dev, int fp32, hipStream_t s, lofp_stats *st, bool count_work,
+                               Timer &tm, bool &used, bool &bounds_done)
 {
     used = false;
     bounds_done = false;
@@ -557,7 +557,7 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     tj.m = m; tj.n = n; tj.D = c.D; tj.nvars = c.nvars; tj.tab_stride = c.tab_stride; tj.fp32 = fp32;
     tj.var_cut = c.d_var_cut.as<int32_t>(); tj.var_time = c.d_var_time.as<int32_t>();
     tj.table = c.d_table.as<double2>(); tj.S = c.d_S.as<int32_t>();
-    tj.stats = st != nullptr;
+    tj.stats = st != nullptr && count_work;
     ContractJob bj = tj;
     tj.nsteps = (int)sp->top.steps.size(); tj.steps = sp->d_top.as<ContractStep>();
     bj.nsteps = (int)sp->bot.steps.size(); bj.steps = sp->d_bot.as<ContractStep>();
@@ -597,7 +597,7 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     HIPCHK(launch_contract_multi(nj, c.d_jobs.as<ContractJob>(),
                                  contract_job_lds_bytes(c.nvars, m, any_lds ? lds_states : 0, any_lds),
                                  any_lds ? lds_states : mx, any_lds, fp32 != 0, ctr + 3,
-                                 reinterpret_cast<int32_t *>(ctr + 4), s, ov, st != nullptr));
+                                 reinterpret_cast<int32_t *>(ctr + 4), s, ov, st != nullptr && count_work));
     tm.mark();
     JoinArgs ja{};
     ja.B = B; ja.m = m; ja.n = n; ja.D = c.D;
@@ -1104,7 +1104,8 @@ lofp_status lofp_amplitudes_device(lofp_circuit c, const int32_t *S, int32_t bat
         Timer inner;
         inner.on = tm.on;
         inner.s = s;
-        rc = run_contract(*c, S, n, batch, T_dev, out_dev, 0, o.precision == LOFP_PREC_FP32, s, stats, inner);
+        rc = run_contract(*c, S, n, batch, T_dev, out_dev, 0, o.precision == LOFP_PREC_FP32, s, stats,
+                          o.count_work != 0, inner);
         if (rc == LOFP_OK && stats && tm.on) {
             // bounds (and key hulls), contraction kernel, join of split halves
             stats->ms_plan = inner.ms(0, 1);
@@ -1183,7 +1184,7 @@ lofp_status lofp_path_counts(lofp_circuit c, const int32_t *S, int32_t batch, co
     HIPCHK(hipMemcpyAsync(c->d_T.p, T, (size_t)batch * c->m * sizeof(int32_t), hipMemcpyHostToDevice, s));
     Timer tm;
     lofp_stats st{};
-    rc = run_contract(*c, S, n, batch, c->d_T.as<int32_t>(), c->d_out.as<lofp_c128>(), 1, 0, s, &st, tm);
+    rc = run_contract(*c, S, n, batch, c->d_T.as<int32_t>(), c->d_out.as<lofp_c128>(), 1, 0, s, &st, false, tm);
     if (rc != LOFP_OK) return rc;
     std::vector<double2> h(batch);
     HIPCHK(hipMemcpyAsync(h.data(), c->d_out.p, (size_t)batch * sizeof(double2), hipMemcpyDeviceToHost, s));
