@@ -122,21 +122,29 @@ __device__ inline void build_desc(const ContractStep &st, const int *vlo, const 
 // Entries of a new state for one step: each entry gathers its summed
 // versions in a fixed order (i1 outer, i0 inner).  Loads and products carry
 // no branch, so the visits of an entry overlap: an invalid visit reads the
-// gate table's zero slot and adds an exact zero.  count: also count the
+// gate table's zero slot and adds an exact zero.  STATS: also count the
 // transitions with a nonzero source (statistics only).
+//
+// Decoding an entry into its digits: small blocks keep the step's strides in
+// registers (an unrolled loop); wide blocks, which run more waves per SIMD
+// and so have fewer registers per lane, read them from the step layout in LDS
+// digit by digit.
 template <bool COUNT, bool F32, int BS, bool STATS>
 __device__ __forceinline__ void step_entries(const StepDesc &d, const double2 *__restrict__ bufA,
                                              double2 *__restrict__ bufB, const gdouble *__restrict__ W,
                                              unsigned zslot, unsigned long long &trans)
 {
+    constexpr bool kRolled = BS >= 512;
     const int n_new = d.n_new, new_size = d.new_size;
-    int nstr[kMaxActive], mstr[kMaxActive];
-    float ninv[kMaxActive];
+    int nstr[kRolled ? 1 : kMaxActive], mstr[kRolled ? 1 : kMaxActive];
+    float ninv[kRolled ? 1 : kMaxActive];
+    if (!kRolled) {
 #pragma unroll
-    for (int q = 0; q < kMaxActive; ++q) {
-        nstr[q] = d.nstr[q];
-        mstr[q] = d.mstr[q];
-        ninv[q] = d.ninv[q];
+        for (int q = 0; q < (kRolled ? 1 : kMaxActive); ++q) {
+            nstr[q] = d.nstr[q];
+            mstr[q] = d.mstr[q];
+            ninv[q] = d.ninv[q];
+        }
     }
     const int srad0 = d.srad0, srad1 = d.srad1, slo0 = d.slo0, slo1 = d.slo1, sstr0 = d.sstr0, sstr1 = d.sstr1;
     int rk[4], ra[4];
@@ -146,16 +154,30 @@ __device__ __forceinline__ void step_entries(const StepDesc &d, const double2 *_
     for (int e = threadIdx.x; e < new_size; e += BS) {
         int rem = e, base_old = 0;
         int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
+        if (kRolled) {
+#pragma nounroll
+            for (int q = n_new - 1; q >= 0; --q) {
+                const int ns = d.nstr[q];
+                const int dq = qdiv(rem, ns, d.ninv[q]);
+                rem -= dq * ns;
+                base_old += dq * d.mstr[q];
+                d0 = q == 0 ? dq : d0;
+                d1 = q == 1 ? dq : d1;
+                d2 = q == 2 ? dq : d2;
+                d3 = q == 3 ? dq : d3;
+            }
+        } else {
 #pragma unroll
-        for (int q = kMaxActive - 1; q >= 0; --q) {
-            if (q < n_new) {
-                const int dq = qdiv(rem, nstr[q], ninv[q]);
-                rem -= dq * nstr[q];
-                base_old += dq * mstr[q];
-                if (q == 0) d0 = dq;
-                if (q == 1) d1 = dq;
-                if (q == 2) d2 = dq;
-                if (q == 3) d3 = dq;
+            for (int q = (kRolled ? 1 : kMaxActive) - 1; q >= 0; --q) {
+                if (q < n_new) {
+                    const int dq = qdiv(rem, nstr[q], ninv[q]);
+                    rem -= dq * nstr[q];
+                    base_old += dq * mstr[q];
+                    if (q == 0) d0 = dq;
+                    if (q == 1) d1 = dq;
+                    if (q == 2) d2 = dq;
+                    if (q == 3) d3 = dq;
+                }
             }
         }
         const int nv0 = nlo0 + d0, nv1 = nlo1 + d1, nv2 = nlo2 + d2, nv3 = nlo3 + d3;
@@ -370,8 +392,12 @@ __global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
 }
 
 // Many circuits, one block per job.
+// Waves per SIMD a multi-job block size is compiled for: 512-thread blocks
+// run three jobs (24 waves) per CU.
+template <int BS> constexpr int multi_waves_per_simd() { return BS >= 512 ? 6 : 1; }
+
 template <bool F32, bool LDS_STATE, int BS, bool STATS>
-__global__ __launch_bounds__(BS) void k_contract_multi(const ContractJob *__restrict__ jobs,
+__global__ __launch_bounds__(BS, multi_waves_per_simd<BS>()) void k_contract_multi(const ContractJob *__restrict__ jobs,
                                                        unsigned long long *stat_transitions, int32_t *overflow,
                                                        MultiOverride ov)
 {
@@ -600,13 +626,16 @@ template <bool F32, bool LDS_STATE>
 static void launch_multi_t(int count, const ContractJob *jobs, size_t dyn, int max_states,
                            unsigned long long *st, int32_t *ov, MultiOverride o, bool stats, hipStream_t stream)
 {
+    // many small jobs: one wave each; larger jobs: 512 threads, so a step's
+    // entries spread thin and the three jobs sharing a CU hide each other's
+    // latencies
     const bool wide = contract_block_size(max_states) != 64;
     const dim3 g(count);
     if (stats) {
-        if (wide) hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 256, true>), g, dim3(256), dyn, stream, jobs, st, ov, o);
+        if (wide) hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 512, true>), g, dim3(512), dyn, stream, jobs, st, ov, o);
         else hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 64, true>), g, dim3(64), dyn, stream, jobs, st, ov, o);
     } else {
-        if (wide) hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 256, false>), g, dim3(256), dyn, stream, jobs, st, ov, o);
+        if (wide) hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 512, false>), g, dim3(512), dyn, stream, jobs, st, ov, o);
         else hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 64, false>), g, dim3(64), dyn, stream, jobs, st, ov, o);
     }
 }
