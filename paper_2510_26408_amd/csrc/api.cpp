@@ -523,14 +523,19 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     // group the patterns by their two halves of T
     int cap = 1;
     while (cap < 2 * B) cap <<= 1;
+    void *old_tab = c.d_ktab.p;
     HIPCHK(ensure(c.d_ktab, (size_t)2 * cap * sizeof(int)));
+    if (c.d_ktab.p != old_tab) c.ktab_clean = false;
     HIPCHK(ensure(c.d_kslot, (size_t)2 * B * sizeof(int)));
     HIPCHK(ensure(c.d_kof, (size_t)2 * B * sizeof(int)));
     HIPCHK(ensure(c.d_krep, (size_t)2 * B * sizeof(int)));
     HIPCHK(ensure(c.d_kcnt, 2 * sizeof(int)));
     HIPCHK(ensure(c.d_khull, (size_t)2 * 2 * B * span * sizeof(int)));
     HIPCHK(ensure(c.d_klohi, (size_t)2 * 2 * B * span * sizeof(int16_t)));
-    HIPCHK(hipMemsetAsync(c.d_ktab.p, 0xFF, (size_t)2 * cap * sizeof(int), s));
+    // the table is left empty by each call; it is cleared here only when new
+    // or when a previous call stopped before emptying it
+    if (!c.ktab_clean) HIPCHK(hipMemsetAsync(c.d_ktab.p, 0xFF, c.d_ktab.cap, s));
+    c.ktab_clean = false;
     KeyArgs ka{};
     ka.B = B; ka.m = m; ka.n = n; ka.rs = rs; ka.cap = cap; ka.span = span;
     ka.T = T_dev;
@@ -540,7 +545,9 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     ka.key_of = c.d_kof.as<int>(); ka.rep_of = c.d_krep.as<int>(); ka.count = c.d_kcnt.as<int>();
     ka.hlo = c.d_khull.as<int>(); ka.hhi = ka.hlo + (size_t)2 * B * span;
     ka.klo = c.d_klohi.as<int16_t>(); ka.khi = ka.klo + (size_t)2 * B * span;
+    ka.counters = c.d_counters.as<unsigned long long>();
     HIPCHK(launch_keys(ka, s));
+    c.ktab_clean = true;
     HIPCHK(hipMemcpyAsync(c.h_pin, c.d_kcnt.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const int ntop = c.h_pin[0], nbot = c.h_pin[1];
@@ -564,8 +571,7 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     HIPCHK(ensure(c.d_jobs, (size_t)std::max(nj, 1) * sizeof(ContractJob)));
     HIPCHK(ensure(c.d_kinf, (size_t)std::max(nj, 1) * sizeof(int32_t)));
     HIPCHK(launch_key_jobs(ka, tj, bj, c.d_jobs.as<ContractJob>(), c.d_kinf.as<int32_t>(), s));
-    unsigned long long *ctr = c.d_counters.as<unsigned long long>();
-    HIPCHK(hipMemsetAsync(ctr, 0, 8 * sizeof(unsigned long long), s));
+    unsigned long long *ctr = c.d_counters.as<unsigned long long>();   // zeroed by k_key_jobs
     int mx;
     if (cap_s <= (1 << 20)) {
         mx = (int)std::max<int64_t>(cap_s, 1);
@@ -1082,7 +1088,10 @@ lofp_status lofp_amplitudes_device(lofp_circuit c, const int32_t *S, int32_t bat
     rc = device_init(*c, n, s);
     if (rc != LOFP_OK) return rc;
     std::vector<int32_t> Sv(S, S + c->m);
-    HIPCHK(upload(c->d_S, Sv, s));
+    if (Sv != c->S_dev) {
+        HIPCHK(upload(c->d_S, Sv, s));
+        c->S_dev = Sv;
+    }
     Timer tm;
     tm.on = o.record_timing != 0 && stats != nullptr;
     tm.s = s;
@@ -1178,7 +1187,10 @@ lofp_status lofp_path_counts(lofp_circuit c, const int32_t *S, int32_t batch, co
     rc = device_init(*c, n, s);
     if (rc != LOFP_OK) return rc;
     std::vector<int32_t> Sv(S, S + c->m);
-    HIPCHK(upload(c->d_S, Sv, s));
+    if (Sv != c->S_dev) {
+        HIPCHK(upload(c->d_S, Sv, s));
+        c->S_dev = Sv;
+    }
     HIPCHK(ensure(c->d_T, (size_t)batch * c->m * sizeof(int32_t)));
     HIPCHK(ensure(c->d_out, (size_t)batch * sizeof(double2)));
     HIPCHK(hipMemcpyAsync(c->d_T.p, T, (size_t)batch * c->m * sizeof(int32_t), hipMemcpyHostToDevice, s));

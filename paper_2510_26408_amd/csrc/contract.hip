@@ -506,9 +506,10 @@ __global__ __launch_bounds__(64) void k_join(JoinArgs g)
             }
         }
     }
-    const double2 *TS = g.top_state + (int64_t)tk * g.state_cap;
-    const double2 *BS_ = g.bot_state + (int64_t)bk * g.state_cap;
+    const gdouble *TS = (const gdouble *)(g.top_state + (int64_t)tk * g.state_cap);
+    const gdouble *BS_ = (const gdouble *)(g.bot_state + (int64_t)bk * g.state_cap);
     CSum sr{0.0, 0.0}, si{0.0, 0.0};
+#pragma unroll 2
     for (int e = threadIdx.x; e < box; e += 64) {
         int rem = e, ti = 0, bi = 0;
 #pragma unroll
@@ -520,7 +521,7 @@ __global__ __launch_bounds__(64) void k_join(JoinArgs g)
                 bi += (d + boff[q]) * bstr[q];
             }
         }
-        const double2 c = cmul(TS[ti], BS_[bi]);
+        const double2 c = cmul(make_double2(TS[2 * ti], TS[2 * ti + 1]), make_double2(BS_[2 * bi], BS_[2 * bi + 1]));
         csum_add(sr, c.x);
         csum_add(si, c.y);
     }

@@ -133,6 +133,8 @@ struct lofp_circuit_s {
     DevBuf d_levels, d_tab_mid, d_counters, d_T, d_out, d_ws, d_cfg, d_rankb;
     DevBuf d_ktab, d_kslot, d_kof, d_krep, d_kcnt, d_khull, d_klohi, d_kinf, d_jobs, d_kstate;
     int32_t *h_pin = nullptr;              // small pinned readback buffer
+    bool ktab_clean = false;               // key hash table known to be empty
+    std::vector<int32_t> S_dev;            // the S now held in d_S
 };
 
 

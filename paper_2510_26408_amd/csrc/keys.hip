@@ -43,6 +43,15 @@ __global__ __launch_bounds__(256) void k_key_insert(KeyArgs a)
         h ^= __shfl_xor(h, o, 64);
     }
     const int v = tot == a.n ? p : p + a.B;
+    // reset hull row (half, p): key numbers are below B, so the rows of all
+    // keys get reset
+    {
+        const int64_t row = ((int64_t)half * a.B + p) * a.span;
+        for (int i = lane; i < a.span; i += 64) {
+            a.hlo[row + i] = 0x7f7f7f7f;
+            a.hhi[row + i] = -1;
+        }
+    }
     int *tab = a.table + (int64_t)half * a.cap;
     uint32_t j = (uint32_t)(h ^ (h >> 32)) & (uint32_t)(a.cap - 1);
     for (int probe = 0; probe < a.cap; ++probe) {
@@ -129,6 +138,12 @@ __global__ __launch_bounds__(1024) void k_key_number(KeyArgs a)
         const int r = rep_of_slot(tab, slot[p], p, a.B);
         if (r != p) key_of[p] = key_of[r];
     }
+    // leave the table empty for the next call (every used slot is some
+    // pattern's slot)
+    __syncthreads();
+    int *wtab = a.table + (int64_t)half * a.cap;
+    for (int p = threadIdx.x; p < a.B; p += blockDim.x)
+        if (slot[p] >= 0) wtab[slot[p]] = -1;
 }
 
 // Hull of the feasible members' intervals, one thread per (pattern, half, entry).
@@ -158,6 +173,7 @@ __global__ void k_key_jobs(KeyArgs a, ContractJob top, ContractJob bot, Contract
     const int half = (int)(gi / per);
     const int64_t r = gi - half * per;
     const int k = (int)(r / a.span), i = (int)(r - (int64_t)k * a.span);
+    if (gi < 8) a.counters[gi] = 0;   // the contraction's counters for this call
     if (k >= a.count[half]) return;
     const int64_t row = ((int64_t)half * a.B + k) * a.span;
     int l = a.hlo[row + i], h = a.hhi[row + i];
@@ -180,10 +196,6 @@ hipError_t launch_keys(const KeyArgs &a, hipStream_t stream)
 {
     if (a.B == 0) return hipSuccess;
     const int64_t n2 = 2 * (int64_t)a.B;
-    // hull accumulators: lo starts above any value (bytes 0x7f), hi at -1
-    hipError_t e = hipMemsetAsync(a.hlo, 0x7f, (size_t)n2 * a.span * sizeof(int), stream);
-    if (e == hipSuccess) e = hipMemsetAsync(a.hhi, 0xff, (size_t)n2 * a.span * sizeof(int), stream);
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_key_insert, dim3((unsigned)((n2 * 64 + 255) / 256)), dim3(256), 0, stream, a);
     hipLaunchKernelGGL(k_key_number, dim3(2), dim3(1024), 0, stream, a);
     const int64_t nh = n2 * a.span;

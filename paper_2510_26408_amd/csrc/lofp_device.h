@@ -260,6 +260,7 @@ struct KeyArgs {
     int *table, *slot, *key_of, *rep_of, *count;
     int *hlo, *hhi;                // int32 hull accumulators
     int16_t *klo, *khi;            // per key intervals (top keys at 0, bottom at B)
+    unsigned long long *counters;  // [8] zeroed by the jobs kernel
 };
 hipError_t launch_keys(const KeyArgs &a, hipStream_t stream);
 // One contraction job per key from the two half templates; jobs[0, ntop) top.
