@@ -51,15 +51,27 @@ typedef const double __attribute__((address_space(1))) gdouble;
 // intervals (all values uniform over the block).  New entry e decodes into
 // digits d_q = (e / nstr[q]) mod rad_q; the old entry it reads sits at
 // sum_q d_q * mstr[q] + i0 * sstr0 + i1 * sstr1 over the summed versions.
+// Per digit q: dig[q] = {nstr, mstr, magic, shift} and ninv[q] = 1 / nstr, where
+// e / nstr == (e * magic) >> shift exactly for every entry index e < 2^22
+// (division by an invariant integer, Granlund and Montgomery: with
+// shift = 31 + ceil(log2 nstr) and magic = ceil(2^shift / nstr) the error of
+// e * magic / 2^shift stays below 2^-9 / nstr).
 struct StepDesc {
     int new_size, n_new, gate;
     int srad0, srad1, slo0, slo1, sstr0, sstr1;
     int rk[4], ra[4], nlo[4];
-    int nstr[kMaxActive], mstr[kMaxActive];
+    int4 dig[kMaxActive];
     float ninv[kMaxActive];
 };
-constexpr int kDescChunk = 16;   // descriptors built per pass
 
+__device__ __forceinline__ int magic_div(int e, int4 g)
+{
+    return (int)(((unsigned long long)(unsigned)e * (unsigned)g.z) >> g.w);
+}
+constexpr int kDescChunk = 16;   // step layouts built per pass
+
+// MAGIC: also the magic multipliers (wide blocks decode with them)
+template <bool MAGIC>
 __device__ inline void build_desc(const ContractStep &st, const int *vlo, const int *vrad, const int *spre,
                                   const int *tpre, int n, StepDesc &d)
 {
@@ -83,9 +95,23 @@ __device__ inline void build_desc(const ContractStep &st, const int *vlo, const 
             for (int q2 = 0; q2 < kMaxActive; ++q2) ms = (q2 == src) ? ostr[q2] : ms;
         }
         const int nsi = ns < (1 << 30) ? (int)ns : (1 << 30);
-        d.nstr[q] = nsi;
+        // magic = ceil(2^sh / nsi), only where entries get decoded: a stride of
+        // 0 (an empty interval: no entries) or above 2^22 (a state too large to
+        // run) never divides.  A double quotient, then exact integer fix-ups;
+        // below 2^53 the quotient is off by at most one, so each loop runs at
+        // most once.
+        int sh = 0;
+        unsigned long long mg = 0;
+        if (MAGIC && nsi >= 1 && nsi <= (1 << 22)) {
+            const int l = nsi > 1 ? 32 - __clz(nsi - 1) : 0;   // ceil(log2 nsi)
+            sh = 31 + l;
+            const unsigned long long two_sh = 1ULL << sh, dn = (unsigned long long)nsi;
+            mg = (unsigned long long)((double)two_sh / (double)nsi);
+            if (mg * dn < two_sh) ++mg;
+            if (mg > 1 && (mg - 1) * dn >= two_sh) --mg;
+        }
+        d.dig[q] = make_int4(nsi, ms, (int)(unsigned)mg, sh);
         d.ninv[q] = 1.0f / (float)nsi;
-        d.mstr[q] = ms;
         if (q < 4) d.nlo[q] = q < n_new ? vlo[st.new_vars[q]] : 0;
         if (q < n_new) ns *= vrad[st.new_vars[q]];
     }
@@ -126,9 +152,9 @@ __device__ inline void build_desc(const ContractStep &st, const int *vlo, const 
 // transitions with a nonzero source (statistics only).
 //
 // Decoding an entry into its digits: small blocks keep the step's strides in
-// registers (an unrolled loop); wide blocks, which run more waves per SIMD
-// and so have fewer registers per lane, read them from the step layout in LDS
-// digit by digit.
+// registers (an unrolled loop, float-reciprocal quotients); wide blocks, which
+// run more waves per SIMD and so have fewer registers per lane, read each
+// digit's stride and magic multiplier from the step layout in LDS.
 template <bool COUNT, bool F32, int BS, bool STATS>
 __device__ __forceinline__ void step_entries(const StepDesc &d, const double2 *__restrict__ bufA,
                                              double2 *__restrict__ bufB, const gdouble *__restrict__ W,
@@ -141,8 +167,8 @@ __device__ __forceinline__ void step_entries(const StepDesc &d, const double2 *_
     if (!kRolled) {
 #pragma unroll
         for (int q = 0; q < (kRolled ? 1 : kMaxActive); ++q) {
-            nstr[q] = d.nstr[q];
-            mstr[q] = d.mstr[q];
+            nstr[q] = d.dig[q].x;
+            mstr[q] = d.dig[q].y;
             ninv[q] = d.ninv[q];
         }
     }
@@ -157,10 +183,10 @@ __device__ __forceinline__ void step_entries(const StepDesc &d, const double2 *_
         if (kRolled) {
 #pragma nounroll
             for (int q = n_new - 1; q >= 0; --q) {
-                const int ns = d.nstr[q];
-                const int dq = qdiv(rem, ns, d.ninv[q]);
-                rem -= dq * ns;
-                base_old += dq * d.mstr[q];
+                const int4 g = d.dig[q];
+                const int dq = magic_div(rem, g);
+                rem -= dq * g.x;
+                base_old += dq * g.y;
                 d0 = q == 0 ? dq : d0;
                 d1 = q == 1 ? dq : d1;
                 d2 = q == 2 ? dq : d2;
@@ -317,7 +343,7 @@ __device__ void contract_run(const ContractJob &g, unsigned char *smem, unsigned
         if (slot == 0) {
             // layouts of the next steps, one thread per step
             for (int k = threadIdx.x; k < kDescChunk && si + k < g.nsteps; k += BS)
-                build_desc(g.steps[si + k], vlo, vrad, spre, tpre, g.n, desc[k]);
+                build_desc<(BS >= 512)>(g.steps[si + k], vlo, vrad, spre, tpre, g.n, desc[k]);
             __syncthreads();
         }
         const StepDesc &d = desc[slot];
