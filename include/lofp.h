@@ -234,12 +234,16 @@ typedef struct {
 
 /* Start a server on the current device (opts may be NULL). */
 lofp_status lofp_server_create(const lofp_server_opts *opts, lofp_server *out);
-/* Queue one request (S, T: host int32[m], copied); *ticket identifies it. */
+/* Queue one request (S, T: host int32[m], copied); *ticket identifies it.
+ * Lengths and occupations are checked here (EINVAL); the request is planned
+ * on the server's thread, so ENOTSUP / ENOMEM for it come from
+ * lofp_server_result. */
 lofp_status lofp_server_submit(lofp_server s, lofp_circuit c, const int32_t *S, const int32_t *T,
                                uint64_t *ticket);
 /* *done = 1 and out / latency_ms filled (either may be NULL) once the ticket
  * has completed; wait = 1 blocks until then.  A completed ticket is
- * consumed.  EDEVICE if its batch failed. */
+ * consumed.  EDEVICE if its batch failed; the planning error (ENOTSUP,
+ * ENOMEM) if the request could not run. */
 lofp_status lofp_server_result(lofp_server s, uint64_t ticket, int32_t wait, lofp_c128 *out,
                                double *latency_ms, int32_t *done);
 lofp_status lofp_server_get_stats(lofp_server s, lofp_server_stats *out);

@@ -139,39 +139,137 @@ void s_only_bounds(const lofp_circuit_s &c, const int32_t *S, int n, std::vector
     (void)propagate_bounds(m, D, n, c.cut_gate.data(), lo.data(), hi.data());
 }
 
-lofp_status device_init(lofp_circuit_s &c, int n, hipStream_t s)
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Appends one array to the staging bytes at a 256-byte boundary and points
+// the DevBuf view at its device copy.
+template <class T>
+void stage(std::vector<unsigned char> &h, size_t base, char *dev, const std::vector<T> &v, DevBuf &view)
 {
-    if (!c.dev_ready) {
-        std::vector<double> th(c.G), ph(c.G);
-        for (int g = 0; g < c.G; ++g) { th[g] = c.gates[g].theta; ph[g] = c.gates[g].phi; }
-        HIPCHK(upload(c.d_theta, th, s));
-        HIPCHK(upload(c.d_phi, ph, s));
-        HIPCHK(upload(c.d_fr_lo, c.fr_lo, s));
-        HIPCHK(upload(c.d_fr_hi, c.fr_hi, s));
-        HIPCHK(upload(c.d_br_lo, c.br_lo, s));
-        HIPCHK(upload(c.d_br_hi, c.br_hi, s));
-        HIPCHK(upload(c.d_cut_gate, c.cut_gate, s));
-        HIPCHK(upload(c.d_stage_time, c.stage_time, s));
-        HIPCHK(upload(c.d_gate_cut, c.gate_cut, s));
-        HIPCHK(upload(c.d_gate_layer, c.gate_layer, s));
-        HIPCHK(upload(c.d_cut_ngates, c.cut_ngates, s));
-        HIPCHK(upload(c.d_cut_gates, c.cut_gates, s));
-        HIPCHK(upload(c.d_ver_at, c.ver_at, s));
-        HIPCHK(ensure(c.d_counters, 16 * sizeof(unsigned long long)));
-        c.dev_ready = true;
-        c.pending_init = true;
+    const size_t off = align256(h.size());
+    const size_t bytes = v.size() * sizeof(T);
+    h.resize(off + std::max<size_t>(bytes, 16), 0);
+    if (bytes) std::memcpy(h.data() + off, v.data(), bytes);
+    set_view(view, dev + base + off, std::max<size_t>(bytes, 16));
+}
+
+}  // namespace
+
+// Device side of circuits: constants, the contraction program (when built)
+// and the transition tables for n photons.  Everything the listed circuits
+// still lack goes into one pooled block, filled by one copy and one
+// table-build launch; the circuits share the block.
+lofp_status init_circuits(const std::vector<std::pair<lofp_circuit_s *, int>> &list, hipStream_t s)
+{
+    struct Part {
+        lofp_circuit_s *c;
+        int n;
+        bool consts, prog, table;
+        int nt, stride;
+        size_t tab_off;
+    };
+    std::vector<Part> parts;
+    size_t tab_bytes = 0;
+    for (const auto &e : list) {
+        lofp_circuit_s *c = e.first;
+        Part P{c, e.second, !c->dev_ready, !c->prog_on_device && c->prog_built && c->prog_error.empty(),
+               c->n_tab < e.second, 0, 0, 0};
+        bool dup = false;
+        for (Part &q : parts)
+            if (q.c == c) { q.n = std::max(q.n, P.n); q.table = q.c->n_tab < q.n; dup = true; }
+        if (dup) continue;
+        if (P.consts || P.prog || P.table) parts.push_back(P);
     }
-    if (c.n_tab < n) {
-        const int nt = std::max(n, 4);
-        const int stride = sector_offset(nt + 1) + 1;   // sectors N = 0..nt, then a zero slot
-        HIPCHK(ensure(c.d_table, (size_t)std::max(c.G, 1) * stride * sizeof(double2)));
-        HIPCHK(launch_build_tables(c.G, nt, c.d_theta.as<double>(), c.d_phi.as<double>(),
-                                   c.d_table.as<double2>(), s));
-        c.n_tab = nt;
-        c.tab_stride = stride;
+    if (parts.empty()) return LOFP_OK;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    for (Part &P : parts) {
+        if (!P.table) continue;
+        P.nt = std::max(P.n, 4);
+        P.stride = sector_offset(P.nt + 1) + 1;   // sectors N = 0..nt, then a zero slot
+        P.tab_off = tab_bytes;
+        tab_bytes += align256((size_t)std::max(P.c->G, 1) * P.stride * sizeof(double2));
+    }
+    // first pass: sizes (the staging layout is deterministic, so build it
+    // once to learn the size, then with the device base)
+    auto fill = [&](std::vector<unsigned char> &h, char *dev_base) {
+        h.clear();
+        for (Part &P : parts) {
+            lofp_circuit_s &c = *P.c;
+            if (P.consts) {
+                std::vector<double> th(c.G), ph(c.G);
+                for (int g = 0; g < c.G; ++g) { th[g] = c.gates[g].theta; ph[g] = c.gates[g].phi; }
+                stage(h, 0, dev_base, th, c.d_theta);
+                stage(h, 0, dev_base, ph, c.d_phi);
+                stage(h, 0, dev_base, c.fr_lo, c.d_fr_lo);
+                stage(h, 0, dev_base, c.fr_hi, c.d_fr_hi);
+                stage(h, 0, dev_base, c.br_lo, c.d_br_lo);
+                stage(h, 0, dev_base, c.br_hi, c.d_br_hi);
+                stage(h, 0, dev_base, c.cut_gate, c.d_cut_gate);
+                stage(h, 0, dev_base, c.stage_time, c.d_stage_time);
+                stage(h, 0, dev_base, c.gate_cut, c.d_gate_cut);
+                stage(h, 0, dev_base, c.gate_layer, c.d_gate_layer);
+                stage(h, 0, dev_base, c.cut_ngates, c.d_cut_ngates);
+                stage(h, 0, dev_base, c.cut_gates, c.d_cut_gates);
+                stage(h, 0, dev_base, c.ver_at, c.d_ver_at);
+                stage(h, 0, dev_base, std::vector<unsigned long long>(16, 0), c.d_counters);
+            }
+            if (P.prog) {
+                stage(h, 0, dev_base, c.var_cut, c.d_var_cut);
+                stage(h, 0, dev_base, c.var_time, c.d_var_time);
+                stage(h, 0, dev_base, c.steps, c.d_steps);
+            }
+        }
+    };
+    std::vector<unsigned char> h;
+    fill(h, nullptr);
+    const size_t jobs_off = align256(h.size());
+    int njobs = 0;
+    for (const Part &P : parts) njobs += P.table ? 1 : 0;
+    const size_t const_bytes = jobs_off + align256((size_t)std::max(njobs, 1) * sizeof(TableJob));
+    auto blk = std::make_shared<SharedBlock>();
+    blk->bytes = const_bytes + tab_bytes;
+    blk->device = dev;
+    blk->p = pool_alloc(blk->bytes, dev);
+    if (!blk->p) return fail(LOFP_ENOMEM, "device memory for circuit set-up");
+    char *base = static_cast<char *>(blk->p);
+    fill(h, base);
+    std::vector<TableJob> jobs;
+    int64_t max_entries = 0;
+    for (Part &P : parts) {
+        lofp_circuit_s &c = *P.c;
+        if (P.table) {
+            TableJob J;
+            J.G = c.G; J.n_tab = P.nt; J.stride = P.stride;
+            J.theta = c.d_theta.as<double>(); J.phi = c.d_phi.as<double>();
+            const size_t tb = (size_t)std::max(c.G, 1) * P.stride * sizeof(double2);
+            set_view(c.d_table, base + const_bytes + P.tab_off, tb);
+            J.table = c.d_table.as<double2>();
+            jobs.push_back(J);
+            max_entries = std::max<int64_t>(max_entries, (int64_t)c.G * P.stride);
+        }
+    }
+    h.resize(const_bytes, 0);
+    if (!jobs.empty()) std::memcpy(h.data() + jobs_off, jobs.data(), jobs.size() * sizeof(TableJob));
+    HIPCHK(hipMemcpyAsync(base, h.data(), const_bytes, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_build_tables_multi((int)jobs.size(), reinterpret_cast<const TableJob *>(base + jobs_off),
+                                     max_entries, s));
+    for (Part &P : parts) {
+        lofp_circuit_s &c = *P.c;
+        c.blocks.push_back(blk);
+        if (P.consts) c.dev_ready = true;
+        if (P.prog) c.prog_on_device = true;
+        if (P.table) { c.n_tab = P.nt; c.tab_stride = P.stride; }
         c.pending_init = true;
     }
     return LOFP_OK;
+}
+
+lofp_status device_init(lofp_circuit_s &c, int n, hipStream_t s)
+{
+    return init_circuits({{&c, n}}, s);
 }
 
 lofp_status run_bounds(lofp_circuit_s &c, int B, int n, const int32_t *T_dev, hipStream_t s)
@@ -248,58 +346,86 @@ Schedule schedule_factors(const lofp_circuit_s &c, const std::vector<int> &order
             if (x.kind < 0) last_use[x.arg] = (int)f;
     for (int v = 0; v < c.nvars; ++v)
         if (!external.empty() && external[v]) last_use[v] = (int)order.size();  // never summed here
-    std::vector<int> active;
+    // live versions in layout order, and each version's position in the
+    // current (old) and next (new) layouts (-1: not there)
+    int act[kMaxActive], n_act = 0;
+    std::vector<int> pos_old(c.nvars, -1), pos_new(c.nvars, -1);
+    sc.steps.reserve(order.size());
     for (size_t f = 0; f < order.size(); ++f) {
         const std::array<FRef, 4> &fr = c.fac[order[f]];
         ContractStep st;
         std::memset(&st, 0, sizeof(st));
         st.gate = c.fgate[order[f]];
-        std::vector<int> F;
-        for (const FRef &x : fr)
-            if (x.kind < 0 && std::find(F.begin(), F.end(), x.arg) == F.end()) F.push_back(x.arg);
-        std::vector<int> summed, kept;
-        for (int v : F) (last_use[v] == (int)f ? summed : kept).push_back(v);
-        std::vector<int> nl = kept;
-        for (int v : active)
-            if (std::find(F.begin(), F.end(), v) == F.end()) nl.push_back(v);
-        if ((int)nl.size() > kMaxActive || (int)active.size() > kMaxActive || summed.size() > 2) {
+        // the splitter's free versions (distinct, in reference order)
+        int F[4], nF = 0;
+        for (const FRef &x : fr) {
+            if (x.kind >= 0) continue;
+            bool seen = false;
+            for (int i = 0; i < nF; ++i) seen |= F[i] == x.arg;
+            if (!seen) F[nF++] = x.arg;
+        }
+        int nl[kMaxActive], n_nl = 0, n_sum = 0;
+        bool too_many = false;
+        for (int i = 0; i < nF; ++i) {
+            const int v = F[i];
+            if (last_use[v] == (int)f) {
+                if (n_sum == 2) { too_many = true; break; }
+                st.sum_vars[n_sum++] = v;
+            } else {
+                if (n_nl == kMaxActive) { too_many = true; break; }
+                nl[n_nl++] = v;
+            }
+        }
+        for (int q = 0; q < n_act && !too_many; ++q) {
+            const int v = act[q];
+            bool inF = false;
+            for (int i = 0; i < nF; ++i) inF |= F[i] == v;
+            if (inF) continue;
+            if (n_nl == kMaxActive) { too_many = true; break; }
+            nl[n_nl++] = v;
+        }
+        if (too_many) {
             sc.error = "contraction state has too many live cut versions";
             return sc;
         }
-        st.n_new = (int)nl.size();
-        st.n_old = (int)active.size();
-        st.n_sum = (int)summed.size();
-        for (int q = 0; q < st.n_old; ++q) st.old_vars[q] = active[q];
-        for (int q = 0; q < st.n_new; ++q) {
+        st.n_new = n_nl;
+        st.n_old = n_act;
+        st.n_sum = n_sum;
+        for (int q = 0; q < n_act; ++q) st.old_vars[q] = act[q];
+        for (int q = 0; q < n_nl; ++q) {
             st.new_vars[q] = nl[q];
-            auto it = std::find(active.begin(), active.end(), nl[q]);
-            st.new_to_old[q] = it == active.end() ? -1 : (int)(it - active.begin());
+            st.new_to_old[q] = pos_old[nl[q]];
+            pos_new[nl[q]] = q;
         }
-        for (int q = 0; q < st.n_sum; ++q) {
-            st.sum_vars[q] = summed[q];
-            auto it = std::find(active.begin(), active.end(), summed[q]);
-            st.sum_to_old[q] = it == active.end() ? -1 : (int)(it - active.begin());
-        }
+        for (int q = 0; q < n_sum; ++q) st.sum_to_old[q] = pos_old[st.sum_vars[q]];
         for (int k = 0; k < 4; ++k) {
             const FRef &x = fr[k];
             if (x.kind >= 0) {
                 st.ref_kind[k] = x.kind;
                 st.ref_arg[k] = x.arg;
+            } else if (n_sum > 0 && st.sum_vars[0] == x.arg) {
+                st.ref_kind[k] = CREF_SUM;
+                st.ref_arg[k] = 0;
+            } else if (n_sum > 1 && st.sum_vars[1] == x.arg) {
+                st.ref_kind[k] = CREF_SUM;
+                st.ref_arg[k] = 1;
             } else {
-                auto it = std::find(summed.begin(), summed.end(), x.arg);
-                if (it != summed.end()) {
-                    st.ref_kind[k] = CREF_SUM;
-                    st.ref_arg[k] = (int)(it - summed.begin());
-                } else {
-                    st.ref_kind[k] = CREF_NEW;
-                    st.ref_arg[k] = (int)(std::find(nl.begin(), nl.end(), x.arg) - nl.begin());
-                }
+                st.ref_kind[k] = CREF_NEW;
+                st.ref_arg[k] = pos_new[x.arg];
             }
         }
         sc.steps.push_back(st);
-        active = nl;
+        // the new layout becomes the old one
+        for (int q = 0; q < n_act; ++q) pos_old[act[q]] = -1;
+        for (int q = 0; q < n_sum; ++q) pos_old[st.sum_vars[q]] = -1;
+        for (int q = 0; q < n_nl; ++q) {
+            act[q] = nl[q];
+            pos_old[nl[q]] = q;
+            pos_new[nl[q]] = -1;
+        }
+        n_act = n_nl;
     }
-    sc.live_out = active;
+    sc.live_out.assign(act, act + n_act);
     return sc;
 }
 
@@ -995,7 +1121,8 @@ lofp_status lofp_circuit_destroy(lofp_circuit c)
                       &c->d_levels, &c->d_tab_mid, &c->d_counters, &c->d_T, &c->d_out, &c->d_ws,
                       &c->d_cfg, &c->d_rankb, &c->d_ktab, &c->d_kslot, &c->d_kof, &c->d_krep, &c->d_kcnt,
                       &c->d_khull, &c->d_klohi, &c->d_kinf, &c->d_jobs, &c->d_kstate};
-    if (c->ready_ev) (void)hipStreamSynchronize(c->ready_stream);
+    // pooled blocks are reused at once, so no work of this circuit may be left
+    if (c->dev_ready || !c->blocks.empty()) (void)hipDeviceSynchronize();
     for (DevBuf *b : bufs) release(*b);
     if (c->h_pin) (void)hipHostFree(c->h_pin);
     if (c->ready_ev) (void)hipEventDestroy(c->ready_ev);

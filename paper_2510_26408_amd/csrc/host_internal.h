@@ -28,9 +28,12 @@ const char *last_error();
                                       std::string(#call) + ": " + hipGetErrorString(e_));         \
     } while (0)
 
+// A device buffer the owner allocates, or (view) a range of a block that
+// someone else owns: a view is never freed through the DevBuf.
 struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
+    bool view = false;
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
@@ -38,12 +41,13 @@ inline hipError_t ensure(DevBuf &b, size_t bytes)
 {
     if (bytes == 0) bytes = 16;
     if (bytes <= b.cap) return hipSuccess;
-    if (b.p) {
+    if (b.p && !b.view) {
         hipError_t e = hipFree(b.p);
         if (e != hipSuccess) return e;
     }
     b.p = nullptr;
     b.cap = 0;
+    b.view = false;
     hipError_t e = hipMalloc(&b.p, bytes);
     if (e == hipSuccess) b.cap = bytes;
     return e;
@@ -51,10 +55,38 @@ inline hipError_t ensure(DevBuf &b, size_t bytes)
 
 inline void release(DevBuf &b)
 {
-    if (b.p) (void)hipFree(b.p);
+    if (b.p && !b.view) (void)hipFree(b.p);
     b.p = nullptr;
     b.cap = 0;
+    b.view = false;
 }
+
+inline void set_view(DevBuf &b, void *p, size_t bytes)
+{
+    release(b);
+    b.p = p;
+    b.cap = bytes;
+    b.view = true;
+}
+
+// Device memory pool for circuit set-up (csrc/pool.cpp): blocks come from
+// 64 MiB slabs in power-of-two size classes and go back to per-class free
+// lists, so creating many small circuits costs no hipMalloc each.  Slabs live
+// until the process ends.
+void *pool_alloc(size_t bytes, int device);
+void pool_free(void *p, size_t bytes, int device);
+
+// A pooled block shared by the circuits set up together; freed to the pool
+// when the last of them is destroyed.
+struct SharedBlock {
+    void *p = nullptr;
+    size_t bytes = 0;
+    int device = 0;
+    ~SharedBlock()
+    {
+        if (p) pool_free(p, bytes, device);
+    }
+};
 
 template <class T>
 hipError_t upload(DevBuf &b, const std::vector<T> &v, hipStream_t s)
@@ -132,6 +164,7 @@ struct lofp_circuit_s {
     DevBuf d_S, d_lo, d_hi, d_inf, d_C, d_E, d_count, d_slot_stage, d_off, d_coff, d_fa, d_fb, d_ba, d_bb;
     DevBuf d_levels, d_tab_mid, d_counters, d_T, d_out, d_ws, d_cfg, d_rankb;
     DevBuf d_ktab, d_kslot, d_kof, d_krep, d_kcnt, d_khull, d_klohi, d_kinf, d_jobs, d_kstate;
+    std::vector<std::shared_ptr<lofp::host::SharedBlock>> blocks;   // pooled set-up blocks in use
     int32_t *h_pin = nullptr;              // small pinned readback buffer
     bool ktab_clean = false;               // key hash table known to be empty
     std::vector<int32_t> S_dev;            // the S now held in d_S
@@ -172,6 +205,7 @@ lofp_status check_S(const lofp_circuit_s &c, const int32_t *S, int &n);
 void s_only_bounds(const lofp_circuit_s &c, const int32_t *S, int n, std::vector<int16_t> &lo,
                    std::vector<int16_t> &hi);
 lofp_status device_init(lofp_circuit_s &c, int n, hipStream_t s);
+lofp_status init_circuits(const std::vector<std::pair<lofp_circuit_s *, int>> &list, hipStream_t s);
 lofp_status prepare_program(lofp_circuit_s &c, hipStream_t s);
 void build_program(lofp_circuit_s &c);
 SplitProgram *get_split(lofp_circuit_s &c, int rs);

@@ -11,20 +11,20 @@ namespace lofp {
 // cut, one lane per cut) until nothing changes.
 constexpr int kBoundsLds = 4096;   // int16 entries per array: (D+1)(m-1) <= 4096
 
-__global__ __launch_bounds__(64) void k_bounds(int B, int m, int D, int n, const int32_t *__restrict__ S,
-                                               const int32_t *__restrict__ T, const int8_t *__restrict__ fr_lo,
-                                               const int8_t *__restrict__ fr_hi, const int8_t *__restrict__ br_lo,
-                                               const int8_t *__restrict__ br_hi, const uint8_t *__restrict__ cut_gate,
-                                               int16_t *__restrict__ lo, int16_t *__restrict__ hi,
-                                               int32_t *__restrict__ infeasible)
+// Bounds of one pattern by one 64-thread wave: light cones into LDS, then
+// row and column passes until nothing changes (a wave vote decides).  S and
+// Tp: this pattern's input and output; results to Lg/Hg and *inf.
+__device__ void bounds_wave(int m, int D, int n, const int32_t *__restrict__ S, const int32_t *__restrict__ Tp,
+                            const int8_t *__restrict__ fr_lo, const int8_t *__restrict__ fr_hi,
+                            const int8_t *__restrict__ br_lo, const int8_t *__restrict__ br_hi,
+                            const uint8_t *__restrict__ cut_gate, int16_t *__restrict__ Lg, int16_t *__restrict__ Hg,
+                            int32_t *__restrict__ inf)
 {
     __shared__ int16_t L[kBoundsLds], H[kBoundsLds];
     __shared__ int sS[kMaxModes], sT[kMaxModes];
     __shared__ int s_bad;
-    const int p = blockIdx.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const int nc = m - 1, span = (D + 1) * nc;
-    const int32_t *Tp = T + (int64_t)p * m;
-    int16_t *Lg = lo + (int64_t)p * span, *Hg = hi + (int64_t)p * span;
     if (tid == 0) {
         int nT = 0, bad = 0;
         for (int i = 0; i < m; ++i) { nT += Tp[i]; bad |= Tp[i] < 0; sS[i] = S[i]; sT[i] = Tp[i]; }
@@ -33,7 +33,7 @@ __global__ __launch_bounds__(64) void k_bounds(int B, int m, int D, int n, const
     __syncthreads();
     if (s_bad) {
         for (int i = tid; i < span; i += 64) { Lg[i] = 1; Hg[i] = 0; }
-        if (tid == 0) infeasible[p] = 1;
+        if (tid == 0) *inf = 1;
         return;
     }
     for (int i = tid; i < span; i += 64) {
@@ -89,7 +89,20 @@ __global__ __launch_bounds__(64) void k_bounds(int B, int m, int D, int n, const
     }
     if (bad) atomicOr(&s_bad, 1);
     __syncthreads();
-    if (tid == 0) infeasible[p] = s_bad;
+    if (tid == 0) *inf = s_bad;
+}
+
+__global__ __launch_bounds__(64) void k_bounds(int B, int m, int D, int n, const int32_t *__restrict__ S,
+                                               const int32_t *__restrict__ T, const int8_t *__restrict__ fr_lo,
+                                               const int8_t *__restrict__ fr_hi, const int8_t *__restrict__ br_lo,
+                                               const int8_t *__restrict__ br_hi, const uint8_t *__restrict__ cut_gate,
+                                               int16_t *__restrict__ lo, int16_t *__restrict__ hi,
+                                               int32_t *__restrict__ infeasible)
+{
+    const int p = blockIdx.x;
+    const int span = (D + 1) * (m - 1);
+    bounds_wave(m, D, n, S, T + (int64_t)p * m, fr_lo, fr_hi, br_lo, br_hi, cut_gate, lo + (int64_t)p * span,
+                hi + (int64_t)p * span, infeasible + p);
 }
 
 // Fallback for circuits with more than 4096 (time, cut) entries: one thread
@@ -132,13 +145,18 @@ hipError_t launch_bounds(int B, int m, int D, int n, const int32_t *S, const int
     return hipGetLastError();
 }
 
-// One thread per job of a multi-circuit batch.
-__global__ void k_bounds_multi(int count, const BoundsJob *__restrict__ jobs)
+// One wave per job of a multi-circuit batch (a job whose (time, cut) grid
+// exceeds the LDS arrays is propagated by one thread on global memory).
+__global__ __launch_bounds__(64) void k_bounds_multi(int count, const BoundsJob *__restrict__ jobs)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    const BoundsJob j = jobs[i];
+    const BoundsJob j = jobs[blockIdx.x];
     const int nc = j.m - 1, span = (j.D + 1) * nc;
+    if (span <= kBoundsLds) {
+        bounds_wave(j.m, j.D, j.n, j.S, j.T, j.fr_lo, j.fr_hi, j.br_lo, j.br_hi, j.cut_gate, j.lo, j.hi,
+                    j.infeasible);
+        return;
+    }
+    if (threadIdx.x != 0) return;
     int nT = 0, bad = 0;
     for (int k = 0; k < j.m; ++k) { nT += j.T[k]; bad |= j.T[k] < 0; }
     if (bad || nT != j.n) {
@@ -153,7 +171,7 @@ __global__ void k_bounds_multi(int count, const BoundsJob *__restrict__ jobs)
 hipError_t launch_bounds_multi(int count, const BoundsJob *jobs, hipStream_t stream)
 {
     if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bounds_multi, dim3((count + 63) / 64), dim3(64), 0, stream, count, jobs);
+    hipLaunchKernelGGL(k_bounds_multi, dim3(count), dim3(64), 0, stream, count, jobs);
     return hipGetLastError();
 }
 

@@ -46,6 +46,7 @@ struct Req {
     int64_t est = 1;        // contraction state bound (entries), from the S-side intervals
     uint64_t ticket = 0;
     double t_submit = 0;
+    bool planned = false;
 };
 
 // Workspace bytes of one request (bounds + contraction state if global).
@@ -55,8 +56,8 @@ size_t req_bytes(const Req &r)
     return (size_t)(c.D + 1) * c.nc * 4 + 64 + (size_t)2 * r.est * sizeof(double2);
 }
 
-// Prepare a request on the host: S-side state bound of the circuit's program.
-lofp_status plan_request(Req &r)
+// Cheap validation of a request (the submitter's thread).
+lofp_status check_request(Req &r)
 {
     lofp_circuit_s &c = *r.c;
     if ((int)r.S.size() != c.m || (int)r.T.size() != c.m) return fail(LOFP_EINVAL, "S/T length");
@@ -64,6 +65,17 @@ lofp_status plan_request(Req &r)
     if (rc != LOFP_OK) return rc;
     for (int v : r.T)
         if (v < 0) return fail(LOFP_EINVAL, "negative occupation in T");
+    return LOFP_OK;
+}
+
+// Prepare a request on the host: the circuit's program and the contraction
+// state bound from this request's exact intervals.
+lofp_status plan_request(Req &r)
+{
+    lofp_status rc = check_request(r);
+    if (rc != LOFP_OK) return rc;
+    r.planned = true;
+    lofp_circuit_s &c = *r.c;
     std::lock_guard<std::mutex> lk(c.mu);
     if (!c.prog_built) build_program(c);
     if (!c.prog_error.empty()) return fail(LOFP_ENOTSUP, c.prog_error);
@@ -113,17 +125,29 @@ lofp_status launch_batch(Batch &b, int fp32)
 {
     const int count = (int)b.reqs.size();
     hipStream_t s = b.s;
-    // circuits: resident tables and programs (first use uploads them on this
-    // stream; later users on other streams wait for that upload)
-    for (Req &r : b.reqs) {
-        lofp_circuit_s &c = *r.c;
-        std::lock_guard<std::mutex> lk(c.mu);
-        lofp_status rc = device_init(c, r.n, s);
+    // circuits: resident tables and programs.  The batch's new circuits are
+    // set up together (one pooled block, one copy, one table launch) on this
+    // stream; later users on other streams wait for that set-up.  Circuit
+    // locks are taken in address order.
+    {
+        std::vector<lofp_circuit_s *> cs;
+        for (Req &r : b.reqs) cs.push_back(r.c);
+        std::sort(cs.begin(), cs.end());
+        cs.erase(std::unique(cs.begin(), cs.end()), cs.end());
+        std::vector<std::unique_lock<std::mutex>> locks;
+        locks.reserve(cs.size());
+        for (lofp_circuit_s *c : cs) locks.emplace_back(c->mu);
+        std::vector<std::pair<lofp_circuit_s *, int>> need;
+        need.reserve(b.reqs.size());
+        for (Req &r : b.reqs) need.emplace_back(r.c, r.n);
+        lofp_status rc = init_circuits(need, s);
         if (rc != LOFP_OK) return rc;
-        rc = prepare_program(c, s);
-        if (rc != LOFP_OK) return rc;
-        rc = ready_on_stream(c, s);
-        if (rc != LOFP_OK) return rc;
+        for (lofp_circuit_s *c : cs) {
+            rc = prepare_program(*c, s);
+            if (rc != LOFP_OK) return rc;
+            rc = ready_on_stream(*c, s);
+            if (rc != LOFP_OK) return rc;
+        }
     }
     // pack S, T and the per-request offsets
     std::vector<int32_t> ST;
@@ -216,9 +240,15 @@ lofp_status launch_batch(Batch &b, int fp32)
 struct lofp_server_s {
     lofp_server_opts o{};
     std::mutex mu;
-    std::condition_variable cv;
-    std::deque<Req> queue;
+    std::condition_variable cv;            // results: completions
+    std::condition_variable cv_plan;       // planners: submissions
+    std::condition_variable cv_launch;     // launcher: planned requests
+    std::deque<Req> queue;                 // submitted, not yet planned
+    std::deque<Req> ready;                 // planned, waiting for a launch
+    int planning = 0;                      // requests being planned now
+    std::vector<std::thread> planners;
     std::unordered_map<uint64_t, std::pair<lofp_c128, double>> done;   // ticket -> (amp, latency)
+    std::unordered_map<uint64_t, std::pair<lofp_status, std::string>> failed;   // ticket -> planning error
     std::vector<double> latencies;
     std::vector<std::unique_ptr<Batch>> batches;
     uint64_t next_ticket = 1;
@@ -263,24 +293,25 @@ void worker_loop(lofp_server_s *sv)
         std::vector<Req> take;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
-            if (sv->stop && sv->queue.empty()) {
+            if (sv->stop && sv->queue.empty() && sv->ready.empty() && sv->planning == 0) {
                 bool any = false;
                 for (auto &bp : sv->batches) any |= bp->busy;
                 if (!any) return;
             }
-            if (!free_b || sv->queue.empty()) {
-                // nothing to launch: wait briefly for arrivals or completions
-                sv->cv.wait_for(lk, std::chrono::microseconds(20));
+            if (!free_b || sv->ready.empty()) {
+                // nothing to launch: wait briefly for planned arrivals or completions
+                sv->cv_launch.wait_for(lk, std::chrono::microseconds(20));
                 continue;
             }
-            // admission: arrivals so far, up to max_batch and the memory budget
+            // admission: planned arrivals so far, up to max_batch and the
+            // memory budget (at least one request)
             size_t bytes = 0;
-            while (!sv->queue.empty() && (int)take.size() < sv->o.max_batch) {
-                const size_t rb = req_bytes(sv->queue.front());
+            while (!sv->ready.empty() && (int)take.size() < sv->o.max_batch) {
+                const size_t rb = req_bytes(sv->ready.front());
                 if (!take.empty() && sv->inflight_bytes + bytes + rb > (size_t)sv->o.memory_budget) break;
                 bytes += rb;
-                take.push_back(std::move(sv->queue.front()));
-                sv->queue.pop_front();
+                take.push_back(std::move(sv->ready.front()));
+                sv->ready.pop_front();
             }
             sv->inflight_bytes += bytes;
             free_b->bytes = bytes;
@@ -300,6 +331,35 @@ void worker_loop(lofp_server_s *sv)
             free_b->busy = false;
             sv->cv.notify_all();
         }
+    }
+}
+
+// Planner threads: requests are planned on the host (program, exact
+// intervals, state bound) off the submitters' and the launcher's threads; a
+// request that cannot run completes with its error.
+void planner_loop(lofp_server_s *sv)
+{
+    for (;;) {
+        Req r;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            sv->cv_plan.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
+            if (sv->queue.empty()) return;   // stopping and nothing left
+            r = std::move(sv->queue.front());
+            sv->queue.pop_front();
+            sv->planning++;
+        }
+        const lofp_status rc = plan_request(r);
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->planning--;
+        if (rc == LOFP_OK) {
+            sv->ready.push_back(std::move(r));
+        } else {
+            sv->failed[r.ticket] = {rc, lofp_last_error()};
+            sv->completed++;
+            sv->cv.notify_all();
+        }
+        sv->cv_launch.notify_one();
     }
 }
 
@@ -374,6 +434,7 @@ lofp_status lofp_server_create(const lofp_server_opts *o, lofp_server *out)
         }
         sv->batches.push_back(std::move(b));
     }
+    for (int i = 0; i < 2; ++i) sv->planners.emplace_back(planner_loop, sv);
     sv->worker = std::thread(worker_loop, sv);
     *out = sv;
     return LOFP_OK;
@@ -386,7 +447,7 @@ lofp_status lofp_server_submit(lofp_server sv, lofp_circuit c, const int32_t *S,
     r.c = c;
     r.S.assign(S, S + c->m);
     r.T.assign(T, T + c->m);
-    lofp_status rc = plan_request(r);
+    lofp_status rc = check_request(r);   // planning happens on the worker
     if (rc != LOFP_OK) return rc;
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->stop) return fail(LOFP_EINVAL, "server is stopping");
@@ -395,7 +456,7 @@ lofp_status lofp_server_submit(lofp_server sv, lofp_circuit c, const int32_t *S,
     *ticket = r.ticket;
     sv->queue.push_back(std::move(r));
     sv->submitted++;
-    sv->cv.notify_all();
+    sv->cv_plan.notify_one();
     return LOFP_OK;
 }
 
@@ -406,6 +467,14 @@ lofp_status lofp_server_result(lofp_server sv, uint64_t ticket, int32_t wait, lo
     std::unique_lock<std::mutex> lk(sv->mu);
     if (ticket == 0 || ticket >= sv->next_ticket) return fail(LOFP_EINVAL, "unknown ticket");
     for (;;) {
+        auto fi = sv->failed.find(ticket);
+        if (fi != sv->failed.end()) {
+            const lofp_status st = fi->second.first;
+            const std::string msg = fi->second.second;
+            sv->failed.erase(fi);
+            *done = 1;
+            return fail(st, msg);
+        }
         auto it = sv->done.find(ticket);
         if (it != sv->done.end()) {
             if (it->second.second < 0) {
@@ -455,7 +524,11 @@ lofp_status lofp_server_destroy(lofp_server sv)
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->stop = true;
         sv->cv.notify_all();
+        sv->cv_plan.notify_all();
+        sv->cv_launch.notify_all();
     }
+    for (auto &t : sv->planners)
+        if (t.joinable()) t.join();
     if (sv->worker.joinable()) sv->worker.join();
     for (auto &b : sv->batches) {
         if (b->s) (void)hipStreamSynchronize(b->s);
