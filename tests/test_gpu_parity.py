@@ -342,3 +342,72 @@ def test_split_contraction_invalid_rows_and_no_sharing():
     got3 = c3.amplitudes(wl3.S, wl3.Ts, lofp.make_opts(method=lofp.METHOD_CONTRACT), st3)
     assert st3.split_top_keys == 0
     check(got3[:64], oracle_amps(wl3.m, wl3.S, wl3.Ts[:64], wl3.layers))
+
+
+def _brickwork(m, depth, seed):
+    rng = np.random.default_rng(seed)
+    layers = []
+    for l in range(depth):
+        layers.append([(a, a + 1, float(rng.uniform(0, np.pi / 2)), float(rng.uniform(0, 2 * np.pi)))
+                       for a in range(l % 2, m - 1, 2)])
+    return layers
+
+
+def test_server_reports_planning_errors_per_request():
+    """A request the contraction cannot take (too many live cut versions)
+    completes with its own error; the requests around it are unaffected."""
+    good = _served(6, seed=11)
+    bad_layers = _brickwork(8, 40, seed=12)
+    bad = lofp.Circuit(8, bad_layers)
+    S = np.array([1, 1, 1, 1, 0, 0, 0, 0], dtype=np.int32)
+    T = np.array([0, 0, 0, 0, 1, 1, 1, 1], dtype=np.int32)
+    srv = lofp.Server(max_batch=8, streams=2)
+    try:
+        t_good = [srv.submit(c, r.S, r.T) for c, r in good]
+        t_bad = srv.submit(bad, S, T)
+        res = [srv.result(t) for t in t_good]
+        with pytest.raises(lofp.LofpError) as ei:
+            srv.result(t_bad)
+        assert ei.value.status == lofp.ENOTSUP
+    finally:
+        srv.close()
+    want = lofp.amplitudes_multi([(c, r.S, r.T) for c, r in good])
+    for (amp, _), w in zip(res, want):
+        assert amp == w
+    # the single-circuit call still answers it, by the path sum
+    a = bad.amplitudes(S, T[None, :])
+    assert abs(a[0] - oracle.amplitude(8, S, T, flat(bad_layers))) <= ATOL
+
+
+def test_circuit_setup_memory_is_reused_and_tables_grow():
+    """Circuits set up together share pooled device blocks that are reused
+    after the circuits go away; a circuit first used with few photons gets
+    larger tables when a later call brings more."""
+    for rnd in range(3):
+        items = _served(40, seed=20 + rnd)
+        got = lofp.amplitudes_multi([(c, r.S, r.T) for c, r in items])
+        for i in (0, 17, 39):
+            c, r = items[i]
+            assert abs(got[i] - oracle.amplitude(r.m, r.S, r.T, flat(r.layers))) <= ATOL
+        del items, got
+    layers = _brickwork(10, 6, seed=30)
+    c = lofp.Circuit(10, layers)
+    for S in (np.array([1, 0, 1, 0, 0, 0, 0, 0, 0, 0]), np.array([1, 1, 1, 1, 1, 1, 0, 0, 0, 0]),
+              np.array([2, 0, 2, 0, 2, 0, 1, 0, 0, 0])):
+        S = S.astype(np.int32)
+        n = int(S.sum())
+        Ts = np.array([p for p in oracle.all_patterns(10, n)][:64], dtype=np.int32)
+        got = c.amplitudes(S, Ts, lofp.make_opts(method=lofp.METHOD_CONTRACT))
+        check(got, oracle_amps(10, S, Ts, layers))
+
+
+def test_count_work_only_counts():
+    """Counting the work done changes no result bit; without it the counter
+    stays zero."""
+    wl = workloads.make("c2", seed=2, batch=512)
+    c = lofp.Circuit(wl.m, wl.layers)
+    st0, st1 = lofp.Stats(), lofp.Stats()
+    a = c.amplitudes(wl.S, wl.Ts, lofp.make_opts(method=lofp.METHOD_CONTRACT), st0)
+    b = c.amplitudes(wl.S, wl.Ts, lofp.make_opts(method=lofp.METHOD_CONTRACT, count_work=True), st1)
+    assert np.array_equal(a, b)
+    assert st0.transitions == 0 and st1.transitions > 0
