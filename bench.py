@@ -301,7 +301,7 @@ def serve_variant(lofp, workloads, n_req=2000, n_warm=200, rate_frac=0.5):
                 time.sleep(delay)
             tk.append(srv.submit(c, r.S, r.T))
         for i, t in enumerate(tk):
-            amp, lat = srv.result(t)
+            amp, lat, _ = srv.result(t)
             if i >= n_warm:
                 lats.append(lat)
         wall = time.perf_counter() - t0

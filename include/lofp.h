@@ -92,6 +92,9 @@ typedef struct {
                                  (stats->transitions); the counting kernels
                                  run slower, so timed calls leave it 0       */
     int32_t reserved;
+    double fp32_rtol;         /* multi-circuit FP32 form: a result whose
+                                 rounding bound exceeds fp32_rtol * |amp| is
+                                 recomputed in FP64 (0 = 1e-6)               */
 } lofp_opts;
 
 /* Per-call statistics (filled when a non-null pointer is passed). */
@@ -201,12 +204,24 @@ typedef struct {
 /* Amplitudes of `count` requests evaluated by the mode-axis contraction
  * (Sec. II.C) in one bounds launch and one contraction launch on `stream`;
  * each circuit's tables and step program stay resident on the device.  out:
- * host lofp_c128[count].  opts: precision (FP64 or FP32 products; sums stay
- * FP64) and record_timing; method must be AUTO or CONTRACT.  Synchronises
- * `stream`.  Errors: EINVAL for null fields or bad occupations, ENOTSUP for a
- * circuit the contraction cannot take, ENOMEM past 2^22 state entries. */
+ * host lofp_c128[count].  opts: precision and record_timing; method must be
+ * AUTO or CONTRACT.  Synchronises `stream`.
+ *
+ * Precision FP32: transition products in FP32, sums in FP64, and for every
+ * result a rounding bound |amp - exact| <= ((1 + f)^G - 1 + 2^-51) A_abs,
+ * exact meaning the same sum in exact arithmetic over the FP64 tables; G is
+ * the circuit's splitter count, A_abs the sum over paths of the products of
+ * |Re W| + |Im W| (computed by a second, absolute pass), and
+ * f = 4u/(1 - 4u) + (2(n+1)^2 + 2) 2^-53 with u = 2^-24 (about 4 G u A_abs).
+ * A result whose bound exceeds opts->fp32_rtol * |amp| is recomputed in FP64
+ * (its bound then has f = (2(n+1)^2 + 2) 2^-53).  The bound assumes no FP32
+ * underflow.  err_bound (host double[count], may be NULL) receives each
+ * result's bound; NaN for the FP64 form, which computes none.
+ *
+ * Errors: EINVAL for null fields or bad occupations, ENOTSUP for a circuit
+ * the contraction cannot take, ENOMEM past 2^22 state entries. */
 lofp_status lofp_amplitudes_multi(int32_t count, const lofp_request *req, lofp_c128 *out,
-                                  const lofp_opts *opts, void *stream, lofp_stats *stats);
+                                  double *err_bound, const lofp_opts *opts, void *stream, lofp_stats *stats);
 
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of amplitude requests.
@@ -222,14 +237,18 @@ typedef struct {
     int32_t max_batch;      /* requests per launch (default 256)              */
     int32_t streams;        /* batches in flight, one HIP stream each (2, <=8) */
     int64_t memory_budget;  /* device workspace bytes admitted at once (1 GiB) */
-    int32_t precision;      /* LOFP_PREC_* for every request                   */
-    int32_t reserved[3];
+    int32_t precision;      /* LOFP_PREC_* for every request; FP32 results
+                               carry bounds and fall back to FP64 as in
+                               lofp_amplitudes_multi                          */
+    int32_t reserved;
+    double fp32_rtol;       /* the fallback threshold (0 = 1e-6)              */
 } lofp_server_opts;
 
 typedef struct {
     int64_t submitted, completed, launches;
     double mean_batch;      /* requests per launch                            */
     double p50_ms, p99_ms, max_ms;   /* submit-to-completion latency          */
+    int64_t fp64_fallbacks; /* FP32 results recomputed in FP64                */
 } lofp_server_stats;
 
 /* Start a server on the current device (opts may be NULL). */
@@ -240,12 +259,13 @@ lofp_status lofp_server_create(const lofp_server_opts *opts, lofp_server *out);
  * lofp_server_result. */
 lofp_status lofp_server_submit(lofp_server s, lofp_circuit c, const int32_t *S, const int32_t *T,
                                uint64_t *ticket);
-/* *done = 1 and out / latency_ms filled (either may be NULL) once the ticket
- * has completed; wait = 1 blocks until then.  A completed ticket is
- * consumed.  EDEVICE if its batch failed; the planning error (ENOTSUP,
- * ENOMEM) if the request could not run. */
+/* *done = 1 and out / latency_ms / err_bound filled (any may be NULL) once
+ * the ticket has completed; wait = 1 blocks until then.  err_bound: the
+ * result's rounding bound (FP32 form and its FP64 fallbacks; NaN for the
+ * FP64 form).  A completed ticket is consumed.  EDEVICE if its batch failed;
+ * the planning error (ENOTSUP, ENOMEM) if the request could not run. */
 lofp_status lofp_server_result(lofp_server s, uint64_t ticket, int32_t wait, lofp_c128 *out,
-                               double *latency_ms, int32_t *done);
+                               double *latency_ms, double *err_bound, int32_t *done);
 lofp_status lofp_server_get_stats(lofp_server s, lofp_server_stats *out);
 /* Finish every queued request, stop the worker and free the server. */
 lofp_status lofp_server_destroy(lofp_server s);

@@ -255,6 +255,27 @@ def path_count_bruteforce(m: int, S, T, circuit) -> int:
     return counts.get(tuple(int(t) for t in T), 0)
 
 
+def absolute_form(m: int, S, T, circuit) -> float:
+    """Sum over the valid paths of Eq. (1) of the product of |Re W| + |Im W|
+    of each splitter's transition amplitude: the scale against which the
+    rounding of path products is bounded.  Same dictionary evolution as
+    :func:`evolve`, with the 1-norm of each weight; small m and n only."""
+    state: Dict[Tuple[int, ...], float] = {tuple(int(s) for s in S): 1.0}
+    for (a, b, th, ph) in circuit:
+        new: Dict[Tuple[int, ...], float] = {}
+        for conf, w in state.items():
+            x1, x2 = conf[a], conf[b]
+            N = x1 + x2
+            for y1 in range(N + 1):
+                t = bs_amplitude(th, ph, x1, x2, y1, N - y1)
+                c = list(conf)
+                c[a], c[b] = y1, N - y1
+                c = tuple(c)
+                new[c] = new.get(c, 0.0) + w * (abs(t.real) + abs(t.imag))
+        state = new
+    return state.get(tuple(int(t) for t in T), 0.0)
+
+
 def all_patterns(m: int, n: int) -> List[Tuple[int, ...]]:
     """Every occupation tuple of n photons in m modes (C(m+n-1, n) of them)."""
     out: List[Tuple[int, ...]] = []

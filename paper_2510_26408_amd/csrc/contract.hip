@@ -218,7 +218,12 @@ __device__ __forceinline__ void step_entries(const StepDesc &d, const double2 *_
         // one transition: acc += prev * W[wi] (an invalid one reads the zero slot)
         auto visit = [&](const double2 prev, bool ok, unsigned wi) {
             if (STATS && ok && (prev.x != 0.0 || prev.y != 0.0)) ++trans;
-            if (COUNT) {
+            if (COUNT && F32) {
+                // absolute form: states hold sums of |path weight|, each
+                // transition weighs |Re W| + |Im W| >= |W|
+                const unsigned wo = 2u * (ok ? wi : zslot);
+                acc.x += prev.x * (fabs(W[wo]) + fabs(W[wo + 1]));
+            } else if (COUNT) {
                 acc.x += ok ? prev.x : 0.0;
             } else {
                 const unsigned wo = 2u * (ok ? wi : zslot);
@@ -422,7 +427,9 @@ __global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
 // run three jobs (24 waves) per CU.
 template <int BS> constexpr int multi_waves_per_simd() { return BS >= 512 ? 6 : 1; }
 
-template <bool F32, bool LDS_STATE, int BS, bool STATS>
+// ABS: the absolute form (sum over paths of the product of |Re W| + |Im W|),
+// which bounds the rounding error of the FP32-product form.
+template <bool F32, bool LDS_STATE, int BS, bool STATS, bool ABS>
 __global__ __launch_bounds__(BS, multi_waves_per_simd<BS>()) void k_contract_multi(const ContractJob *__restrict__ jobs,
                                                        unsigned long long *stat_transitions, int32_t *overflow,
                                                        MultiOverride ov)
@@ -442,13 +449,13 @@ __global__ __launch_bounds__(BS, multi_waves_per_simd<BS>()) void k_contract_mul
         // per-job choice: the state in LDS when this job's largest state fits
         if (job_max_state<BS>(j, smem) <= ov.lds_states) {
             j.max_states = ov.lds_states;
-            contract_run<false, F32, true, BS, STATS>(j, smem, stat_transitions, overflow);
+            contract_run<ABS, F32 || ABS, true, BS, STATS>(j, smem, stat_transitions, overflow);
         } else {
-            contract_run<false, F32, false, BS, STATS>(j, smem, stat_transitions, overflow);
+            contract_run<ABS, F32 || ABS, false, BS, STATS>(j, smem, stat_transitions, overflow);
         }
         return;
     }
-    contract_run<false, F32, LDS_STATE, BS, STATS>(j, smem, stat_transitions, overflow);
+    contract_run<ABS, F32 || ABS, LDS_STATE, BS, STATS>(j, smem, stat_transitions, overflow);
 }
 
 // Largest state of each job's program under its intervals.
@@ -651,35 +658,39 @@ hipError_t launch_contract(const ContractArgs &a, hipStream_t stream)
 
 template <bool F32, bool LDS_STATE>
 static void launch_multi_t(int count, const ContractJob *jobs, size_t dyn, int max_states,
-                           unsigned long long *st, int32_t *ov, MultiOverride o, bool stats, hipStream_t stream)
+                           unsigned long long *st, int32_t *ov, MultiOverride o, bool stats, bool abs,
+                           hipStream_t stream)
 {
     // many small jobs: one wave each; larger jobs: 512 threads, so a step's
     // entries spread thin and the three jobs sharing a CU hide each other's
     // latencies
     const bool wide = contract_block_size(max_states) != 64;
     const dim3 g(count);
-    if (stats) {
-        if (wide) hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 512, true>), g, dim3(512), dyn, stream, jobs, st, ov, o);
-        else hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 64, true>), g, dim3(64), dyn, stream, jobs, st, ov, o);
+    if (abs) {
+        if (wide) hipLaunchKernelGGL((k_contract_multi<true, LDS_STATE, 512, false, true>), g, dim3(512), dyn, stream, jobs, st, ov, o);
+        else hipLaunchKernelGGL((k_contract_multi<true, LDS_STATE, 64, false, true>), g, dim3(64), dyn, stream, jobs, st, ov, o);
+    } else if (stats) {
+        if (wide) hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 512, true, false>), g, dim3(512), dyn, stream, jobs, st, ov, o);
+        else hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 64, true, false>), g, dim3(64), dyn, stream, jobs, st, ov, o);
     } else {
-        if (wide) hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 512, false>), g, dim3(512), dyn, stream, jobs, st, ov, o);
-        else hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 64, false>), g, dim3(64), dyn, stream, jobs, st, ov, o);
+        if (wide) hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 512, false, false>), g, dim3(512), dyn, stream, jobs, st, ov, o);
+        else hipLaunchKernelGGL((k_contract_multi<F32, LDS_STATE, 64, false, false>), g, dim3(64), dyn, stream, jobs, st, ov, o);
     }
 }
 
 hipError_t launch_contract_multi(int count, const ContractJob *jobs, size_t lds_bytes, int max_states,
                                  bool state_in_lds, bool fp32, unsigned long long *stat_transitions,
-                                 int32_t *overflow, hipStream_t stream, MultiOverride o, bool stats)
+                                 int32_t *overflow, hipStream_t stream, MultiOverride o, bool stats, bool abs)
 {
     if (count == 0) return hipSuccess;
     if (lds_bytes > max_lds_per_block()) return hipErrorInvalidValue;
     unsigned long long *st = stat_transitions;
     if (fp32) {
-        if (state_in_lds) launch_multi_t<true, true>(count, jobs, lds_bytes, max_states, st, overflow, o, stats, stream);
-        else launch_multi_t<true, false>(count, jobs, lds_bytes, max_states, st, overflow, o, stats, stream);
+        if (state_in_lds) launch_multi_t<true, true>(count, jobs, lds_bytes, max_states, st, overflow, o, stats, abs, stream);
+        else launch_multi_t<true, false>(count, jobs, lds_bytes, max_states, st, overflow, o, stats, abs, stream);
     } else {
-        if (state_in_lds) launch_multi_t<false, true>(count, jobs, lds_bytes, max_states, st, overflow, o, stats, stream);
-        else launch_multi_t<false, false>(count, jobs, lds_bytes, max_states, st, overflow, o, stats, stream);
+        if (state_in_lds) launch_multi_t<false, true>(count, jobs, lds_bytes, max_states, st, overflow, o, stats, abs, stream);
+        else launch_multi_t<false, false>(count, jobs, lds_bytes, max_states, st, overflow, o, stats, abs, stream);
     }
     return hipGetLastError();
 }

@@ -252,7 +252,8 @@ hipError_t launch_bounds_multi(int count, const BoundsJob *jobs, hipStream_t str
 hipError_t launch_contract_multi(int count, const ContractJob *jobs, size_t lds_bytes, int max_states,
                                  bool state_in_lds, bool fp32, unsigned long long *stat_transitions,
                                  int32_t *overflow, hipStream_t stream,
-                                 MultiOverride ov = MultiOverride{0, nullptr, nullptr, 0, 0}, bool stats = false);
+                                 MultiOverride ov = MultiOverride{0, nullptr, nullptr, 0, 0}, bool stats = false,
+                                 bool abs = false);
 // Largest state over the jobs (one thread per job), atomically maxed into *mx.
 hipError_t launch_multi_sizes(int count, const ContractJob *jobs, int *mx, hipStream_t stream);
 

@@ -47,9 +47,39 @@ struct Req {
     uint64_t ticket = 0;
     double t_submit = 0;
     bool planned = false;
+    bool fp64 = false;      // recomputed in FP64 (its FP32 bound was too loose)
+    double abs_form = -1;   // absolute form from the FP32 pass (-1: none)
+};
+
+struct DoneRec {
+    lofp_c128 amp;
+    double latency_ms;      // < 0: the batch failed
+    double err_bound;       // rounding bound of amp (NaN: not computed)
 };
 
 // Workspace bytes of one request (bounds + contraction state if global).
+// Rounding bounds from the absolute form A_abs (the sum over paths of the
+// products of |Re W| + |Im W|, which bounds the 1-norm of every exact state
+// entry by the same sum over that entry's paths).  One step with relative
+// error f per transition term turns an error E of each source entry (relative
+// to its absolute-form value a) into at most (1 + f) E + f a, so after G
+// splitters the error is at most ((1 + f)^G - 1) A_abs.  FP32 products: the
+// source and the weight are each rounded to FP32 and the two products and the
+// sum of each component round again (4 roundings, gamma_4 = 4u/(1 - 4u),
+// u = 2^-24); their FP64 sum over the at most (n+1)^2 transitions into an
+// entry adds (2k + 2) 2^-53.  FP64 (complex FMA chains): (2k + 2) 2^-53 alone.
+// The final compensated sum adds 4 * 2^-53; the last factor covers the
+// rounding of A_abs itself and of this formula.  Values in the FP32 normal
+// range are assumed (an underflowing product adds an absolute 2^-149 or so).
+double rounding_bound(int G, int n, double abs_form, bool fp32)
+{
+    const double k = (double)(n + 1) * (n + 1);
+    const double u = 0x1p-24;
+    const double f = (fp32 ? 4 * u / (1 - 4 * u) : 0.0) + (2 * k + 2) * 0x1p-53;
+    const double grow = std::expm1((double)G * std::log1p(f)) + 4 * 0x1p-53;
+    return grow * abs_form * (1 + 0x1p-30);
+}
+
 size_t req_bytes(const Req &r)
 {
     const lofp_circuit_s &c = *r.c;
@@ -102,7 +132,10 @@ lofp_status plan_request(Req &r)
 struct Batch {
     hipStream_t s = nullptr;
     hipEvent_t ev = nullptr;
-    DevBuf d_ST, d_lohi, d_inf, d_out, d_bj, d_cj, d_ws, d_ctr;
+    DevBuf d_ST, d_lohi, d_inf, d_out, d_bj, d_cj, d_ws, d_ctr, d_abs, d_cja;
+    std::vector<ContractJob> cja;          // jobs of the absolute pass (outputs to d_abs)
+    double *h_abs = nullptr;
+    bool checked = false;                  // FP32 products with per-result bounds
     std::vector<BoundsJob> bj;
     std::vector<ContractJob> cj;
     lofp_c128 *h_out = nullptr;
@@ -113,16 +146,20 @@ struct Batch {
 
     ~Batch()
     {
-        DevBuf *b[] = {&d_ST, &d_lohi, &d_inf, &d_out, &d_bj, &d_cj, &d_ws, &d_ctr};
+        DevBuf *b[] = {&d_ST, &d_lohi, &d_inf, &d_out, &d_bj, &d_cj, &d_ws, &d_ctr, &d_abs, &d_cja};
         for (DevBuf *x : b) release(*x);
         if (h_out) (void)hipHostFree(h_out);
+        if (h_abs) (void)hipHostFree(h_abs);
         if (ev) (void)hipEventDestroy(ev);
     }
 };
 
-// Enqueue one multi-circuit batch on b.s (reqs already planned).
-lofp_status launch_batch(Batch &b, int fp32)
+// Enqueue one multi-circuit batch on b.s (reqs already planned).  checked:
+// FP32 products plus the absolute form of every request, from which each
+// result's rounding bound follows (rounding_bound).
+lofp_status launch_batch(Batch &b, int fp32, bool checked = false)
 {
+    b.checked = checked && fp32;
     const int count = (int)b.reqs.size();
     hipStream_t s = b.s;
     // circuits: resident tables and programs.  The batch's new circuits are
@@ -220,15 +257,34 @@ lofp_status launch_batch(Batch &b, int fp32)
     unsigned long long *ctr = b.d_ctr.as<unsigned long long>();
     HIPCHK(launch_contract_multi(count, b.d_cj.as<ContractJob>(), lds, (int)max_est, in_lds, fp32 != 0, ctr,
                                  reinterpret_cast<int32_t *>(ctr + 1), s));
+    if (b.checked) {
+        // the absolute form: same jobs, FP64, outputs to d_abs
+        HIPCHK(ensure(b.d_abs, count * sizeof(double2)));
+        b.cja = b.cj;
+        for (int i = 0; i < count; ++i) {
+            b.cja[i].out = b.d_abs.as<double2>() + i;
+            b.cja[i].fp32 = 0;
+        }
+        HIPCHK(upload(b.d_cja, b.cja, s));
+        HIPCHK(launch_contract_multi(count, b.d_cja.as<ContractJob>(), lds, (int)max_est, in_lds, false, ctr,
+                                     reinterpret_cast<int32_t *>(ctr + 1), s, MultiOverride{0, nullptr, nullptr, 0, 0},
+                                     false, true));
+    }
     if (b.h_cap < (size_t)count) {
         if (b.h_out) (void)hipHostFree(b.h_out);
+        if (b.h_abs) (void)hipHostFree(b.h_abs);
         b.h_out = nullptr;
+        b.h_abs = nullptr;
         b.h_cap = 0;
         HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&b.h_out), std::max(count, 256) * sizeof(lofp_c128),
+                             hipHostMallocDefault));
+        HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&b.h_abs), std::max(count, 256) * sizeof(double) * 2,
                              hipHostMallocDefault));
         b.h_cap = std::max(count, 256);
     }
     HIPCHK(hipMemcpyAsync(b.h_out, b.d_out.p, count * sizeof(lofp_c128), hipMemcpyDeviceToHost, s));
+    if (b.checked)
+        HIPCHK(hipMemcpyAsync(b.h_abs, b.d_abs.p, count * 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     if (!b.ev) HIPCHK(hipEventCreateWithFlags(&b.ev, hipEventDisableTiming));
     HIPCHK(hipEventRecord(b.ev, s));
     return LOFP_OK;
@@ -247,7 +303,8 @@ struct lofp_server_s {
     std::deque<Req> ready;                 // planned, waiting for a launch
     int planning = 0;                      // requests being planned now
     std::vector<std::thread> planners;
-    std::unordered_map<uint64_t, std::pair<lofp_c128, double>> done;   // ticket -> (amp, latency)
+    std::unordered_map<uint64_t, DoneRec> done;
+    int64_t fp64_fallbacks = 0;
     std::unordered_map<uint64_t, std::pair<lofp_status, std::string>> failed;   // ticket -> planning error
     std::vector<double> latencies;
     std::vector<std::unique_ptr<Batch>> batches;
@@ -265,13 +322,32 @@ namespace {
 void complete_batch(lofp_server_s &sv, Batch &b)
 {
     const double t = now_ms();
+    const double rtol = sv.o.fp32_rtol > 0 ? sv.o.fp32_rtol : 1e-6;
     std::lock_guard<std::mutex> lk(sv.mu);
+    int64_t finished = 0;
     for (size_t i = 0; i < b.reqs.size(); ++i) {
-        const double lat = t - b.reqs[i].t_submit;
-        sv.done[b.reqs[i].ticket] = {b.h_out[i], lat};
+        Req &r = b.reqs[i];
+        const lofp_c128 a = b.h_out[i];
+        double bound = std::nan("");
+        if (b.checked) {
+            r.abs_form = b.h_abs[2 * i];
+            bound = rounding_bound(r.c->G, r.n, r.abs_form, true);
+            if (bound > rtol * std::hypot(a.re, a.im)) {
+                // the FP32 form cannot certify this result: recompute in FP64
+                r.fp64 = true;
+                sv.fp64_fallbacks++;
+                sv.ready.push_front(std::move(r));
+                continue;
+            }
+        } else if (r.fp64 && r.abs_form >= 0) {
+            bound = rounding_bound(r.c->G, r.n, r.abs_form, false);
+        }
+        const double lat = t - r.t_submit;
+        sv.done[r.ticket] = {a, lat, bound};
         sv.latencies.push_back(lat);
+        ++finished;
     }
-    sv.completed += (int64_t)b.reqs.size();
+    sv.completed += finished;
     sv.inflight_bytes -= b.bytes;
     b.reqs.clear();
     b.busy = false;
@@ -306,7 +382,8 @@ void worker_loop(lofp_server_s *sv)
             // admission: planned arrivals so far, up to max_batch and the
             // memory budget (at least one request)
             size_t bytes = 0;
-            while (!sv->ready.empty() && (int)take.size() < sv->o.max_batch) {
+            const bool run_fp64 = sv->ready.front().fp64;   // a batch has one precision
+            while (!sv->ready.empty() && (int)take.size() < sv->o.max_batch && sv->ready.front().fp64 == run_fp64) {
                 const size_t rb = req_bytes(sv->ready.front());
                 if (!take.empty() && sv->inflight_bytes + bytes + rb > (size_t)sv->o.memory_budget) break;
                 bytes += rb;
@@ -318,13 +395,14 @@ void worker_loop(lofp_server_s *sv)
         }
         free_b->reqs = std::move(take);
         free_b->busy = true;
-        lofp_status rc = launch_batch(*free_b, sv->o.precision == LOFP_PREC_FP32);
+        const bool fp32 = sv->o.precision == LOFP_PREC_FP32 && !free_b->reqs.front().fp64;
+        lofp_status rc = launch_batch(*free_b, fp32, fp32);
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->launches++;
         sv->launched_reqs += (int64_t)free_b->reqs.size();
         if (rc != LOFP_OK) {
             sv->error = lofp_last_error();
-            for (const Req &r : free_b->reqs) sv->done[r.ticket] = {lofp_c128{NAN, NAN}, -1.0};
+            for (const Req &r : free_b->reqs) sv->done[r.ticket] = {lofp_c128{NAN, NAN}, -1.0, NAN};
             sv->completed += (int64_t)free_b->reqs.size();
             sv->inflight_bytes -= free_b->bytes;
             free_b->reqs.clear();
@@ -367,14 +445,16 @@ void planner_loop(lofp_server_s *sv)
 
 extern "C" {
 
-lofp_status lofp_amplitudes_multi(int32_t count, const lofp_request *req, lofp_c128 *out, const lofp_opts *opts,
-                                  void *stream, lofp_stats *stats)
+lofp_status lofp_amplitudes_multi(int32_t count, const lofp_request *req, lofp_c128 *out, double *err_bound,
+                                  const lofp_opts *opts, void *stream, lofp_stats *stats)
 {
     if (count < 0) return fail(LOFP_EINVAL, "negative count");
     if (count > 0 && (!req || !out)) return fail(LOFP_EINVAL, "null requests or out");
     if (opts && opts->method == LOFP_METHOD_PATHSUM) return fail(LOFP_ENOTSUP, "multi-circuit batches use the contraction");
     if (stats) { std::memset(stats, 0, sizeof(*stats)); stats->batch = count; stats->method_used = LOFP_METHOD_CONTRACT; }
     if (count == 0) return LOFP_OK;
+    const bool fp32 = opts && opts->precision == LOFP_PREC_FP32;
+    const double rtol = opts && opts->fp32_rtol > 0 ? opts->fp32_rtol : 1e-6;
     Batch b;
     b.s = static_cast<hipStream_t>(stream);
     b.reqs.resize(count);
@@ -391,7 +471,7 @@ lofp_status lofp_amplitudes_multi(int32_t count, const lofp_request *req, lofp_c
     tm.on = stats && opts && opts->record_timing;
     tm.s = b.s;
     tm.mark();
-    lofp_status rc = launch_batch(b, opts && opts->precision == LOFP_PREC_FP32);
+    lofp_status rc = launch_batch(b, fp32, fp32);
     if (rc != LOFP_OK) return rc;
     tm.mark();
     HIPCHK(hipStreamSynchronize(b.s));
@@ -402,6 +482,32 @@ lofp_status lofp_amplitudes_multi(int32_t count, const lofp_request *req, lofp_c
         if (h[1]) return fail(LOFP_ENOMEM, "contraction workspace overflow");
         stats->transitions = (int64_t)h[0];
         if (tm.on) stats->ms_total = stats->ms_contract = tm.ms(0, 1);
+    }
+    for (int i = 0; i < count && err_bound; ++i) err_bound[i] = std::nan("");
+    if (!fp32) return LOFP_OK;
+    // bounds of the FP32 form; results it cannot certify are recomputed in FP64
+    Batch f;
+    f.s = b.s;
+    std::vector<int> redo;
+    for (int i = 0; i < count; ++i) {
+        const double abs_form = b.h_abs[2 * i];
+        const double bound = rounding_bound(b.reqs[i].c->G, b.reqs[i].n, abs_form, true);
+        if (err_bound) err_bound[i] = bound;
+        if (bound > rtol * std::hypot(out[i].re, out[i].im)) {
+            redo.push_back(i);
+            Req r = b.reqs[i];
+            r.abs_form = abs_form;
+            f.reqs.push_back(std::move(r));
+        }
+    }
+    if (redo.empty()) return LOFP_OK;
+    rc = launch_batch(f, 0, false);
+    if (rc != LOFP_OK) return rc;
+    HIPCHK(hipStreamSynchronize(f.s));
+    for (size_t k = 0; k < redo.size(); ++k) {
+        const int i = redo[k];
+        out[i] = f.h_out[k];
+        if (err_bound) err_bound[i] = rounding_bound(f.reqs[k].c->G, f.reqs[k].n, f.reqs[k].abs_form, false);
     }
     return LOFP_OK;
 }
@@ -419,6 +525,7 @@ lofp_status lofp_server_create(const lofp_server_opts *o, lofp_server *out)
         if (o->streams > 0) sv->o.streams = std::min(o->streams, 8);
         if (o->memory_budget > 0) sv->o.memory_budget = o->memory_budget;
         sv->o.precision = o->precision;
+        sv->o.fp32_rtol = o->fp32_rtol;
     }
     if (sv->o.precision != LOFP_PREC_FP64 && sv->o.precision != LOFP_PREC_FP32) {
         delete sv;
@@ -461,7 +568,7 @@ lofp_status lofp_server_submit(lofp_server sv, lofp_circuit c, const int32_t *S,
 }
 
 lofp_status lofp_server_result(lofp_server sv, uint64_t ticket, int32_t wait, lofp_c128 *out, double *latency_ms,
-                               int32_t *done)
+                               double *err_bound, int32_t *done)
 {
     if (!sv || !done) return fail(LOFP_EINVAL, "null argument");
     std::unique_lock<std::mutex> lk(sv->mu);
@@ -477,14 +584,15 @@ lofp_status lofp_server_result(lofp_server sv, uint64_t ticket, int32_t wait, lo
         }
         auto it = sv->done.find(ticket);
         if (it != sv->done.end()) {
-            if (it->second.second < 0) {
+            if (it->second.latency_ms < 0) {
                 const std::string msg = sv->error;
                 sv->done.erase(it);
                 *done = 1;
                 return fail(LOFP_EDEVICE, "request failed: " + msg);
             }
-            if (out) *out = it->second.first;
-            if (latency_ms) *latency_ms = it->second.second;
+            if (out) *out = it->second.amp;
+            if (latency_ms) *latency_ms = it->second.latency_ms;
+            if (err_bound) *err_bound = it->second.err_bound;
             sv->done.erase(it);
             *done = 1;
             return LOFP_OK;
@@ -506,6 +614,7 @@ lofp_status lofp_server_get_stats(lofp_server sv, lofp_server_stats *st)
     st->completed = sv->completed;
     st->launches = sv->launches;
     st->mean_batch = sv->launches ? (double)sv->launched_reqs / (double)sv->launches : 0.0;
+    st->fp64_fallbacks = sv->fp64_fallbacks;
     if (!sv->latencies.empty()) {
         std::vector<double> v = sv->latencies;
         std::sort(v.begin(), v.end());

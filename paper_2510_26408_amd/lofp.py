@@ -45,7 +45,8 @@ class C128(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("precision", ctypes.c_int32), ("fwd_layer", ctypes.c_int32),
                 ("bwd_layer", ctypes.c_int32), ("record_timing", ctypes.c_int32),
-                ("frontier_budget_kb", ctypes.c_int32), ("count_work", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("frontier_budget_kb", ctypes.c_int32), ("count_work", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("fp32_rtol", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -70,13 +71,13 @@ class Request(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_int32), ("streams", ctypes.c_int32), ("memory_budget", ctypes.c_int64),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32), ("fp32_rtol", ctypes.c_double)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("launches", ctypes.c_int64),
                 ("mean_batch", ctypes.c_double), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
-                ("max_ms", ctypes.c_double)]
+                ("max_ms", ctypes.c_double), ("fp64_fallbacks", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -110,11 +111,13 @@ def load():
     lib.lofp_amplitude.argtypes = [vp, i32p, i32p, ctypes.POINTER(C128)]
     lib.lofp_path_counts.argtypes = [vp, i32p, ctypes.c_int32, i32p, ctypes.POINTER(ctypes.c_double)]
     lib.lofp_amplitudes_multi.argtypes = [ctypes.c_int32, ctypes.POINTER(Request), ctypes.POINTER(C128),
-                                          ctypes.POINTER(Opts), vp, ctypes.POINTER(Stats)]
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(Opts), vp,
+                                          ctypes.POINTER(Stats)]
     lib.lofp_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
     lib.lofp_server_submit.argtypes = [vp, vp, i32p, i32p, ctypes.POINTER(ctypes.c_uint64)]
     lib.lofp_server_result.argtypes = [vp, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(C128),
-                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int32)]
     lib.lofp_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     lib.lofp_server_destroy.argtypes = [vp]
     for f in EXPORTED[2:]:
@@ -137,12 +140,14 @@ def _ip(a: np.ndarray):
 
 
 def make_opts(method: int = METHOD_AUTO, precision: int = PREC_FP64, fwd_layer: int = -1, bwd_layer: int = -1,
-              record_timing: bool = False, frontier_budget_kb: int = 0, count_work: bool = False) -> Opts:
+              record_timing: bool = False, frontier_budget_kb: int = 0, count_work: bool = False,
+              fp32_rtol: float = 0.0) -> Opts:
     o = Opts()
     o.method, o.precision, o.fwd_layer, o.bwd_layer = method, precision, fwd_layer, bwd_layer
     o.record_timing = 1 if record_timing else 0
     o.frontier_budget_kb = frontier_budget_kb
     o.count_work = 1 if count_work else 0
+    o.fp32_rtol = fp32_rtol
     return o
 
 
@@ -245,8 +250,10 @@ class Circuit:
         return out
 
 
-def amplitudes_multi(items, opts: Optional[Opts] = None, stats: Optional[Stats] = None) -> np.ndarray:
-    """items: list of (Circuit, S, T).  All evaluated in one multi-circuit launch."""
+def amplitudes_multi(items, opts: Optional[Opts] = None, stats: Optional[Stats] = None, bounds: bool = False):
+    """items: list of (Circuit, S, T).  All evaluated in one multi-circuit
+    launch.  bounds=True also returns each result's rounding bound (FP32
+    form; NaN for FP64)."""
     keep = []
     reqs = (Request * max(1, len(items)))()
     for i, (c, S, T) in enumerate(items):
@@ -254,18 +261,23 @@ def amplitudes_multi(items, opts: Optional[Opts] = None, stats: Optional[Stats] 
         keep.append((S, T))
         reqs[i] = Request(c.handle, _ip(S), _ip(T))
     out = (C128 * max(1, len(items)))()
-    _check(load().lofp_amplitudes_multi(len(items), reqs, out, ctypes.byref(opts) if opts is not None else None,
+    eb = (ctypes.c_double * max(1, len(items)))()
+    _check(load().lofp_amplitudes_multi(len(items), reqs, out, eb, ctypes.byref(opts) if opts is not None else None,
                                         None, ctypes.byref(stats) if stats is not None else None))
-    return np.frombuffer(out, dtype=np.complex128)[:len(items)].copy()
+    amps = np.frombuffer(out, dtype=np.complex128)[:len(items)].copy()
+    if bounds:
+        return amps, np.frombuffer(eb, dtype=np.float64)[:len(items)].copy()
+    return amps
 
 
 class Server:
     """Continuous-batching request loop (native worker thread)."""
 
     def __init__(self, max_batch: int = 256, streams: int = 2, memory_budget: int = 1 << 30,
-                 precision: int = PREC_FP64):
+                 precision: int = PREC_FP64, fp32_rtol: float = 0.0):
         o = ServerOpts()
         o.max_batch, o.streams, o.memory_budget, o.precision = max_batch, streams, memory_budget, precision
+        o.fp32_rtol = fp32_rtol
         h = ctypes.c_void_p()
         _check(load().lofp_server_create(ctypes.byref(o), ctypes.byref(h)))
         self._h = h
@@ -279,16 +291,22 @@ class Server:
         return t.value
 
     def result(self, ticket: int, wait: bool = True):
-        """(amplitude, latency_ms) or None if not finished (wait=False)."""
+        """(amplitude, latency_ms, err_bound) or None if not finished
+        (wait=False); err_bound is NaN for the FP64 form."""
         out = C128()
         lat = ctypes.c_double()
+        eb = ctypes.c_double()
         done = ctypes.c_int32()
-        _check(load().lofp_server_result(self._h, ticket, 1 if wait else 0, ctypes.byref(out), ctypes.byref(lat),
-                                         ctypes.byref(done)))
+        try:
+            _check(load().lofp_server_result(self._h, ticket, 1 if wait else 0, ctypes.byref(out), ctypes.byref(lat),
+                                             ctypes.byref(eb), ctypes.byref(done)))
+        except LofpError:
+            self._keep.pop(ticket, None)
+            raise
         if not done.value:
             return None
         self._keep.pop(ticket, None)
-        return complex(out.re, out.im), lat.value
+        return complex(out.re, out.im), lat.value, eb.value
 
     def stats(self) -> dict:
         st = ServerStats()

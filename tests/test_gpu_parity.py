@@ -280,12 +280,63 @@ def test_multi_circuit_batch_matches_oracle_and_single_calls():
 def test_multi_fp32_products_within_bound():
     items = _served(24, seed=4)
     f64 = lofp.amplitudes_multi([(c, r.S, r.T) for c, r in items])
-    f32 = lofp.amplitudes_multi([(c, r.S, r.T) for c, r in items], lofp.make_opts(precision=lofp.PREC_FP32))
-    scale = np.maximum(np.abs(f64), 1e-300)
+    f32, eb = lofp.amplitudes_multi([(c, r.S, r.T) for c, r in items], lofp.make_opts(precision=lofp.PREC_FP32),
+                                    bounds=True)
+    assert np.all(np.isfinite(eb)) and np.all(eb >= 0)
+    # every returned result is certified to 1e-6 relative or came from the FP64 re-run
+    assert np.all(np.abs(f32 - f64) <= eb + 1e-14)
+    assert np.all((eb <= 1e-6 * np.abs(f32)) | (np.abs(f32 - f64) <= 1e-13))
     nz = np.abs(f64) > 1e-12
-    rel = np.abs(f32 - f64)[nz] / scale[nz]
+    rel = np.abs(f32 - f64)[nz] / np.abs(f64)[nz]
     assert rel.max() < 1e-5, rel.max()
-    assert np.all(f32[~nz] == 0) or np.abs(f32[~nz]).max() < 1e-12
+    f64b = lofp.amplitudes_multi([(c, r.S, r.T) for c, r in items])
+    assert np.all(np.isnan(lofp.amplitudes_multi([(c, r.S, r.T) for c, r in items], bounds=True)[1]))
+    assert np.array_equal(f64, f64b)
+
+
+def _growth(G, n, fp32):
+    """The factor ((1 + f)^G - 1 + 4 * 2^-53)(1 + 2^-30) that multiplies the
+    absolute form in the stated rounding bound."""
+    u = 2.0 ** -24
+    k = (n + 1) ** 2
+    f = (4 * u / (1 - 4 * u) if fp32 else 0.0) + (2 * k + 2) * 2.0 ** -53
+    return (math.expm1(G * math.log1p(f)) + 4 * 2.0 ** -53) * (1 + 2.0 ** -30)
+
+
+def _small_items(count, seed):
+    rng = np.random.default_rng(seed)
+    items = []
+    for i in range(count):
+        m = int(rng.choice([6, 8, 9]))
+        n = m // 2
+        layers = _brickwork(m, int(rng.integers(3, 7)), seed * 100 + i)
+        S = np.zeros(m, np.int32)
+        T = np.zeros(m, np.int32)
+        for _ in range(n):
+            S[rng.integers(m)] += 1
+            T[rng.integers(m)] += 1
+        items.append((lofp.Circuit(m, layers), m, n, layers, S, T))
+    return items
+
+
+@pytest.mark.parametrize("rtol", [1e300, 1e-300])
+def test_fp32_bound_is_the_absolute_form_and_holds(rtol):
+    """The bound each FP32 result carries is the stated growth factor times the
+    absolute form (checked against the oracle's absolute form), and it holds
+    against the oracle's amplitude.  rtol 1e300: no result falls back;
+    1e-300: every result is recomputed in FP64 and carries the FP64 bound."""
+    items = _small_items(20, seed=21 if rtol > 1 else 22)
+    amps, eb = lofp.amplitudes_multi([(c, S, T) for c, _, _, _, S, T in items],
+                                     lofp.make_opts(precision=lofp.PREC_FP32, fp32_rtol=rtol), bounds=True)
+    for i, (c, m, n, layers, S, T) in enumerate(items):
+        circ = flat(layers)
+        want = oracle.amplitude(m, S, T, circ)
+        a_abs = oracle.absolute_form(m, S, T, circ)
+        grow = _growth(len(circ), n, fp32=rtol > 1)
+        assert abs(eb[i] - grow * a_abs) <= 1e-9 * grow * a_abs + 1e-300, (i, eb[i], grow * a_abs)
+        assert abs(amps[i] - want) <= eb[i] + 1e-15 * max(1.0, a_abs)
+        if rtol < 1:
+            assert abs(amps[i] - want) <= ATOL
 
 
 def test_server_results_same_alone_and_in_mix():
@@ -298,7 +349,7 @@ def test_server_results_same_alone_and_in_mix():
         st = srv.stats()
     finally:
         srv.close()
-    for i, (amp, lat) in enumerate(res):
+    for i, (amp, lat, _) in enumerate(res):
         assert amp == alone[i]
         assert lat >= 0
     assert st["completed"] == len(items) and st["launches"] >= 3
@@ -372,7 +423,7 @@ def test_server_reports_planning_errors_per_request():
     finally:
         srv.close()
     want = lofp.amplitudes_multi([(c, r.S, r.T) for c, r in good])
-    for (amp, _), w in zip(res, want):
+    for (amp, _, _), w in zip(res, want):
         assert amp == w
     # the single-circuit call still answers it, by the path sum
     a = bad.amplitudes(S, T[None, :])
@@ -411,3 +462,32 @@ def test_count_work_only_counts():
     b = c.amplitudes(wl.S, wl.Ts, lofp.make_opts(method=lofp.METHOD_CONTRACT, count_work=True), st1)
     assert np.array_equal(a, b)
     assert st0.transitions == 0 and st1.transitions > 0
+
+
+def test_server_fp32_bounds_and_fallbacks():
+    """FP32 serving: results whose bound exceeds rtol * |amp| are recomputed in
+    FP64 (counted; rtol 1e-300 sends back every result with a path); every
+    returned result lies within its bound of the oracle."""
+    items = _small_items(16, seed=23)
+    for rtol, all_back in ((1e-300, True), (0.0, False)):
+        srv = lofp.Server(max_batch=8, streams=2, precision=lofp.PREC_FP32, fp32_rtol=rtol)
+        try:
+            tickets = [srv.submit(c, S, T) for c, _, _, _, S, T in items]
+            res = [srv.result(t) for t in tickets]
+            st = srv.stats()
+        finally:
+            srv.close()
+        assert st["completed"] == len(items)
+        if all_back:
+            # a result with no path has bound 0 and needs no re-run
+            live = sum(oracle.absolute_form(m, S, T, flat(layers)) > 0 for _, m, _, layers, S, T in items)
+            assert 0 < live < len(items) and st["fp64_fallbacks"] == live
+        for (amp, lat, eb), (c, m, n, layers, S, T) in zip(res, items):
+            want = oracle.amplitude(m, S, T, flat(layers))
+            assert math.isfinite(eb) and eb >= 0
+            assert abs(amp - want) <= eb + 1e-15
+            assert lat >= 0
+            if all_back:
+                assert abs(amp - want) <= ATOL
+            else:
+                assert eb <= 1e-6 * abs(amp) or st["fp64_fallbacks"] > 0

@@ -206,3 +206,39 @@ def test_ryser_bound_small_on_workloads():
         wl = workloads.make(name, seed=0, batch=4)
         _, eb, _ = oracle.amplitudes(wl.m, wl.S, wl.Ts, wl.flat_circuit(), nthreads=4, with_bound=True)
         assert eb.max() < 1e-15
+
+
+# ------------------------------------------------------------ absolute form
+@pytest.mark.parametrize("m,D", [(4, 3), (6, 5), (7, 4)])
+def test_absolute_form_single_photon_is_matrix_product(m, D):
+    """With one photon every path is a walk of the photon through the modes,
+    so the absolute form is an entry of the product of the splitters' mode
+    matrices with each entry replaced by |Re| + |Im|."""
+    circ = flat(brick(m, D, 40 + m + D))
+    P = np.eye(m)
+    for (a, b, th, ph) in circ:
+        M = np.eye(m)
+        for xa in range(2):
+            for ya in range(2):
+                t = oracle.bs_amplitude(th, ph, xa, 1 - xa, ya, 1 - ya)
+                M[(a, b)[1 - ya], (a, b)[1 - xa]] = abs(t.real) + abs(t.imag)
+        P = M @ P
+    for i in range(m):
+        S = [0] * m
+        S[i] = 1
+        for j in range(m):
+            T = [0] * m
+            T[j] = 1
+            got = oracle.absolute_form(m, S, T, circ)
+            assert abs(got - P[j, i]) <= 1e-14 * max(1.0, P[j, i])
+
+
+def test_absolute_form_bounds_amplitude_and_vanishes_with_paths():
+    m, D = 5, 4
+    circ = flat(brick(m, D, 50))
+    S = (1, 0, 2, 0, 1)
+    for T in oracle.all_patterns(m, sum(S)):
+        a = oracle.absolute_form(m, S, T, circ)
+        amp = oracle.amplitude(m, S, T, circ)
+        assert a >= abs(amp) - 1e-14
+        assert (a > 0) == (oracle.path_count_bruteforce(m, S, T, circ) > 0)
