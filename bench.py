@@ -265,56 +265,75 @@ def variants(lofp, workloads, torch, dev, stream):
             "served_c4": serve_variant(lofp, workloads)}
 
 
-def serve_variant(lofp, workloads, n_req=2000, n_warm=200, rate_frac=0.5):
-    """Served mixed requests: m in {12,16,24}, n=m/2, depth in {4,6,8}, a fresh
-    circuit and pattern per request, FP32 path products with FP64 sums.
-    First the saturated throughput (everything submitted at once), then
-    Poisson arrivals at rate_frac of it; p50/p99 from submit to completion."""
-    reqs = workloads.served_requests(n_req + n_warm, rate_hz=1.0, seed=7)
-    circs = [lofp.Circuit(r.m, r.layers) for r in reqs]
-    srv = lofp.Server(max_batch=512, streams=3, precision=lofp.PREC_FP32)
-    try:
-        # saturated: submit all at once
-        t0 = time.perf_counter()
-        tk = [srv.submit(c, r.S, r.T) for c, r in zip(circs, reqs)]
-        amps32 = [srv.result(t)[0] for t in tk]
-        sat = len(reqs) / (time.perf_counter() - t0)
-    finally:
-        srv.close()
-    # complex128 reference for the FP32 form, same library (multi-circuit batch)
-    f64 = lofp.amplitudes_multi([(c, r.S, r.T) for c, r in zip(circs, reqs)])
-    a32 = np.array(amps32)
-    nz = np.abs(f64) > 1e-14
-    rel = float((np.abs(a32 - f64)[nz] / np.abs(f64)[nz]).max()) if nz.any() else 0.0
-    # Poisson arrivals at rate_frac * saturated (fresh circuits, new seed)
-    rate = rate_frac * sat
-    reqs2 = workloads.served_requests(n_req + n_warm, rate_hz=rate, seed=8)
-    circs2 = [lofp.Circuit(r.m, r.layers) for r in reqs2]
-    srv = lofp.Server(max_batch=512, streams=3, precision=lofp.PREC_FP32)
-    lats = []
+def _serve(lofp, reqs, circs, precision, rate_hz=0.0, n_warm=0):
+    """Serve reqs (saturated when rate_hz == 0, else at their Poisson arrival
+    times); returns (amplitudes, bounds, latencies after warm-up, wall s, stats)."""
+    srv = lofp.Server(max_batch=512, streams=3, precision=precision)
     try:
         t0 = time.perf_counter()
         tk = []
-        for c, r in zip(circs2, reqs2):
-            delay = r.arrival_s - (time.perf_counter() - t0)
-            if delay > 0:
-                time.sleep(delay)
+        for c, r in zip(circs, reqs):
+            if rate_hz > 0:
+                delay = r.arrival_s - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
             tk.append(srv.submit(c, r.S, r.T))
-        for i, t in enumerate(tk):
-            amp, lat, _ = srv.result(t)
-            if i >= n_warm:
-                lats.append(lat)
+        res = [srv.result(t) for t in tk]
         wall = time.perf_counter() - t0
         st = srv.stats()
     finally:
         srv.close()
-    lats = np.array(lats)
-    return {"requests": n_req, "warmup": n_warm, "precision": "fp32 products, fp64 sums",
-            "saturated_amplitudes_per_s": sat, "rate_hz": rate,
-            "offered_amplitudes_per_s": (n_req + n_warm) / wall,
-            "p50_ms": float(np.percentile(lats, 50)), "p99_ms": float(np.percentile(lats, 99)),
-            "mean_batch": st["mean_batch"], "launches": st["launches"],
-            "max_rel_err_fp32_vs_c128": rel}
+    amps = np.array([a for a, _, _ in res])
+    bounds = np.array([b for _, _, b in res])
+    lats = np.array([l for _, l, _ in res][n_warm:])
+    return amps, bounds, lats, wall, st
+
+
+def serve_variant(lofp, workloads, n_req=2000, n_warm=200, rate_frac=0.5):
+    """Served mixed requests: m in {12,16,24}, n=m/2, depth in {4,6,8}, a fresh
+    circuit and pattern per request.  The FP32-product form (FP64 sums) with
+    its per-result bound, a result whose bound exceeds 1e-6 |amp| recomputed in
+    FP64; beside it the FP64 form.  First the saturated throughput (everything
+    submitted at once), then Poisson arrivals at rate_frac of it; p50/p99 from
+    submit to completion."""
+    reqs = workloads.served_requests(n_req + n_warm, rate_hz=1.0, seed=7)
+    circs = [lofp.Circuit(r.m, r.layers) for r in reqs]
+    out = {"requests": n_req, "warmup": n_warm}
+    # complex128 reference (multi-circuit batch, same library)
+    f64 = lofp.amplitudes_multi([(c, r.S, r.T) for c, r in zip(circs, reqs)])
+    nz = np.abs(f64) > 1e-14
+    # unchecked FP32 products: the observed error and the a-priori bound
+    raw, raw_b = lofp.amplitudes_multi([(c, r.S, r.T) for c, r in zip(circs, reqs)],
+                                       lofp.make_opts(precision=lofp.PREC_FP32, fp32_rtol=1e300), bounds=True)
+    rel_raw = np.abs(raw - f64)[nz] / np.abs(f64)[nz]
+    ratio = raw_b[nz] / np.abs(f64)[nz]
+    out["fp32_unchecked"] = {"max_rel_err_vs_c128": float(rel_raw.max()),
+                             "median_rel_err_vs_c128": float(np.median(rel_raw)),
+                             "median_bound_over_amp": float(np.median(ratio)),
+                             "certifiable_at_1e-6": float((ratio <= 1e-6).mean())}
+    for name, prec in (("fp32_checked", lofp.PREC_FP32), ("fp64", lofp.PREC_FP64)):
+        # saturated: submit all at once (fresh circuits: the set-up is served too)
+        circs_s = [lofp.Circuit(r.m, r.layers) for r in reqs]
+        amps, bounds, _, wall, st = _serve(lofp, reqs, circs_s, prec)
+        sat = len(reqs) / wall
+        rel = float((np.abs(amps - f64)[nz] / np.abs(f64)[nz]).max()) if nz.any() else 0.0
+        # Poisson arrivals at rate_frac * saturated (fresh circuits, new seed)
+        rate = rate_frac * sat
+        reqs2 = workloads.served_requests(n_req + n_warm, rate_hz=rate, seed=8)
+        circs2 = [lofp.Circuit(r.m, r.layers) for r in reqs2]
+        _, _, lats, wall2, st2 = _serve(lofp, reqs2, circs2, prec, rate_hz=rate, n_warm=n_warm)
+        rec = {"precision": "fp32 products, fp64 sums, fp64 re-run above 1e-6 |amp|" if prec == lofp.PREC_FP32
+               else "fp64",
+               "saturated_amplitudes_per_s": sat, "rate_hz": rate,
+               "offered_amplitudes_per_s": (n_req + n_warm) / wall2,
+               "p50_ms": float(np.percentile(lats, 50)), "p99_ms": float(np.percentile(lats, 99)),
+               "mean_batch": st2["mean_batch"], "launches": st2["launches"],
+               "max_rel_err_vs_c128": rel}
+        if prec == lofp.PREC_FP32:
+            rec["fp64_fallback_fraction"] = st["fp64_fallbacks"] / len(reqs)
+            rec["max_bound_over_amp"] = float((bounds[nz] / np.abs(amps[nz])).max())
+        out[name] = rec
+    return out
 
 
 def host_threads() -> int:

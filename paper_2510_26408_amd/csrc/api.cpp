@@ -672,6 +672,9 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     ka.hlo = c.d_khull.as<int>(); ka.hhi = ka.hlo + (size_t)2 * B * span;
     ka.klo = c.d_klohi.as<int16_t>(); ka.khi = ka.klo + (size_t)2 * B * span;
     ka.counters = c.d_counters.as<unsigned long long>();
+    HIPCHK(ensure(c.d_korder, (size_t)2 * 2 * B * sizeof(int)));
+    ka.job_bucket = c.d_korder.as<int>();
+    ka.order = ka.job_bucket + 2 * B;
     HIPCHK(launch_keys(ka, s));
     c.ktab_clean = true;
     HIPCHK(hipMemcpyAsync(c.h_pin, c.d_kcnt.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -717,7 +720,7 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     const size_t lds_fixed = contract_job_lds_bytes(c.nvars, m, 0, true);
     const int64_t room = lds_job > lds_fixed ? (int64_t)((lds_job - lds_fixed) / (2 * sizeof(double2))) : 0;
     const int lds_states = (int)std::min<int64_t>(mx, room);
-    MultiOverride ov{mx, nullptr, nullptr, mx, lds_states};
+    MultiOverride ov{mx, nullptr, nullptr, mx, lds_states, ka.order};
     if (lds_states < mx) {
         HIPCHK(ensure(c.d_ws, (size_t)nj * 2 * mx * sizeof(double2)));
         ov.ws_base = c.d_ws.as<double2>();
@@ -1120,7 +1123,7 @@ lofp_status lofp_circuit_destroy(lofp_circuit c)
                       &c->d_count, &c->d_slot_stage, &c->d_off, &c->d_coff, &c->d_fa, &c->d_fb, &c->d_ba, &c->d_bb,
                       &c->d_levels, &c->d_tab_mid, &c->d_counters, &c->d_T, &c->d_out, &c->d_ws,
                       &c->d_cfg, &c->d_rankb, &c->d_ktab, &c->d_kslot, &c->d_kof, &c->d_krep, &c->d_kcnt,
-                      &c->d_khull, &c->d_klohi, &c->d_kinf, &c->d_jobs, &c->d_kstate};
+                      &c->d_khull, &c->d_klohi, &c->d_kinf, &c->d_jobs, &c->d_kstate, &c->d_korder};
     // pooled blocks are reused at once, so no work of this circuit may be left
     if (c->dev_ready || !c->blocks.empty()) (void)hipDeviceSynchronize();
     for (DevBuf *b : bufs) release(*b);

@@ -422,7 +422,8 @@ __global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
     contract_run<COUNT, F32, LDS_STATE, BS, STATS>(j, smem, g.stat_transitions, g.overflow);
 }
 
-// Many circuits, one block per job.
+// Many circuits, one block per job (in the order ov.order gives: the
+// largest jobs first, so that every CU starts one of them).
 // Waves per SIMD a multi-job block size is compiled for: 512-thread blocks
 // run three jobs (24 waves) per CU.
 template <int BS> constexpr int multi_waves_per_simd() { return BS >= 512 ? 6 : 1; }
@@ -435,12 +436,13 @@ __global__ __launch_bounds__(BS, multi_waves_per_simd<BS>()) void k_contract_mul
                                                        MultiOverride ov)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    ContractJob j = jobs[blockIdx.x];
+    const int jb = ov.order ? ov.order[blockIdx.x] : (int)blockIdx.x;
+    ContractJob j = jobs[jb];
     if (ov.max_states > 0) {
         j.max_states = ov.max_states;
-        j.ws = ov.ws_base ? ov.ws_base + (int64_t)blockIdx.x * 2 * ov.max_states : nullptr;
+        j.ws = ov.ws_base ? ov.ws_base + (int64_t)jb * 2 * ov.max_states : nullptr;
         if (ov.state_base) {
-            j.state_out = ov.state_base + (int64_t)blockIdx.x * ov.state_cap;
+            j.state_out = ov.state_base + (int64_t)jb * ov.state_cap;
             j.state_cap = ov.state_cap;
         }
     }

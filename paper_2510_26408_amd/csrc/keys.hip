@@ -162,27 +162,51 @@ __global__ void k_key_hull(KeyArgs a)
     atomicMax(&a.hhi[o], (int)a.hi[(int64_t)p * a.span + i]);
 }
 
-// One thread per (key, interval entry): the key's 16-bit interval rows; the
-// thread of entry 0 also writes the key's contraction job (top keys first,
-// then bottom keys).
-__global__ void k_key_jobs(KeyArgs a, ContractJob top, ContractJob bot, ContractJob *jobs, int32_t *kinf)
+// One wave per (half, key): the key's 16-bit interval rows, its contraction
+// job (top keys first, then bottom keys) and the bucket of its work, the sum
+// over its steps of the state entries times the summed versions' radii
+// (lanes over steps).
+__global__ __launch_bounds__(256) void k_key_jobs(KeyArgs a, ContractJob top, ContractJob bot, ContractJob *jobs,
+                                                  int32_t *kinf)
 {
-    const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t per = (int64_t)a.B * a.span;
-    if (gi >= 2 * per) return;
-    const int half = (int)(gi / per);
-    const int64_t r = gi - half * per;
-    const int k = (int)(r / a.span), i = (int)(r - (int64_t)k * a.span);
-    if (gi < 8) a.counters[gi] = 0;   // the contraction's counters for this call
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gw = gt >> 6;
+    const int lane = threadIdx.x & 63;
+    if (gt < 8) a.counters[gt] = 0;   // the contraction's counters for this call
+    if (gw >= 2 * (int64_t)a.B) return;
+    const int half = (int)(gw / a.B), k = (int)(gw - (int64_t)half * a.B);
     if (k >= a.count[half]) return;
     const int64_t row = ((int64_t)half * a.B + k) * a.span;
-    int l = a.hlo[row + i], h = a.hhi[row + i];
-    if (h < 0) { l = 1; h = 0; }   // no feasible member: empty interval
-    a.klo[row + i] = (int16_t)l;
-    a.khi[row + i] = (int16_t)h;
-    if (i != 0) return;
+    for (int i = lane; i < a.span; i += 64) {
+        int l = a.hlo[row + i], h = a.hhi[row + i];
+        if (h < 0) { l = 1; h = 0; }   // no feasible member: empty interval
+        a.klo[row + i] = (int16_t)l;
+        a.khi[row + i] = (int16_t)h;
+    }
+    const ContractJob &tmpl = half ? bot : top;
+    const int nc = a.m - 1;
+    float work = 0.0f;
+    for (int si = lane; si < tmpl.nsteps; si += 64) {
+        const ContractStep &st = tmpl.steps[si];
+        float e = 1.0f;
+        for (int q = 0; q < st.n_new; ++q) {
+            const int v = st.new_vars[q];
+            const int64_t i = row + tmpl.var_time[v] * nc + tmpl.var_cut[v];
+            e *= (float)max(0, a.hhi[i] - a.hlo[i] + 1);
+        }
+        for (int q = 0; q < st.n_sum; ++q) {
+            const int v = st.sum_vars[q];
+            const int64_t i = row + tmpl.var_time[v] * nc + tmpl.var_cut[v];
+            e *= (float)max(1, a.hhi[i] - a.hlo[i] + 1);
+        }
+        work += e;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) work += __shfl_xor(work, o, 64);
+    if (lane != 0) return;
     const int j = half ? a.count[0] + k : k;
-    ContractJob J = half ? bot : top;
+    a.job_bucket[j] = work > 1.0f ? min(255, (int)(8.0f * log2f(work))) : 0;
+    ContractJob J = tmpl;
     J.T = a.T + (int64_t)a.rep_of[(int64_t)half * a.B + k] * a.m;
     J.lo = a.klo + row;
     J.hi = a.khi + row;
@@ -190,6 +214,40 @@ __global__ void k_key_jobs(KeyArgs a, ContractJob top, ContractJob bot, Contract
     kinf[j] = 0;
     J.out = nullptr;
     jobs[j] = J;
+}
+
+// One block: the jobs in decreasing work bucket (a counting sort; the order
+// inside a bucket is arbitrary and changes no result).
+__global__ __launch_bounds__(1024) void k_key_order(KeyArgs a)
+{
+    __shared__ int hist[256], start[256];
+    __shared__ int wsum[4];
+    const int nj = a.count[0] + a.count[1];
+    const int t = threadIdx.x;
+    if (t < 256) hist[t] = 0;
+    __syncthreads();
+    for (int j = t; j < nj; j += blockDim.x) atomicAdd(&hist[255 - a.job_bucket[j]], 1);
+    __syncthreads();
+    // exclusive scan of the 256 counts (largest bucket first), four waves
+    if (t < 256) {
+        const int lane = t & 63, w = t >> 6;
+        int x = hist[t];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
+        start[t] = x - hist[t];
+    }
+    __syncthreads();
+    if (t < 256) {
+        int before = 0;
+        for (int w = 0; w < (t >> 6); ++w) before += wsum[w];
+        start[t] += before;
+    }
+    __syncthreads();
+    for (int j = t; j < nj; j += blockDim.x) a.order[atomicAdd(&start[255 - a.job_bucket[j]], 1)] = j;
 }
 
 hipError_t launch_keys(const KeyArgs &a, hipStream_t stream)
@@ -206,9 +264,10 @@ hipError_t launch_keys(const KeyArgs &a, hipStream_t stream)
 hipError_t launch_key_jobs(const KeyArgs &a, const ContractJob &top, const ContractJob &bot, ContractJob *jobs,
                            int32_t *kinf, hipStream_t stream)
 {
-    const int64_t n2 = 2 * (int64_t)a.B * a.span;
-    hipLaunchKernelGGL(k_key_jobs, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, stream, a, top, bot, jobs,
+    const int64_t threads = 2 * (int64_t)a.B * 64;
+    hipLaunchKernelGGL(k_key_jobs, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, stream, a, top, bot, jobs,
                        kinf);
+    hipLaunchKernelGGL(k_key_order, dim3(1), dim3(1024), 0, stream, a);
     return hipGetLastError();
 }
 

@@ -238,6 +238,7 @@ struct MultiOverride {
     int state_cap;
     int lds_states;              // > 0: a job whose own largest state fits this
                                  // many entries keeps it in LDS, others in ws
+    const int *order;            // block b runs job order[b] (nullptr: job b)
 };
 struct BoundsJob {
     int m, D, n;
@@ -269,9 +270,13 @@ struct KeyArgs {
     int *hlo, *hhi;                // int32 hull accumulators
     int16_t *klo, *khi;            // per key intervals (top keys at 0, bottom at B)
     unsigned long long *counters;  // [8] zeroed by the jobs kernel
+    int *job_bucket;               // [2B] cost bucket of each job
+    int *order;                    // [2B] jobs by decreasing cost bucket
 };
 hipError_t launch_keys(const KeyArgs &a, hipStream_t stream);
 // One contraction job per key from the two half templates; jobs[0, ntop) top.
+// Also the dispatch order a.order: jobs by decreasing work (the sum over the
+// job's steps of state entries times summed versions), in buckets of 2^(1/8).
 hipError_t launch_key_jobs(const KeyArgs &a, const ContractJob &top, const ContractJob &bot, ContractJob *jobs,
                            int32_t *kinf, hipStream_t stream);
 struct JoinArgs {

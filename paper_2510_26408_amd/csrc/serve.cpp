@@ -267,7 +267,7 @@ lofp_status launch_batch(Batch &b, int fp32, bool checked = false)
         }
         HIPCHK(upload(b.d_cja, b.cja, s));
         HIPCHK(launch_contract_multi(count, b.d_cja.as<ContractJob>(), lds, (int)max_est, in_lds, false, ctr,
-                                     reinterpret_cast<int32_t *>(ctr + 1), s, MultiOverride{0, nullptr, nullptr, 0, 0},
+                                     reinterpret_cast<int32_t *>(ctr + 1), s, MultiOverride{0, nullptr, nullptr, 0, 0, nullptr},
                                      false, true));
     }
     if (b.h_cap < (size_t)count) {
