@@ -649,34 +649,39 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     // group the patterns by their two halves of T
     int cap = 1;
     while (cap < 2 * B) cap <<= 1;
-    void *old_tab = c.d_ktab.p;
+    const void *old_tab = c.d_ktab.p, *old_hull = c.d_khull.p, *old_cnt = c.d_kcnt.p;
     HIPCHK(ensure(c.d_ktab, (size_t)2 * cap * sizeof(int)));
-    if (c.d_ktab.p != old_tab) c.ktab_clean = false;
     HIPCHK(ensure(c.d_kslot, (size_t)2 * B * sizeof(int)));
-    HIPCHK(ensure(c.d_kof, (size_t)2 * B * sizeof(int)));
+    HIPCHK(ensure(c.d_kof, (size_t)2 * cap * sizeof(int)));
     HIPCHK(ensure(c.d_krep, (size_t)2 * B * sizeof(int)));
     HIPCHK(ensure(c.d_kcnt, 2 * sizeof(int)));
-    HIPCHK(ensure(c.d_khull, (size_t)2 * 2 * B * span * sizeof(int)));
+    HIPCHK(ensure(c.d_khull, (size_t)2 * 2 * cap * span * sizeof(int)));
     HIPCHK(ensure(c.d_klohi, (size_t)2 * 2 * B * span * sizeof(int16_t)));
-    // the table is left empty by each call; it is cleared here only when new
-    // or when a previous call stopped before emptying it
-    if (!c.ktab_clean) HIPCHK(hipMemsetAsync(c.d_ktab.p, 0xFF, c.d_ktab.cap, s));
-    c.ktab_clean = false;
+    if (c.d_ktab.p != old_tab || c.d_khull.p != old_hull || c.d_kcnt.p != old_cnt) c.ktab_clean = false;
     KeyArgs ka{};
     ka.B = B; ka.m = m; ka.n = n; ka.rs = rs; ka.cap = cap; ka.span = span;
     ka.T = T_dev;
     ka.lo = c.d_lo.as<int16_t>(); ka.hi = c.d_hi.as<int16_t>();
     ka.infeasible = c.d_inf.as<int32_t>();
     ka.table = c.d_ktab.as<int>(); ka.slot = c.d_kslot.as<int>();
-    ka.key_of = c.d_kof.as<int>(); ka.rep_of = c.d_krep.as<int>(); ka.count = c.d_kcnt.as<int>();
-    ka.hlo = c.d_khull.as<int>(); ka.hhi = ka.hlo + (size_t)2 * B * span;
+    ka.slot_key = c.d_kof.as<int>(); ka.key_slot = c.d_krep.as<int>(); ka.count = c.d_kcnt.as<int>();
+    ka.hlo = c.d_khull.as<int>(); ka.hhi = ka.hlo + (size_t)2 * cap * span;
     ka.klo = c.d_klohi.as<int16_t>(); ka.khi = ka.klo + (size_t)2 * B * span;
     ka.counters = c.d_counters.as<unsigned long long>();
     HIPCHK(ensure(c.d_korder, (size_t)2 * 2 * B * sizeof(int)));
     ka.job_bucket = c.d_korder.as<int>();
     ka.order = ka.job_bucket + 2 * B;
+    // the table, the slot hulls and the counts are left empty by the jobs
+    // kernel of each call; they are cleared here only when new or when a
+    // previous call stopped before that kernel
+    if (!c.ktab_clean) {
+        HIPCHK(hipMemsetAsync(ka.table, 0xFF, (size_t)2 * cap * sizeof(int), s));
+        HIPCHK(hipMemsetAsync(ka.hlo, 0x7F, (size_t)2 * cap * span * sizeof(int), s));
+        HIPCHK(hipMemsetAsync(ka.hhi, 0xFF, (size_t)2 * cap * span * sizeof(int), s));
+        HIPCHK(hipMemsetAsync(ka.count, 0, 2 * sizeof(int), s));
+    }
+    c.ktab_clean = false;
     HIPCHK(launch_keys(ka, s));
-    c.ktab_clean = true;
     HIPCHK(hipMemcpyAsync(c.h_pin, c.d_kcnt.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const int ntop = c.h_pin[0], nbot = c.h_pin[1];
@@ -699,7 +704,8 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     bj.nsteps = (int)sp->bot.steps.size(); bj.steps = sp->d_bot.as<ContractStep>();
     HIPCHK(ensure(c.d_jobs, (size_t)std::max(nj, 1) * sizeof(ContractJob)));
     HIPCHK(ensure(c.d_kinf, (size_t)std::max(nj, 1) * sizeof(int32_t)));
-    HIPCHK(launch_key_jobs(ka, tj, bj, c.d_jobs.as<ContractJob>(), c.d_kinf.as<int32_t>(), s));
+    HIPCHK(launch_key_jobs(ka, ntop, nbot, tj, bj, c.d_jobs.as<ContractJob>(), c.d_kinf.as<int32_t>(), s));
+    c.ktab_clean = true;
     unsigned long long *ctr = c.d_counters.as<unsigned long long>();   // zeroed by k_key_jobs
     int mx;
     if (cap_s <= (1 << 20)) {
@@ -738,7 +744,7 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     ja.B = B; ja.m = m; ja.n = n; ja.D = c.D;
     ja.lo = c.d_lo.as<int16_t>(); ja.hi = c.d_hi.as<int16_t>();
     ja.infeasible = c.d_inf.as<int32_t>();
-    ja.top_of = ka.key_of; ja.bot_of = ka.key_of + B;
+    ja.slot = ka.slot; ja.slot_key = ka.slot_key; ja.cap = cap;
     ja.tlo = ka.klo; ja.thi = ka.khi;
     ja.blo = ka.klo + (size_t)B * span; ja.bhi = ka.khi + (size_t)B * span;
     ja.nshared = (int)sp->top.live_out.size();

@@ -501,7 +501,7 @@ __global__ __launch_bounds__(64) void k_join(JoinArgs g)
         if (threadIdx.x == 0) g.out[p] = make_double2(0.0, 0.0);
         return;
     }
-    const int tk = g.top_of[p], bk = g.bot_of[p];
+    const int tk = g.slot_key[g.slot[p]], bk = g.slot_key[g.cap + g.slot[g.B + p]];
     const int16_t *plo = g.lo + (int64_t)p * span, *phi = g.hi + (int64_t)p * span;
     const int16_t *tlo = g.tlo + (int64_t)tk * span, *thi = g.thi + (int64_t)tk * span;
     const int16_t *blo = g.blo + (int64_t)bk * span, *bhi = g.bhi + (int64_t)bk * span;

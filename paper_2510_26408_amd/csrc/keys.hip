@@ -5,10 +5,12 @@
 // one contraction of that half.
 //
 // Per half: an open-addressing hash table over the sub-rows of T (equal rows
-// found by comparing values), numbered in order of each group's
-// representative -- the lowest-indexed member whose photon number is right,
-// else the lowest member -- so key numbers do not depend on thread timing.
-// The group's cut intervals are the hull of its feasible members' intervals.
+// found by comparing values).  The wave that claims a slot numbers the key;
+// every member folds its intervals into the slot's hull (feasible members
+// only) and its index into the slot's representative, the lowest-indexed
+// member whose photon number is right, else the lowest member.  The jobs
+// kernel reads each key's slot and leaves the table and the hulls empty for
+// the next call.
 #include "lofp_device.h"
 
 namespace lofp {
@@ -43,17 +45,9 @@ __global__ __launch_bounds__(256) void k_key_insert(KeyArgs a)
         h ^= __shfl_xor(h, o, 64);
     }
     const int v = tot == a.n ? p : p + a.B;
-    // reset hull row (half, p): key numbers are below B, so the rows of all
-    // keys get reset
-    {
-        const int64_t row = ((int64_t)half * a.B + p) * a.span;
-        for (int i = lane; i < a.span; i += 64) {
-            a.hlo[row + i] = 0x7f7f7f7f;
-            a.hhi[row + i] = -1;
-        }
-    }
     int *tab = a.table + (int64_t)half * a.cap;
     uint32_t j = (uint32_t)(h ^ (h >> 32)) & (uint32_t)(a.cap - 1);
+    // at most B rows per half and cap >= 2B slots: a free slot is always found
     for (int probe = 0; probe < a.cap; ++probe) {
         int cur = tab[j];
         if (cur < 0) {
@@ -61,127 +55,56 @@ __global__ __launch_bounds__(256) void k_key_insert(KeyArgs a)
             if (lane == 0) won = atomicCAS(&tab[j], -1, v);
             cur = __shfl(won, 0, 64);
             if (cur < 0) {
-                if (lane == 0) a.slot[gw] = (int)j;
-                return;
+                // claimed: number the key
+                if (lane == 0) {
+                    const int key = atomicAdd(&a.count[half], 1);   // < B: at most B rows
+                    a.slot_key[(int64_t)half * a.cap + j] = key;
+                    if (key < a.B) a.key_slot[(int64_t)half * a.B + key] = (int)j;
+                }
+                break;
             }
         }
         const int occ = cur >= a.B ? cur - a.B : cur;
         const int y = mine ? a.T[(int64_t)occ * a.m + lane] : x;
         if (__all(y == x)) {
-            if (lane == 0) {
-                atomicMin(&tab[j], v);
-                a.slot[gw] = (int)j;
-            }
-            return;
+            if (lane == 0) atomicMin(&tab[j], v);
+            break;
         }
         j = (j + 1) & (uint32_t)(a.cap - 1);
     }
-    if (lane == 0) a.slot[gw] = -1;   // unreachable: the table has twice as many slots as rows
-}
-
-// Representative of the group in table slot sl (a pattern that found no
-// slot, which a table twice the batch size rules out, stands alone).
-__device__ __forceinline__ int rep_of_slot(const int *tab, int sl, int p, int B)
-{
-    if (sl < 0) return p;
-    const int v = tab[sl];
-    return v >= B ? v - B : v;
-}
-
-// One block per half: number the groups in order of their representatives
-// (a block-wide scan over the patterns), then give every pattern its key and
-// every key its representative.
-__global__ __launch_bounds__(1024) void k_key_number(KeyArgs a)
-{
-    const int half = blockIdx.x;
-    const int *tab = a.table + (int64_t)half * a.cap;
-    const int *slot = a.slot + (int64_t)half * a.B;
-    int *key_of = a.key_of + (int64_t)half * a.B;
-    int *rep_of = a.rep_of + (int64_t)half * a.B;
-    __shared__ int wsum[16];
-    __shared__ int base_s;
-    if (threadIdx.x == 0) base_s = 0;
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int c = 0; c < a.B; c += blockDim.x) {
-        const int p = c + threadIdx.x;
-        int is_rep = 0;
-        if (p < a.B) is_rep = rep_of_slot(tab, slot[p], p, a.B) == p;
-        // exclusive scan of is_rep over the block
-        int x = is_rep;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
-        if (lane == 63) wsum[wid] = x;
-        __syncthreads();
-        int before = base_s;
-        for (int w = 0; w < wid; ++w) before += wsum[w];
-        if (is_rep) key_of[p] = before + x - 1;   // the representative's key number
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int t = 0;
-            for (int w = 0; w < nw; ++w) t += wsum[w];
-            base_s += t;
-        }
-        __syncthreads();
-    }
-    const int nkeys = base_s;
-    if (threadIdx.x == 0) a.count[half] = nkeys;
-    __syncthreads();
-    // representatives hold their key numbers; members copy theirs
-    for (int p = threadIdx.x; p < a.B; p += blockDim.x)
-        if (rep_of_slot(tab, slot[p], p, a.B) == p) rep_of[key_of[p]] = p;
-    __syncthreads();
-    for (int p = threadIdx.x; p < a.B; p += blockDim.x) {
-        const int r = rep_of_slot(tab, slot[p], p, a.B);
-        if (r != p) key_of[p] = key_of[r];
-    }
-    // leave the table empty for the next call (every used slot is some
-    // pattern's slot)
-    __syncthreads();
-    int *wtab = a.table + (int64_t)half * a.cap;
-    for (int p = threadIdx.x; p < a.B; p += blockDim.x)
-        if (slot[p] >= 0) wtab[slot[p]] = -1;
-}
-
-// Hull of the feasible members' intervals, one thread per (pattern, half, entry).
-__global__ void k_key_hull(KeyArgs a)
-{
-    const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t per = (int64_t)a.B * a.span;
-    if (gi >= 2 * per) return;
-    const int half = (int)(gi / per);
-    const int64_t r = gi - half * per;
-    const int p = (int)(r / a.span), i = (int)(r - (int64_t)p * a.span);
+    if (lane == 0) a.slot[gw] = (int)j;
     if (a.infeasible[p]) return;
-    const int k = a.key_of[(int64_t)half * a.B + p];
-    const int64_t o = ((int64_t)half * a.B + k) * a.span + i;
-    atomicMin(&a.hlo[o], (int)a.lo[(int64_t)p * a.span + i]);
-    atomicMax(&a.hhi[o], (int)a.hi[(int64_t)p * a.span + i]);
+    // the slot's hull of its feasible members' intervals
+    const int64_t row = ((int64_t)half * a.cap + j) * a.span;
+    for (int i = lane; i < a.span; i += 64) {
+        atomicMin(&a.hlo[row + i], (int)a.lo[(int64_t)p * a.span + i]);
+        atomicMax(&a.hhi[row + i], (int)a.hi[(int64_t)p * a.span + i]);
+    }
 }
 
-// One wave per (half, key): the key's 16-bit interval rows, its contraction
-// job (top keys first, then bottom keys) and the bucket of its work, the sum
-// over its steps of the state entries times the summed versions' radii
-// (lanes over steps).
-__global__ __launch_bounds__(256) void k_key_jobs(KeyArgs a, ContractJob top, ContractJob bot, ContractJob *jobs,
-                                                  int32_t *kinf)
+// One wave per key (top keys, then bottom keys; wave w is job w): the key's
+// 16-bit interval rows from its slot's hull, its contraction job and the
+// bucket of its work, the sum over its steps of the state entries times the
+// summed versions' radii (lanes over steps).  Then the slot's hull and table
+// entry are reset, and the key counts zeroed, for the next call.
+__global__ __launch_bounds__(256) void k_key_jobs(KeyArgs a, int ntop, int nbot, ContractJob top, ContractJob bot,
+                                                  ContractJob *jobs, int32_t *kinf)
 {
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t gw = gt >> 6;
+    const int w = (int)(gt >> 6);
     const int lane = threadIdx.x & 63;
     if (gt < 8) a.counters[gt] = 0;   // the contraction's counters for this call
-    if (gw >= 2 * (int64_t)a.B) return;
-    const int half = (int)(gw / a.B), k = (int)(gw - (int64_t)half * a.B);
-    if (k >= a.count[half]) return;
-    const int64_t row = ((int64_t)half * a.B + k) * a.span;
+    if (gt == 0) { a.count[0] = 0; a.count[1] = 0; }
+    if (w >= ntop + nbot) return;
+    const int half = w >= ntop, k = half ? w - ntop : w;
+    const int sl = a.key_slot[(int64_t)half * a.B + k];
+    const int64_t srow = ((int64_t)half * a.cap + sl) * a.span;
+    const int64_t krow = ((int64_t)half * a.B + k) * a.span;
     for (int i = lane; i < a.span; i += 64) {
-        int l = a.hlo[row + i], h = a.hhi[row + i];
+        int l = a.hlo[srow + i], h = a.hhi[srow + i];
         if (h < 0) { l = 1; h = 0; }   // no feasible member: empty interval
-        a.klo[row + i] = (int16_t)l;
-        a.khi[row + i] = (int16_t)h;
+        a.klo[krow + i] = (int16_t)l;
+        a.khi[krow + i] = (int16_t)h;
     }
     const ContractJob &tmpl = half ? bot : top;
     const int nc = a.m - 1;
@@ -191,38 +114,44 @@ __global__ __launch_bounds__(256) void k_key_jobs(KeyArgs a, ContractJob top, Co
         float e = 1.0f;
         for (int q = 0; q < st.n_new; ++q) {
             const int v = st.new_vars[q];
-            const int64_t i = row + tmpl.var_time[v] * nc + tmpl.var_cut[v];
+            const int64_t i = srow + tmpl.var_time[v] * nc + tmpl.var_cut[v];
             e *= (float)max(0, a.hhi[i] - a.hlo[i] + 1);
         }
         for (int q = 0; q < st.n_sum; ++q) {
             const int v = st.sum_vars[q];
-            const int64_t i = row + tmpl.var_time[v] * nc + tmpl.var_cut[v];
+            const int64_t i = srow + tmpl.var_time[v] * nc + tmpl.var_cut[v];
             e *= (float)max(1, a.hhi[i] - a.hlo[i] + 1);
         }
         work += e;
     }
+    // (the reduction consumes every lane's loads before the hull is reset)
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) work += __shfl_xor(work, o, 64);
+    for (int i = lane; i < a.span; i += 64) {
+        a.hlo[srow + i] = 0x7f7f7f7f;
+        a.hhi[srow + i] = -1;
+    }
     if (lane != 0) return;
-    const int j = half ? a.count[0] + k : k;
-    a.job_bucket[j] = work > 1.0f ? min(255, (int)(8.0f * log2f(work))) : 0;
+    int *tab = a.table + (int64_t)half * a.cap;
+    const int rv = tab[sl];
+    tab[sl] = -1;
+    a.job_bucket[w] = work > 1.0f ? min(255, (int)(8.0f * log2f(work))) : 0;
     ContractJob J = tmpl;
-    J.T = a.T + (int64_t)a.rep_of[(int64_t)half * a.B + k] * a.m;
-    J.lo = a.klo + row;
-    J.hi = a.khi + row;
-    J.infeasible = kinf + j;
-    kinf[j] = 0;
+    J.T = a.T + (int64_t)(rv >= a.B ? rv - a.B : rv) * a.m;
+    J.lo = a.klo + krow;
+    J.hi = a.khi + krow;
+    J.infeasible = kinf + w;
+    kinf[w] = 0;
     J.out = nullptr;
-    jobs[j] = J;
+    jobs[w] = J;
 }
 
 // One block: the jobs in decreasing work bucket (a counting sort; the order
 // inside a bucket is arbitrary and changes no result).
-__global__ __launch_bounds__(1024) void k_key_order(KeyArgs a)
+__global__ __launch_bounds__(1024) void k_key_order(KeyArgs a, int nj)
 {
     __shared__ int hist[256], start[256];
     __shared__ int wsum[4];
-    const int nj = a.count[0] + a.count[1];
     const int t = threadIdx.x;
     if (t < 256) hist[t] = 0;
     __syncthreads();
@@ -255,19 +184,16 @@ hipError_t launch_keys(const KeyArgs &a, hipStream_t stream)
     if (a.B == 0) return hipSuccess;
     const int64_t n2 = 2 * (int64_t)a.B;
     hipLaunchKernelGGL(k_key_insert, dim3((unsigned)((n2 * 64 + 255) / 256)), dim3(256), 0, stream, a);
-    hipLaunchKernelGGL(k_key_number, dim3(2), dim3(1024), 0, stream, a);
-    const int64_t nh = n2 * a.span;
-    hipLaunchKernelGGL(k_key_hull, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 
-hipError_t launch_key_jobs(const KeyArgs &a, const ContractJob &top, const ContractJob &bot, ContractJob *jobs,
-                           int32_t *kinf, hipStream_t stream)
+hipError_t launch_key_jobs(const KeyArgs &a, int ntop, int nbot, const ContractJob &top, const ContractJob &bot,
+                           ContractJob *jobs, int32_t *kinf, hipStream_t stream)
 {
-    const int64_t threads = 2 * (int64_t)a.B * 64;
-    hipLaunchKernelGGL(k_key_jobs, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, stream, a, top, bot, jobs,
-                       kinf);
-    hipLaunchKernelGGL(k_key_order, dim3(1), dim3(1024), 0, stream, a);
+    const int64_t threads = (int64_t)(ntop + nbot) * 64;
+    hipLaunchKernelGGL(k_key_jobs, dim3((unsigned)(threads > 0 ? (threads + 255) / 256 : 1)), dim3(256), 0, stream,
+                       a, ntop, nbot, top, bot, jobs, kinf);
+    hipLaunchKernelGGL(k_key_order, dim3(1), dim3(1024), 0, stream, a, ntop + nbot);
     return hipGetLastError();
 }
 

@@ -253,37 +253,47 @@ hipError_t launch_bounds_multi(int count, const BoundsJob *jobs, hipStream_t str
 hipError_t launch_contract_multi(int count, const ContractJob *jobs, size_t lds_bytes, int max_states,
                                  bool state_in_lds, bool fp32, unsigned long long *stat_transitions,
                                  int32_t *overflow, hipStream_t stream,
-                                 MultiOverride ov = MultiOverride{0, nullptr, nullptr, 0, 0}, bool stats = false,
+                                 MultiOverride ov = MultiOverride{0, nullptr, nullptr, 0, 0, nullptr}, bool stats = false,
                                  bool abs = false);
 // Largest state over the jobs (one thread per job), atomically maxed into *mx.
 hipError_t launch_multi_sizes(int count, const ContractJob *jobs, int *mx, hipStream_t stream);
 
-// Split contraction: per key, the hull of its member patterns' intervals.
 // Grouping of a batch by the halves of T (split contraction), per half h:
-// table [2][cap], slot/key_of/rep_of [2][B], count [2], hulls [2][B][span].
+// a hash table over the distinct half-rows, whose slots carry the group's
+// key number and the hull of its feasible members' intervals.
 struct KeyArgs {
     int B, m, n, rs, cap, span;
     const int32_t *T;              // [B][m]
     const int16_t *lo, *hi;        // per pattern [B][span]
     const int32_t *infeasible;     // [B]
-    int *table, *slot, *key_of, *rep_of, *count;
-    int *hlo, *hhi;                // int32 hull accumulators
+    int *table;                    // [2][cap] -1, or the group's lowest member p
+                                   // (p + B if p has the wrong photon number)
+    int *slot;                     // [2][B] each pattern's slot
+    int *slot_key;                 // [2][cap] key number of a claimed slot
+    int *key_slot;                 // [2][B] slot of each key
+    int *count;                    // [2] keys per half (zeroed by the jobs kernel)
+    int *hlo, *hhi;                // [2][cap][span] int32 hull per slot
     int16_t *klo, *khi;            // per key intervals (top keys at 0, bottom at B)
     unsigned long long *counters;  // [8] zeroed by the jobs kernel
     int *job_bucket;               // [2B] cost bucket of each job
     int *order;                    // [2B] jobs by decreasing cost bucket
 };
+// Insert every pattern's two half-rows; keys are numbered as their slots are
+// claimed, so their numbers (not the results) depend on thread timing.
 hipError_t launch_keys(const KeyArgs &a, hipStream_t stream);
 // One contraction job per key from the two half templates; jobs[0, ntop) top.
 // Also the dispatch order a.order: jobs by decreasing work (the sum over the
 // job's steps of state entries times summed versions), in buckets of 2^(1/8).
-hipError_t launch_key_jobs(const KeyArgs &a, const ContractJob &top, const ContractJob &bot, ContractJob *jobs,
-                           int32_t *kinf, hipStream_t stream);
+// Leaves the table, the slot hulls and the counts empty for the next call.
+hipError_t launch_key_jobs(const KeyArgs &a, int ntop, int nbot, const ContractJob &top, const ContractJob &bot,
+                           ContractJob *jobs, int32_t *kinf, hipStream_t stream);
 struct JoinArgs {
     int B, m, n, D;
     const int16_t *lo, *hi;          // per pattern [B][span]
     const int32_t *infeasible;
-    const int32_t *top_of, *bot_of;  // key of each pattern
+    const int32_t *slot;             // [2][B] each pattern's slot per half
+    const int32_t *slot_key;         // [2][cap] key number of each slot
+    int cap;
     const int16_t *tlo, *thi;        // per top key [ntop][span]
     const int16_t *blo, *bhi;        // per bottom key [nbot][span]
     int nshared;
