@@ -156,6 +156,15 @@ lofp_status lofp_light_cone(lofp_circuit c, int32_t layer, int32_t mode, int32_t
 lofp_status lofp_bounds(lofp_circuit c, const int32_t *S, const int32_t *T, int32_t *lo,
                         int32_t *hi, int32_t *feasible);
 
+/* The same cut bounds for a batch of patterns, computed on the device by the
+ * planner kernel that the amplitude calls run (one wave per pattern).  T:
+ * host int32[batch][m]; lo, hi: host int32[batch][(D+1)*(m-1)] in the layout
+ * of lofp_bounds; feasible: host int32[batch].  lo/hi of an infeasible
+ * pattern are unspecified (lo > hi somewhere).  EINVAL for null arguments
+ * or negative occupations.  Synchronises the default stream. */
+lofp_status lofp_bounds_batch(lofp_circuit c, const int32_t *S, int32_t batch, const int32_t *T, int32_t *lo,
+                              int32_t *hi, int32_t *feasible);
+
 /* Single-beam-splitter transition table (Appendix): out[x1*(N+1)+y1] =
  * <y1, N-y1| BS_g |x1, N-x1> for beam splitter g (0-based, in application
  * order) and photon number N, computed on the device in FP64 by the same

@@ -1183,6 +1183,55 @@ lofp_status lofp_bounds(lofp_circuit c, const int32_t *S, const int32_t *T, int3
     return LOFP_OK;
 }
 
+lofp_status lofp_bounds_batch(lofp_circuit c, const int32_t *S, int32_t batch, const int32_t *T, int32_t *lo,
+                              int32_t *hi, int32_t *feasible)
+{
+    if (!c) return fail(LOFP_EINVAL, "null circuit");
+    if (batch < 0) return fail(LOFP_EINVAL, "negative batch");
+    if (batch > 0 && (!T || !lo || !hi || !feasible)) return fail(LOFP_EINVAL, "null argument");
+    int n = 0;
+    lofp_status rc = check_S(*c, S, n);
+    if (rc != LOFP_OK) return rc;
+    if (batch == 0) return LOFP_OK;
+    for (int64_t i = 0; i < (int64_t)batch * c->m; ++i)
+        if (T[i] < 0) return fail(LOFP_EINVAL, "negative occupation in T");
+    std::lock_guard<std::mutex> lk(c->mu);
+    hipStream_t s = nullptr;
+    rc = device_init(*c, n, s);
+    if (rc != LOFP_OK) return rc;
+    std::vector<int32_t> Sv(S, S + c->m);
+    if (Sv != c->S_dev) {
+        HIPCHK(upload(c->d_S, Sv, s));
+        c->S_dev = Sv;
+    }
+    rc = ready_on_stream(*c, s);
+    if (rc != LOFP_OK) return rc;
+    const size_t span = (size_t)(c->D + 1) * c->nc;
+    DevBuf dT;
+    std::vector<int16_t> L((size_t)batch * span), H((size_t)batch * span);
+    std::vector<int32_t> inf(batch);
+    hipError_t e = ensure(dT, (size_t)batch * c->m * sizeof(int32_t));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dT.p, T, (size_t)batch * c->m * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        rc = run_bounds(*c, batch, n, dT.as<int32_t>(), s);
+        if (rc == LOFP_OK) {
+            e = hipMemcpyAsync(L.data(), c->d_lo.p, L.size() * sizeof(int16_t), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(H.data(), c->d_hi.p, H.size() * sizeof(int16_t), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(inf.data(), c->d_inf.p, inf.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+        }
+    }
+    release(dT);
+    if (rc != LOFP_OK) return rc;
+    if (e != hipSuccess) return fail(LOFP_EDEVICE, hipGetErrorString(e));
+    for (size_t i = 0; i < L.size(); ++i) { lo[i] = L[i]; hi[i] = H[i]; }
+    for (int p = 0; p < batch; ++p) feasible[p] = !inf[p];
+    return LOFP_OK;
+}
+
 lofp_status lofp_bs_table(lofp_circuit c, int32_t gate, int32_t N, lofp_c128 *out)
 {
     if (!c || !out) return fail(LOFP_EINVAL, "null argument");

@@ -22,7 +22,7 @@ PREC_FP64, PREC_FP32 = 0, 1
 
 EXPORTED = (
     "lofp_last_error", "lofp_version", "lofp_circuit_create", "lofp_circuit_destroy", "lofp_light_cone",
-    "lofp_bounds", "lofp_bs_table", "lofp_amplitudes_device", "lofp_amplitudes", "lofp_amplitude",
+    "lofp_bounds", "lofp_bounds_batch", "lofp_bs_table", "lofp_amplitudes_device", "lofp_amplitudes", "lofp_amplitude",
     "lofp_path_counts", "lofp_amplitudes_multi", "lofp_server_create", "lofp_server_submit",
     "lofp_server_result", "lofp_server_get_stats", "lofp_server_destroy",
 )
@@ -103,6 +103,7 @@ def load():
     lib.lofp_circuit_destroy.argtypes = [vp]
     lib.lofp_light_cone.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, i32p, i32p, i32p, i32p]
     lib.lofp_bounds.argtypes = [vp, i32p, i32p, i32p, i32p, i32p]
+    lib.lofp_bounds_batch.argtypes = [vp, i32p, ctypes.c_int32, i32p, i32p, i32p, i32p]
     lib.lofp_bs_table.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(C128)]
     lib.lofp_amplitudes_device.argtypes = [vp, i32p, ctypes.c_int32, vp, vp, ctypes.POINTER(Opts), vp,
                                            ctypes.POINTER(Stats)]
@@ -199,6 +200,16 @@ class Circuit:
         return lo.reshape(self.depth + 1, self.m - 1), hi.reshape(self.depth + 1, self.m - 1), bool(f.value)
 
     # -- device calls
+    def bounds_batch(self, S, Ts) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+        """Device planner's bounds for every row of Ts: lo, hi [B, D+1, m-1], feasible [B]."""
+        S, Ts = _i32(S), _i32(np.atleast_2d(Ts))
+        B = Ts.shape[0]
+        lo = np.zeros((B, self.depth + 1, self.m - 1), dtype=np.int32)
+        hi = np.zeros_like(lo)
+        f = np.zeros(B, dtype=np.int32)
+        _check(load().lofp_bounds_batch(self._h, _ip(S), B, _ip(Ts), _ip(lo), _ip(hi), _ip(f)))
+        return lo, hi, f.astype(bool)
+
     def bs_table(self, gate: int, N: int) -> np.ndarray:
         """Sector N of beam splitter `gate`: W[x1, y1] = <y1,N-y1|BS|x1,N-x1>."""
         out = (C128 * ((N + 1) * (N + 1)))()

@@ -491,3 +491,41 @@ def test_server_fp32_bounds_and_fallbacks():
                 assert abs(amp - want) <= ATOL
             else:
                 assert eb <= 1e-6 * abs(amp) or st["fp64_fallbacks"] > 0
+
+
+# ------------------------------------------------------------------ planner
+@pytest.mark.parametrize("case", ["c2", "c3", "deep", "served"])
+def test_device_bounds_equal_host_bounds(case):
+    """The planner kernel's intervals (one wave per pattern) are the host
+    propagation's, integer for integer; feasibility likewise.  Covers single
+    and bunched photons, a depth-20 circuit and a served request shape."""
+    rng = np.random.default_rng(31)
+    if case in ("c2", "c3"):
+        wl = workloads.make(case, seed=0)
+        m, layers, S, Ts = wl.m, wl.layers, wl.S, np.asarray(wl.Ts[:512], dtype=np.int32)
+    elif case == "deep":
+        m, layers = 8, _brickwork(8, 20, seed=32)
+        S = np.array([1, 0, 1, 0, 1, 0, 1, 0], np.int32)
+        Ts = np.zeros((200, m), np.int32)
+        for row in Ts:
+            for _ in range(4):
+                row[rng.integers(m)] += 1
+    else:
+        r = workloads.served_requests(1, rate_hz=0.0, seed=33)[0]
+        m, layers, S = r.m, r.layers, r.S
+        Ts = np.zeros((200, m), np.int32)
+        for row in Ts:
+            for _ in range(int(np.sum(S))):
+                row[min(m - 1, max(0, int(np.flatnonzero(S)[rng.integers(len(np.flatnonzero(S)))] + rng.integers(-3, 4))))] += 1
+    Ts = Ts.copy()
+    Ts[3, 0] += 1                      # wrong photon number: infeasible
+    c = lofp.Circuit(m, layers)
+    lo, hi, feas = c.bounds_batch(S, Ts)
+    nfeas = 0
+    for p in range(Ts.shape[0]):
+        hl, hh, hf = c.bounds(S, Ts[p])
+        assert feas[p] == hf, p
+        if hf:
+            nfeas += 1
+            assert np.array_equal(lo[p], hl) and np.array_equal(hi[p], hh), p
+    assert not feas[3] and nfeas > 0
