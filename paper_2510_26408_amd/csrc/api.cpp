@@ -637,8 +637,6 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     if (!sp->on_device) {
         HIPCHK(upload(sp->d_top, sp->top.steps, s));
         HIPCHK(upload(sp->d_bot, sp->bot.steps, s));
-        HIPCHK(upload(sp->d_top_live, sp->top.live_out, s));
-        HIPCHK(upload(sp->d_bot_live, sp->bot.live_out, s));
         sp->on_device = true;
     }
     if (!c.h_pin) HIPCHK(hipHostMalloc((void **)&c.h_pin, 64, hipHostMallocDefault));
@@ -702,6 +700,14 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     ContractJob bj = tj;
     tj.nsteps = (int)sp->top.steps.size(); tj.steps = sp->d_top.as<ContractStep>();
     bj.nsteps = (int)sp->bot.steps.size(); bj.steps = sp->d_bot.as<ContractStep>();
+    // the bottom states are written in the top state's variable order
+    {
+        const std::vector<int> &tl = sp->top.live_out, &bl = sp->bot.live_out;
+        bj.out_remap = 1;
+        bj.out_pos = 0;
+        for (size_t q2 = 0; q2 < bl.size(); ++q2)
+            bj.out_pos |= (uint64_t)(std::find(tl.begin(), tl.end(), bl[q2]) - tl.begin()) << (4 * q2);
+    }
     HIPCHK(ensure(c.d_jobs, (size_t)std::max(nj, 1) * sizeof(ContractJob)));
     HIPCHK(ensure(c.d_kinf, (size_t)std::max(nj, 1) * sizeof(int32_t)));
     HIPCHK(launch_key_jobs(ka, ntop, nbot, tj, bj, c.d_jobs.as<ContractJob>(), c.d_kinf.as<int32_t>(), s));
@@ -748,9 +754,10 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     ja.tlo = ka.klo; ja.thi = ka.khi;
     ja.blo = ka.klo + (size_t)B * span; ja.bhi = ka.khi + (size_t)B * span;
     ja.nshared = (int)sp->top.live_out.size();
-    ja.top_live = sp->d_top_live.as<int32_t>();
-    ja.bot_live = sp->d_bot_live.as<int32_t>();
-    ja.var_cut = c.d_var_cut.as<int32_t>(); ja.var_time = c.d_var_time.as<int32_t>();
+    for (int q = 0; q < ja.nshared; ++q) {
+        const int v = sp->top.live_out[q];
+        ja.cidx[q] = c.var_time[v] * nc + c.var_cut[v];
+    }
     ja.top_state = c.d_kstate.as<double2>();
     ja.bot_state = c.d_kstate.as<double2>() + (size_t)ntop * mx;
     ja.state_cap = mx;

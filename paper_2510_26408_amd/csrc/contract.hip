@@ -369,7 +369,36 @@ __device__ void contract_run(const ContractJob &g, unsigned char *smem, unsigned
             if (threadIdx.x == 0) atomicOr(overflow, 1);
             return;
         }
-        for (int i = threadIdx.x; i < cur_size; i += BS) g.state_out[i] = bufA[i];
+        if (!g.out_remap || g.nsteps == 0) {
+            for (int i = threadIdx.x; i < cur_size; i += BS) g.state_out[i] = bufA[i];
+        } else {
+            // write in the order out_pos gives (mixed radix over the same
+            // radii); the step layouts' LDS is free by now
+            int *s_rad = reinterpret_cast<int *>(desc), *s_ostr = s_rad + kMaxActive;
+            const ContractStep &last = g.steps[g.nsteps - 1];
+            const int nv = last.n_new;
+            if (threadIdx.x == 0) {
+                for (int q = 0; q < nv; ++q) s_rad[q] = vrad[last.new_vars[q]];
+                for (int q = 0; q < nv; ++q) {
+                    const int pq = (int)(g.out_pos >> (4 * q)) & 15;
+                    int st = 1;
+                    for (int q2 = 0; q2 < nv; ++q2)
+                        if (((int)(g.out_pos >> (4 * q2)) & 15) < pq) st *= s_rad[q2];
+                    s_ostr[q] = st;
+                }
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < cur_size; i += BS) {
+                int rem = i, o = 0;
+                for (int q = 0; q < nv; ++q) {
+                    const int r = s_rad[q];
+                    const int d = rem % r;
+                    rem /= r;
+                    o += d * s_ostr[q];
+                }
+                g.state_out[o] = bufA[i];
+            }
+        }
         if (STATS) atomicAdd(stat_transitions, trans);
         return;
     }
@@ -492,7 +521,9 @@ hipError_t launch_multi_sizes(int count, const ContractJob *jobs, int *mx, hipSt
 
 // Join of a split contraction, one wave per pattern: the sum over the
 // pattern's own box of crossing versions of TOP(versions) * BOT(versions),
-// each state addressed by value through its key's interval layout.
+// each state addressed by value through its key's interval layout.  Both
+// states list the crossing versions in the same order, so neighbouring lanes
+// read neighbouring entries of both.
 __global__ __launch_bounds__(64) void k_join(JoinArgs g)
 {
     const int p = blockIdx.x;
@@ -505,40 +536,24 @@ __global__ __launch_bounds__(64) void k_join(JoinArgs g)
     const int16_t *plo = g.lo + (int64_t)p * span, *phi = g.hi + (int64_t)p * span;
     const int16_t *tlo = g.tlo + (int64_t)tk * span, *thi = g.thi + (int64_t)tk * span;
     const int16_t *blo = g.blo + (int64_t)bk * span, *bhi = g.bhi + (int64_t)bk * span;
-    // per crossing variable (top order): pattern box, top stride/offset, bottom stride/offset
-    int prad[kMaxActive], pstr[kMaxActive], toff[kMaxActive], tstr[kMaxActive], boff[kMaxActive], bstr[kMaxActive];
+    // per crossing variable (both states in the top order): pattern box,
+    // top stride/offset, bottom stride/offset
+    int pstr[kMaxActive], toff[kMaxActive], tstr[kMaxActive], boff[kMaxActive], bstr[kMaxActive];
     float pinv[kMaxActive];
-    int box = 1, ts = 1;
+    int box = 1, ts = 1, bs = 1;
 #pragma unroll
     for (int q = 0; q < kMaxActive; ++q) {
-        prad[q] = 1; pstr[q] = box; pinv[q] = 1.0f / (float)box; toff[q] = 0; tstr[q] = 0; boff[q] = 0; bstr[q] = 0;
+        pstr[q] = box; pinv[q] = 1.0f / (float)box; toff[q] = 0; tstr[q] = 0; boff[q] = 0; bstr[q] = 0;
         if (q < g.nshared) {
-            const int v = g.top_live[q];
-            const int i = g.var_time[v] * nc + g.var_cut[v];
-            prad[q] = phi[i] - plo[i] + 1;
-            toff[q] = plo[i] - tlo[i];          // top digit = pattern digit + toff
+            const int i = g.cidx[q];
+            const int pl = plo[i], ph = phi[i], tl = tlo[i], th = thi[i], bl = blo[i], bh = bhi[i];
+            toff[q] = pl - tl;          // state digit = pattern digit + offset
+            boff[q] = pl - bl;
             tstr[q] = ts;
-            ts *= thi[i] - tlo[i] + 1;
-            box *= prad[q] > 0 ? prad[q] : 0;
-        }
-    }
-    // bottom strides follow the bottom state's own order
-    {
-        int bs = 1;
-#pragma unroll
-        for (int q2 = 0; q2 < kMaxActive; ++q2) {
-            if (q2 < g.nshared) {
-                const int v = g.bot_live[q2];
-                const int i = g.var_time[v] * nc + g.var_cut[v];
-#pragma unroll
-                for (int q = 0; q < kMaxActive; ++q) {
-                    if (q < g.nshared && g.top_live[q] == v) {
-                        bstr[q] = bs;
-                        boff[q] = plo[i] - blo[i];
-                    }
-                }
-                bs *= bhi[i] - blo[i] + 1;
-            }
+            bstr[q] = bs;
+            ts *= th - tl + 1;
+            bs *= bh - bl + 1;
+            box *= ph >= pl ? ph - pl + 1 : 0;
         }
     }
     const gdouble *TS = (const gdouble *)(g.top_state + (int64_t)tk * g.state_cap);

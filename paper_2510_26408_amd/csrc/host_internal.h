@@ -112,14 +112,12 @@ struct Schedule {
 struct SplitProgram {
     int rs = 0;
     Schedule top, bot;
-    DevBuf d_top, d_bot, d_top_live, d_bot_live;
+    DevBuf d_top, d_bot;
     bool on_device = false;
     ~SplitProgram()
     {
         release(d_top);
         release(d_bot);
-        release(d_top_live);
-        release(d_bot_live);
     }
 };
 

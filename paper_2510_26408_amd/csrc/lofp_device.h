@@ -227,6 +227,9 @@ struct ContractJob {
     double2 *state_out;          // if set: write the final state here instead of summing it
     int state_cap;               // entries available at state_out
     int stats;                   // count transitions into the statistics counter
+    int out_remap;               // state_out in another variable order: the
+    uint64_t out_pos;            // final state's variable q goes to place
+                                 // (out_pos >> 4q) & 15
 };
 // Per-launch overrides for key jobs of a split contraction (0 / nullptr: use
 // the job's own fields): one state size for every job, and per-job slices of
@@ -297,9 +300,9 @@ struct JoinArgs {
     const int16_t *tlo, *thi;        // per top key [ntop][span]
     const int16_t *blo, *bhi;        // per bottom key [nbot][span]
     int nshared;
-    const int32_t *top_live;         // crossing variables in the top state's order
-    const int32_t *bot_live;         // the same variables in the bottom state's order
-    const int32_t *var_cut, *var_time;
+    int cidx[kMaxActive];            // interval index (time * (m-1) + cut) of each
+                                     // crossing variable, in the top state's order;
+                                     // both states are laid out in that order
     const double2 *top_state, *bot_state;
     int state_cap;
     double2 *out;
