@@ -27,6 +27,8 @@
 // over the new state, each entry gathered in a fixed order; the final sum is
 // compensated and combined in a fixed order.  With unit weights the same
 // program counts the valid paths.
+#include <utility>
+
 #include "lofp_device.h"
 
 namespace lofp {
@@ -524,6 +526,9 @@ hipError_t launch_multi_sizes(int count, const ContractJob *jobs, int *mx, hipSt
 // each state addressed by value through its key's interval layout.  Both
 // states list the crossing versions in the same order, so neighbouring lanes
 // read neighbouring entries of both.
+// NS: the number of crossing versions (a compile-time count, so the set-up
+// loads are all issued together and the digit loop has no branches).
+template <int NS>
 __global__ __launch_bounds__(64) void k_join(JoinArgs g)
 {
     const int p = blockIdx.x;
@@ -538,38 +543,41 @@ __global__ __launch_bounds__(64) void k_join(JoinArgs g)
     const int16_t *blo = g.blo + (int64_t)bk * span, *bhi = g.bhi + (int64_t)bk * span;
     // per crossing variable (both states in the top order): pattern box,
     // top stride/offset, bottom stride/offset
-    int pstr[kMaxActive], toff[kMaxActive], tstr[kMaxActive], boff[kMaxActive], bstr[kMaxActive];
-    float pinv[kMaxActive];
+    int pl[NS > 0 ? NS : 1], ph[NS > 0 ? NS : 1], tl[NS > 0 ? NS : 1], th[NS > 0 ? NS : 1];
+    int bl[NS > 0 ? NS : 1], bh[NS > 0 ? NS : 1];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const int i = g.cidx[q];
+        pl[q] = plo[i]; ph[q] = phi[i]; tl[q] = tlo[i]; th[q] = thi[i]; bl[q] = blo[i]; bh[q] = bhi[i];
+    }
+    int pstr[NS > 0 ? NS : 1], toff[NS > 0 ? NS : 1], tstr[NS > 0 ? NS : 1], boff[NS > 0 ? NS : 1];
+    int bstr[NS > 0 ? NS : 1];
+    float pinv[NS > 0 ? NS : 1];
     int box = 1, ts = 1, bs = 1;
 #pragma unroll
-    for (int q = 0; q < kMaxActive; ++q) {
-        pstr[q] = box; pinv[q] = 1.0f / (float)box; toff[q] = 0; tstr[q] = 0; boff[q] = 0; bstr[q] = 0;
-        if (q < g.nshared) {
-            const int i = g.cidx[q];
-            const int pl = plo[i], ph = phi[i], tl = tlo[i], th = thi[i], bl = blo[i], bh = bhi[i];
-            toff[q] = pl - tl;          // state digit = pattern digit + offset
-            boff[q] = pl - bl;
-            tstr[q] = ts;
-            bstr[q] = bs;
-            ts *= th - tl + 1;
-            bs *= bh - bl + 1;
-            box *= ph >= pl ? ph - pl + 1 : 0;
-        }
+    for (int q = 0; q < NS; ++q) {
+        pstr[q] = box;
+        pinv[q] = 1.0f / (float)box;
+        toff[q] = pl[q] - tl[q];          // state digit = pattern digit + offset
+        boff[q] = pl[q] - bl[q];
+        tstr[q] = ts;
+        bstr[q] = bs;
+        ts *= th[q] - tl[q] + 1;
+        bs *= bh[q] - bl[q] + 1;
+        box *= ph[q] >= pl[q] ? ph[q] - pl[q] + 1 : 0;
     }
     const gdouble *TS = (const gdouble *)(g.top_state + (int64_t)tk * g.state_cap);
     const gdouble *BS_ = (const gdouble *)(g.bot_state + (int64_t)bk * g.state_cap);
     CSum sr{0.0, 0.0}, si{0.0, 0.0};
-#pragma unroll 2
+#pragma unroll 4
     for (int e = threadIdx.x; e < box; e += 64) {
         int rem = e, ti = 0, bi = 0;
 #pragma unroll
-        for (int q = kMaxActive - 1; q >= 0; --q) {
-            if (q < g.nshared) {
-                const int d = qdiv(rem, pstr[q], pinv[q]);
-                rem -= d * pstr[q];
-                ti += (d + toff[q]) * tstr[q];
-                bi += (d + boff[q]) * bstr[q];
-            }
+        for (int q = NS - 1; q >= 0; --q) {
+            const int d = q > 0 ? qdiv(rem, pstr[q], pinv[q]) : rem;
+            rem -= d * pstr[q];
+            ti += (d + toff[q]) * tstr[q];
+            bi += (d + boff[q]) * bstr[q];
         }
         const double2 c = cmul(make_double2(TS[2 * ti], TS[2 * ti + 1]), make_double2(BS_[2 * bi], BS_[2 * bi + 1]));
         csum_add(sr, c.x);
@@ -586,10 +594,19 @@ __global__ __launch_bounds__(64) void k_join(JoinArgs g)
     if (threadIdx.x == 0) g.out[p] = make_double2(sr.s + sr.c, si.s + si.c);
 }
 
+template <int... N>
+static void launch_join_ns(const JoinArgs &a, hipStream_t stream, std::integer_sequence<int, N...>)
+{
+    using K = void (*)(JoinArgs);
+    static const K table[] = {k_join<N>...};
+    hipLaunchKernelGGL(table[a.nshared], dim3(a.B), dim3(64), 0, stream, a);
+}
+
 hipError_t launch_join(const JoinArgs &a, hipStream_t stream)
 {
     if (a.B == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_join, dim3(a.B), dim3(64), 0, stream, a);
+    if (a.nshared < 0 || a.nshared > kMaxActive) return hipErrorInvalidValue;
+    launch_join_ns(a, stream, std::make_integer_sequence<int, kMaxActive + 1>{});
     return hipGetLastError();
 }
 
