@@ -256,11 +256,14 @@ def run_variant(lofp, workloads, torch, dev, stream, name, method, steps=5, fwd=
 
 
 def variants(lofp, workloads, torch, dev, stream):
-    """The depth-first path-sum form on the same batch, the contraction on the
-    m=32, n=16 workload, and the served mixed-request workload."""
+    """The path-sum forms on the same batch, the contraction on the small
+    single-pattern, the bunched and the m=32, n=16 workloads, and the served
+    mixed-request workload."""
     return {"pathsum_c2": run_variant(lofp, workloads, torch, dev, stream, "c2", lofp.METHOD_PATHSUM, steps=3),
             "pathsum_dfs_c2": run_variant(lofp, workloads, torch, dev, stream, "c2", lofp.METHOD_PATHSUM, steps=2,
                                           fwd=5, bwd=6),
+            "contract_c1": run_variant(lofp, workloads, torch, dev, stream, "c1", lofp.METHOD_CONTRACT, steps=50),
+            "contract_c3": run_variant(lofp, workloads, torch, dev, stream, "c3", lofp.METHOD_CONTRACT, steps=20),
             "contract_c5": run_variant(lofp, workloads, torch, dev, stream, "c5", lofp.METHOD_CONTRACT, steps=20),
             "served_c4": serve_variant(lofp, workloads)}
 

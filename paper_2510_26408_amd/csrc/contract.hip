@@ -43,8 +43,6 @@ __device__ __forceinline__ int qdiv(int a, int d, float inv)
     return q;
 }
 
-enum { RK_CONST = 0, RK_NEW = 1, RK_SUM = 2 };
-
 // a table in global memory, read as pairs of doubles (lets the compiler use
 // global loads with a 32-bit offset rather than flat ones)
 typedef const double __attribute__((address_space(1))) gdouble;
@@ -58,10 +56,17 @@ typedef const double __attribute__((address_space(1))) gdouble;
 // (division by an invariant integer, Granlund and Montgomery: with
 // shift = 31 + ceil(log2 nstr) and magic = ceil(2^shift / nstr) the error of
 // e * magic / 2^shift stays below 2^-9 / nstr).
+// The splitter's photon numbers x1 (mode r in), y1 (mode r out) and N (both
+// modes) are differences of its four cut references, so each is an affine
+// function of the entry's first four digits and of the summed versions i0,
+// i1: Q = kq + sum_j wq[j] d_j + cq0 i0 + cq1 i1 for Q in (x1, y1, N), with
+// weights and coefficients in {-1, 0, 1} (q = x, y, n below).
 struct StepDesc {
     int new_size, n_new, gate;
-    int srad0, srad1, slo0, slo1, sstr0, sstr1;
-    int rk[4], ra[4], nlo[4];
+    int srad0, srad1, sstr0, sstr1;
+    int kx, ky, kn;
+    int cx0, cy0, cn0, cx1, cy1, cn1;
+    int4 wx, wy, wn;
     int4 dig[kMaxActive];
     float ninv[kMaxActive];
 };
@@ -114,43 +119,66 @@ __device__ inline void build_desc(const ContractStep &st, const int *vlo, const 
         }
         d.dig[q] = make_int4(nsi, ms, (int)(unsigned)mg, sh);
         d.ninv[q] = 1.0f / (float)nsi;
-        if (q < 4) d.nlo[q] = q < n_new ? vlo[st.new_vars[q]] : 0;
         if (q < n_new) ns *= vrad[st.new_vars[q]];
     }
     d.new_size = ns < (1 << 30) ? (int)ns : (1 << 30);
     d.n_new = n_new;
     d.gate = st.gate;
-    d.srad0 = 1; d.srad1 = 1; d.slo0 = 0; d.slo1 = 0; d.sstr0 = 0; d.sstr1 = 0;
+    d.srad0 = 1; d.srad1 = 1; d.sstr0 = 0; d.sstr1 = 0;
+    int slo[2] = {0, 0};
     if (st.n_sum > 0) {
         const int v = st.sum_vars[0], src = st.sum_to_old[0];
         int ss = 0;
 #pragma unroll
         for (int q2 = 0; q2 < kMaxActive; ++q2) ss = (q2 == src) ? ostr[q2] : ss;
-        d.srad0 = vrad[v]; d.slo0 = vlo[v]; d.sstr0 = ss;
+        d.srad0 = vrad[v]; slo[0] = vlo[v]; d.sstr0 = ss;
     }
     if (st.n_sum > 1) {
         const int v = st.sum_vars[1], src = st.sum_to_old[1];
         int ss = 0;
 #pragma unroll
         for (int q2 = 0; q2 < kMaxActive; ++q2) ss = (q2 == src) ? ostr[q2] : ss;
-        d.srad1 = vrad[v]; d.slo1 = vlo[v]; d.sstr1 = ss;
+        d.srad1 = vrad[v]; slo[1] = vlo[v]; d.sstr1 = ss;
     }
+    // each reference as k + (digit j) + c0 i0 + c1 i1
+    int K[4], J[4], C0[4], C1[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int kind = st.ref_kind[k], arg = st.ref_arg[k];
-        if (kind == CREF_NEW) { d.rk[k] = RK_NEW; d.ra[k] = arg; }
-        else if (kind == CREF_SUM) { d.rk[k] = RK_SUM; d.ra[k] = arg; }
-        else {
-            d.rk[k] = RK_CONST;
-            d.ra[k] = kind == CREF_ZERO ? 0 : kind == CREF_N ? n : kind == CREF_SPRE ? spre[arg] : tpre[arg];
+        J[k] = -1; C0[k] = 0; C1[k] = 0;
+        if (kind == CREF_NEW) {
+            K[k] = vlo[st.new_vars[arg]];
+            J[k] = arg;
+        } else if (kind == CREF_SUM) {
+            K[k] = slo[arg & 1];
+            C0[k] = arg == 0;
+            C1[k] = arg == 1;
+        } else {
+            K[k] = kind == CREF_ZERO ? 0 : kind == CREF_N ? n : kind == CREF_SPRE ? spre[arg] : tpre[arg];
         }
     }
+    // x1 = before - below, y1 = after - below, N = above - below
+    d.kx = K[0] - K[2]; d.ky = K[1] - K[2]; d.kn = K[3] - K[2];
+    d.cx0 = C0[0] - C0[2]; d.cy0 = C0[1] - C0[2]; d.cn0 = C0[3] - C0[2];
+    d.cx1 = C1[0] - C1[2]; d.cy1 = C1[1] - C1[2]; d.cn1 = C1[3] - C1[2];
+    int w[3][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int below = J[2] == j;
+        w[0][j] = (J[0] == j) - below;
+        w[1][j] = (J[1] == j) - below;
+        w[2][j] = (J[3] == j) - below;
+    }
+    d.wx = make_int4(w[0][0], w[0][1], w[0][2], w[0][3]);
+    d.wy = make_int4(w[1][0], w[1][1], w[1][2], w[1][3]);
+    d.wn = make_int4(w[2][0], w[2][1], w[2][2], w[2][3]);
 }
 
 // Entries of a new state for one step: each entry gathers its summed
-// versions in a fixed order (i1 outer, i0 inner).  Loads and products carry
-// no branch, so the visits of an entry overlap: an invalid visit reads the
-// gate table's zero slot and adds an exact zero.  STATS: also count the
+// versions in a fixed order (i1 outer, i0 inner), the same trip counts in
+// every lane.  Loads and products carry no branch, so the visits of an entry
+// overlap: a visit without a transition (not 0 <= x1, y1 <= N) reads the gate
+// table's zero slot and adds an exact zero.  STATS: also count the
 // transitions with a nonzero source (statistics only).
 //
 // Decoding an entry into its digits: small blocks keep the step's strides in
@@ -174,11 +202,9 @@ __device__ __forceinline__ void step_entries(const StepDesc &d, const double2 *_
             ninv[q] = d.ninv[q];
         }
     }
-    const int srad0 = d.srad0, srad1 = d.srad1, slo0 = d.slo0, slo1 = d.slo1, sstr0 = d.sstr0, sstr1 = d.sstr1;
-    int rk[4], ra[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) { rk[k] = d.rk[k]; ra[k] = d.ra[k]; }
-    const int nlo0 = d.nlo[0], nlo1 = d.nlo[1], nlo2 = d.nlo[2], nlo3 = d.nlo[3];
+    const int srad0 = d.srad0, srad1 = d.srad1, sstr0 = d.sstr0, sstr1 = d.sstr1;
+    const int cx0 = d.cx0, cy0 = d.cy0, cn0 = d.cn0, cx1 = d.cx1, cy1 = d.cy1, cn1 = d.cn1;
+    const int4 wx = d.wx, wy = d.wy, wn = d.wn;
     for (int e = threadIdx.x; e < new_size; e += BS) {
         int rem = e, base_old = 0;
         int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
@@ -208,14 +234,10 @@ __device__ __forceinline__ void step_entries(const StepDesc &d, const double2 *_
                 }
             }
         }
-        const int nv0 = nlo0 + d0, nv1 = nlo1 + d1, nv2 = nlo2 + d2, nv3 = nlo3 + d3;
-        // values of the four references that do not depend on the summed versions
-        int cv[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int a = ra[k];
-            cv[k] = rk[k] == RK_NEW ? (a == 0 ? nv0 : a == 1 ? nv1 : a == 2 ? nv2 : nv3) : a;
-        }
+        // the splitter's photon numbers at i0 = i1 = 0
+        const int bx = d.kx + wx.x * d0 + wx.y * d1 + wx.z * d2 + wx.w * d3;
+        const int by = d.ky + wy.x * d0 + wy.y * d1 + wy.z * d2 + wy.w * d3;
+        const int bn = d.kn + wn.x * d0 + wn.y * d1 + wn.z * d2 + wn.w * d3;
         double2 acc = make_double2(0.0, 0.0);
         // one transition: acc += prev * W[wi] (an invalid one reads the zero slot)
         auto visit = [&](const double2 prev, bool ok, unsigned wi) {
@@ -231,26 +253,24 @@ __device__ __forceinline__ void step_entries(const StepDesc &d, const double2 *_
                 const unsigned wo = 2u * (ok ? wi : zslot);
                 const double2 w = make_double2(W[wo], W[wo + 1]);
                 if (F32) {
-                    const float px = (float)prev.x, py = (float)prev.y, wx = (float)w.x, wy = (float)w.y;
-                    acc.x += (double)(px * wx - py * wy);
-                    acc.y += (double)(px * wy + py * wx);
+                    const float px = (float)prev.x, py = (float)prev.y, wx_ = (float)w.x, wy_ = (float)w.y;
+                    acc.x += (double)(px * wx_ - py * wy_);
+                    acc.y += (double)(px * wy_ + py * wx_);
                 } else {
                     acc = cfma(prev, w, acc);
                 }
             }
         };
         for (int i1 = 0; i1 < srad1; ++i1) {
+            const int gx = bx + cx1 * i1, gy = by + cy1 * i1, gn = bn + cn1 * i1;
             const int ob = base_old + i1 * sstr1;
 #pragma unroll 2
             for (int i0 = 0; i0 < srad0; ++i0) {
                 const double2 prev = bufA[ob + i0 * sstr0];
-                int val[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    val[k] = rk[k] == RK_SUM ? (ra[k] == 0 ? slo0 + i0 : slo1 + i1) : cv[k];
-                const int N = val[3] - val[2], x1 = val[0] - val[2], y1 = val[1] - val[2];
-                const bool ok = x1 >= 0 && y1 >= 0 && x1 <= N && y1 <= N;
-                visit(prev, ok, (unsigned)(sector_offset(N) + x1 * (N + 1) + y1));
+                const int N = gn + cn0 * i0, x1 = gx + cx0 * i0, y1 = gy + cy0 * i0;
+                const bool ok = (x1 < y1 ? x1 : y1) >= 0 && (x1 > y1 ? x1 : y1) <= N;
+                const unsigned un = (unsigned)N;
+                visit(prev, ok, un * (un + 1u) * (2u * un + 1u) / 6u + (unsigned)x1 * (un + 1u) + (unsigned)y1);
             }
         }
         bufB[e] = acc;
