@@ -139,6 +139,15 @@ void s_only_bounds(const lofp_circuit_s &c, const int32_t *S, int n, std::vector
     (void)propagate_bounds(m, D, n, c.cut_gate.data(), lo.data(), hi.data());
 }
 
+void s_only_cached(lofp_circuit_s &c, const int32_t *S, int n)
+{
+    if (!c.sb_S.empty() && std::equal(c.sb_S.begin(), c.sb_S.end(), S)) return;
+    c.sb_S.assign(S, S + c.m);
+    s_only_bounds(c, S, n, c.sb_lo, c.sb_hi);
+    c.sb_prog = -1;
+    c.sb_split.clear();
+}
+
 namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -585,9 +594,9 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
     a.stats = st != nullptr && count_work;
     // state size: the S-side bound holds for every pattern; only when it is too
     // large for LDS ask the device for this batch's exact maximum
-    std::vector<int16_t> slo, shi;
-    s_only_bounds(c, S, n, slo, shi);
-    int64_t max_states = program_state_bound(c, slo, shi);
+    s_only_cached(c, S, n);
+    if (c.sb_prog < 0) c.sb_prog = program_state_bound(c, c.sb_lo, c.sb_hi);
+    const int64_t max_states = c.sb_prog;
     a.max_states = (int)std::min<int64_t>(max_states, 1 << 22);
     a.ws = nullptr;
     if (max_states > (1 << 22) || contract_lds_bytes(a, true) > 64 * 1024) {
@@ -639,20 +648,20 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
         HIPCHK(upload(sp->d_bot, sp->bot.steps, s));
         sp->on_device = true;
     }
-    if (!c.h_pin) HIPCHK(hipHostMalloc((void **)&c.h_pin, 64, hipHostMallocDefault));
+    if (!c.h_pin) HIPCHK(hipHostMalloc((void **)&c.h_pin, 1024, hipHostMallocDefault));
     tm.mark();
     lofp_status rc = run_bounds(c, B, n, T_dev, s);
     if (rc != LOFP_OK) return rc;
     bounds_done = true;
     // group the patterns by their two halves of T
     int cap = 1;
-    while (cap < 2 * B) cap <<= 1;
+    while (cap < 4 * B) cap <<= 1;   // load factor <= 1/4: short probe runs
     const void *old_tab = c.d_ktab.p, *old_hull = c.d_khull.p, *old_cnt = c.d_kcnt.p;
-    HIPCHK(ensure(c.d_ktab, (size_t)2 * cap * sizeof(int)));
+    HIPCHK(ensure(c.d_ktab, (size_t)2 * cap * sizeof(unsigned long long)));
     HIPCHK(ensure(c.d_kslot, (size_t)2 * B * sizeof(int)));
     HIPCHK(ensure(c.d_kof, (size_t)2 * cap * sizeof(int)));
-    HIPCHK(ensure(c.d_krep, (size_t)2 * B * sizeof(int)));
-    HIPCHK(ensure(c.d_kcnt, 2 * sizeof(int)));
+    HIPCHK(ensure(c.d_krep, (size_t)2 * kKeySubs * B * sizeof(int)));
+    HIPCHK(ensure(c.d_kcnt, 2 * kKeySubs * sizeof(int)));
     HIPCHK(ensure(c.d_khull, (size_t)2 * 2 * cap * span * sizeof(int)));
     HIPCHK(ensure(c.d_klohi, (size_t)2 * 2 * B * span * sizeof(int16_t)));
     if (c.d_ktab.p != old_tab || c.d_khull.p != old_hull || c.d_kcnt.p != old_cnt) c.ktab_clean = false;
@@ -661,7 +670,7 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     ka.T = T_dev;
     ka.lo = c.d_lo.as<int16_t>(); ka.hi = c.d_hi.as<int16_t>();
     ka.infeasible = c.d_inf.as<int32_t>();
-    ka.table = c.d_ktab.as<int>(); ka.slot = c.d_kslot.as<int>();
+    ka.table = c.d_ktab.as<unsigned long long>(); ka.slot = c.d_kslot.as<int>();
     ka.slot_key = c.d_kof.as<int>(); ka.key_slot = c.d_krep.as<int>(); ka.count = c.d_kcnt.as<int>();
     ka.hlo = c.d_khull.as<int>(); ka.hhi = ka.hlo + (size_t)2 * cap * span;
     ka.klo = c.d_klohi.as<int16_t>(); ka.khi = ka.klo + (size_t)2 * B * span;
@@ -673,24 +682,33 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     // kernel of each call; they are cleared here only when new or when a
     // previous call stopped before that kernel
     if (!c.ktab_clean) {
-        HIPCHK(hipMemsetAsync(ka.table, 0xFF, (size_t)2 * cap * sizeof(int), s));
+        HIPCHK(hipMemsetAsync(ka.table, 0xFF, (size_t)2 * cap * sizeof(unsigned long long), s));
         HIPCHK(hipMemsetAsync(ka.hlo, 0x7F, (size_t)2 * cap * span * sizeof(int), s));
         HIPCHK(hipMemsetAsync(ka.hhi, 0xFF, (size_t)2 * cap * span * sizeof(int), s));
-        HIPCHK(hipMemsetAsync(ka.count, 0, 2 * sizeof(int), s));
+        HIPCHK(hipMemsetAsync(ka.count, 0, 2 * kKeySubs * sizeof(int), s));
     }
     c.ktab_clean = false;
     HIPCHK(launch_keys(ka, s));
-    HIPCHK(hipMemcpyAsync(c.h_pin, c.d_kcnt.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(c.h_pin, c.d_kcnt.p, 2 * kKeySubs * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    const int ntop = c.h_pin[0], nbot = c.h_pin[1];
-    if ((int64_t)(ntop + nbot) * 4 > (int64_t)B * 3) return LOFP_OK;   // little sharing: contract per pattern
+    int ntop = 0, nbot = 0;
+    for (int i = 0; i < kKeySubs; ++i) { ntop += c.h_pin[i]; nbot += c.h_pin[kKeySubs + i]; }
+    if ((int64_t)(ntop + nbot) * 4 > (int64_t)B * 3) {
+        // little sharing: contract per pattern (the bounds are in place)
+        HIPCHK(launch_key_reset(ka, ntop, nbot, s));
+        HIPCHK(hipMemsetAsync(ka.count, 0, 2 * kKeySubs * sizeof(int), s));
+        c.ktab_clean = true;
+        return LOFP_OK;
+    }
     used = true;
     // state capacity from the S-side intervals (they contain every key's
     // hull); the device is asked only when that bound is too large
-    std::vector<int16_t> slo, shi;
-    s_only_bounds(c, S, n, slo, shi);
-    const int64_t cap_s = std::max(steps_state_bound(c, sp->top.steps, slo, shi),
-                                   steps_state_bound(c, sp->bot.steps, slo, shi));
+    s_only_cached(c, S, n);
+    auto sit = c.sb_split.find(rs);
+    if (sit == c.sb_split.end())
+        sit = c.sb_split.emplace(rs, std::max(steps_state_bound(c, sp->top.steps, c.sb_lo, c.sb_hi),
+                                              steps_state_bound(c, sp->bot.steps, c.sb_lo, c.sb_hi))).first;
+    const int64_t cap_s = sit->second;
     const int nj = ntop + nbot;
     ContractJob tj{};
     tj.m = m; tj.n = n; tj.D = c.D; tj.nvars = c.nvars; tj.tab_stride = c.tab_stride; tj.fp32 = fp32;
@@ -719,9 +737,9 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     } else {
         int *d_max = reinterpret_cast<int *>(ctr + 5);
         HIPCHK(launch_multi_sizes(nj, c.d_jobs.as<ContractJob>(), d_max, s));
-        HIPCHK(hipMemcpyAsync(c.h_pin + 2, d_max, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(c.h_pin + 2 * kKeySubs, d_max, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        mx = c.h_pin[2];
+        mx = c.h_pin[2 * kKeySubs];
         if (mx > (1 << 22)) return fail(LOFP_ENOMEM, "contraction state exceeds 2^22 entries");
         mx = std::max(mx, 1);
     }
@@ -1294,9 +1312,9 @@ lofp_status lofp_amplitudes_device(lofp_circuit c, const int32_t *S, int32_t bat
         // contraction state is affordable, otherwise enumerate paths
         method = LOFP_METHOD_PATHSUM;
         if (prepare_program(*c, s) == LOFP_OK) {
-            std::vector<int16_t> slo, shi;
-            s_only_bounds(*c, S, n, slo, shi);
-            if (program_state_bound(*c, slo, shi) <= (1 << 20)) method = LOFP_METHOD_CONTRACT;
+            s_only_cached(*c, S, n);
+            if (c->sb_prog < 0) c->sb_prog = program_state_bound(*c, c->sb_lo, c->sb_hi);
+            if (c->sb_prog <= (1 << 20)) method = LOFP_METHOD_CONTRACT;
         }
         clear_error();
     }

@@ -166,6 +166,12 @@ struct lofp_circuit_s {
     int32_t *h_pin = nullptr;              // small pinned readback buffer
     bool ktab_clean = false;               // key hash table known to be empty
     std::vector<int32_t> S_dev;            // the S now held in d_S
+    // S-only bounds of the last S asked for, and the state bounds under them
+    // (the whole program; each split program by its split cut)
+    std::vector<int32_t> sb_S;
+    std::vector<int16_t> sb_lo, sb_hi;
+    int64_t sb_prog = -1;
+    std::map<int, int64_t> sb_split;
 };
 
 
@@ -200,6 +206,8 @@ struct Timer {
 
 
 lofp_status check_S(const lofp_circuit_s &c, const int32_t *S, int &n);
+// S-only bounds of S, cached on the circuit (the caller holds its lock).
+void s_only_cached(lofp_circuit_s &c, const int32_t *S, int n);
 void s_only_bounds(const lofp_circuit_s &c, const int32_t *S, int n, std::vector<int16_t> &lo,
                    std::vector<int16_t> &hi);
 lofp_status device_init(lofp_circuit_s &c, int n, hipStream_t s);

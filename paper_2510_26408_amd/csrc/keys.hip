@@ -5,7 +5,7 @@
 // one contraction of that half.
 //
 // Per half: an open-addressing hash table over the sub-rows of T (equal rows
-// found by comparing values).  The wave that claims a slot numbers the key;
+// found by comparing hashes, then values).  The wave that claims a slot numbers the key;
 // every member folds its intervals into the slot's hull (feasible members
 // only) and its index into the slot's representative, the lowest-indexed
 // member whose photon number is right, else the lowest member.  The jobs
@@ -24,10 +24,11 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z)
 }
 
 // One wave per (pattern, half); lane i holds row entry i (m <= 32).  The
-// hash is the XOR of per-entry mixes (order-free, so the same on every run);
-// equal hashes are confirmed by comparing the rows lane by lane.  A slot
-// holds p (right photon number) or p + B (otherwise); the minimum over a
-// group is its representative.
+// hash is the XOR of per-entry mixes (order-free, so the same on every run).
+// A slot holds the row's 32-bit hash above p (right photon number) or p + B
+// (otherwise), all ones when empty: a probe compares hashes first and the
+// rows lane by lane only when they agree, and the minimum over a group (one
+// hash) is its representative.
 __global__ __launch_bounds__(256) void k_key_insert(KeyArgs a)
 {
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -44,31 +45,37 @@ __global__ __launch_bounds__(256) void k_key_insert(KeyArgs a)
         tot += __shfl_xor(tot, o, 64);
         h ^= __shfl_xor(h, o, 64);
     }
-    const int v = tot == a.n ? p : p + a.B;
-    int *tab = a.table + (int64_t)half * a.cap;
-    uint32_t j = (uint32_t)(h ^ (h >> 32)) & (uint32_t)(a.cap - 1);
-    // at most B rows per half and cap >= 2B slots: a free slot is always found
+    const unsigned v = (unsigned)(tot == a.n ? p : p + a.B);
+    const unsigned long long hv = (h >> 32) << 32;
+    const unsigned long long mine_e = hv | v;
+    unsigned long long *tab = a.table + (int64_t)half * a.cap;
+    uint32_t j = (uint32_t)h & (uint32_t)(a.cap - 1);
+    // at most B rows per half and cap >= 4B slots: a free slot is always found
     for (int probe = 0; probe < a.cap; ++probe) {
-        int cur = tab[j];
-        if (cur < 0) {
-            int won = 0;
-            if (lane == 0) won = atomicCAS(&tab[j], -1, v);
+        unsigned long long cur = tab[j];
+        if (cur == kKeyEmpty) {
+            unsigned long long won = 0;
+            if (lane == 0) won = atomicCAS(&tab[j], kKeyEmpty, mine_e);
             cur = __shfl(won, 0, 64);
-            if (cur < 0) {
-                // claimed: number the key
+            if (cur == kKeyEmpty) {
+                // claimed: list the slot under its sub-counter (the keys
+                // are numbered by the jobs kernel, through the counts)
                 if (lane == 0) {
-                    const int key = atomicAdd(&a.count[half], 1);   // < B: at most B rows
-                    a.slot_key[(int64_t)half * a.cap + j] = key;
-                    if (key < a.B) a.key_slot[(int64_t)half * a.B + key] = (int)j;
+                    const int sub = (int)(j & (kKeySubs - 1));
+                    const int local = atomicAdd(&a.count[half * kKeySubs + sub], 1);   // < B
+                    if (local < a.B) a.key_slot[((int64_t)half * kKeySubs + sub) * a.B + local] = (int)j;
                 }
                 break;
             }
         }
-        const int occ = cur >= a.B ? cur - a.B : cur;
-        const int y = mine ? a.T[(int64_t)occ * a.m + lane] : x;
-        if (__all(y == x)) {
-            if (lane == 0) atomicMin(&tab[j], v);
-            break;
+        if ((cur >> 32) == (hv >> 32)) {
+            const unsigned cv = (unsigned)cur;
+            const int occ = (int)(cv >= (unsigned)a.B ? cv - a.B : cv);
+            const int y = mine ? a.T[(int64_t)occ * a.m + lane] : x;
+            if (__all(y == x)) {
+                if (lane == 0) atomicMin(&tab[j], mine_e);
+                break;
+            }
         }
         j = (j + 1) & (uint32_t)(a.cap - 1);
     }
@@ -80,6 +87,26 @@ __global__ __launch_bounds__(256) void k_key_insert(KeyArgs a)
         atomicMin(&a.hlo[row + i], (int)a.lo[(int64_t)p * a.span + i]);
         atomicMax(&a.hhi[row + i], (int)a.hi[(int64_t)p * a.span + i]);
     }
+}
+
+// Slot of key k of a half (whole wave): keys are numbered through the
+// sub-counters in order, so key k is entry k - (claims of earlier
+// sub-counters) of its sub-counter's list.
+__device__ __forceinline__ int key_slot_of(const KeyArgs &a, int half, int k)
+{
+    const int lane = threadIdx.x & 63;
+    const int c = a.count[half * kKeySubs + lane];
+    int incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    const int excl = incl - c;
+    const unsigned long long hit = __ballot(k >= excl && k < incl);
+    const int sub = hit ? __ffsll((long long)hit) - 1 : 0;
+    const int local = k - __shfl(excl, sub, 64);
+    return a.key_slot[((int64_t)half * kKeySubs + sub) * a.B + local];
 }
 
 // One wave per key (top keys, then bottom keys; wave w is job w): the key's
@@ -94,10 +121,10 @@ __global__ __launch_bounds__(256) void k_key_jobs(KeyArgs a, int ntop, int nbot,
     const int w = (int)(gt >> 6);
     const int lane = threadIdx.x & 63;
     if (gt < 8) a.counters[gt] = 0;   // the contraction's counters for this call
-    if (gt == 0) { a.count[0] = 0; a.count[1] = 0; }
     if (w >= ntop + nbot) return;
     const int half = w >= ntop, k = half ? w - ntop : w;
-    const int sl = a.key_slot[(int64_t)half * a.B + k];
+    const int sl = key_slot_of(a, half, k);
+    if (lane == 0) a.slot_key[(int64_t)half * a.cap + sl] = k;
     const int64_t srow = ((int64_t)half * a.cap + sl) * a.span;
     const int64_t krow = ((int64_t)half * a.B + k) * a.span;
     for (int i = lane; i < a.span; i += 64) {
@@ -132,9 +159,9 @@ __global__ __launch_bounds__(256) void k_key_jobs(KeyArgs a, int ntop, int nbot,
         a.hhi[srow + i] = -1;
     }
     if (lane != 0) return;
-    int *tab = a.table + (int64_t)half * a.cap;
-    const int rv = tab[sl];
-    tab[sl] = -1;
+    unsigned long long *tab = a.table + (int64_t)half * a.cap;
+    const int rv = (int)(unsigned)tab[sl];
+    tab[sl] = kKeyEmpty;
     a.job_bucket[w] = work > 1.0f ? min(255, (int)(8.0f * log2f(work))) : 0;
     ContractJob J = tmpl;
     J.T = a.T + (int64_t)(rv >= a.B ? rv - a.B : rv) * a.m;
@@ -146,6 +173,25 @@ __global__ __launch_bounds__(256) void k_key_jobs(KeyArgs a, int ntop, int nbot,
     jobs[w] = J;
 }
 
+// One wave per key: empties the key's slot (hull and table entry), for a
+// call that groups the batch but then contracts per pattern (the counts are
+// cleared after it).
+__global__ __launch_bounds__(256) void k_key_reset(KeyArgs a, int ntop, int nbot)
+{
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = (int)(gt >> 6);
+    const int lane = threadIdx.x & 63;
+    if (w >= ntop + nbot) return;
+    const int half = w >= ntop, k = half ? w - ntop : w;
+    const int sl = key_slot_of(a, half, k);
+    const int64_t srow = ((int64_t)half * a.cap + sl) * a.span;
+    for (int i = lane; i < a.span; i += 64) {
+        a.hlo[srow + i] = 0x7f7f7f7f;
+        a.hhi[srow + i] = -1;
+    }
+    if (lane == 0) a.table[(int64_t)half * a.cap + sl] = kKeyEmpty;
+}
+
 // One block: the jobs in decreasing work bucket (a counting sort; the order
 // inside a bucket is arbitrary and changes no result).
 __global__ __launch_bounds__(1024) void k_key_order(KeyArgs a, int nj)
@@ -153,6 +199,7 @@ __global__ __launch_bounds__(1024) void k_key_order(KeyArgs a, int nj)
     __shared__ int hist[256], start[256];
     __shared__ int wsum[4];
     const int t = threadIdx.x;
+    if (t < 2 * kKeySubs) a.count[t] = 0;   // the jobs kernel has read them
     if (t < 256) hist[t] = 0;
     __syncthreads();
     for (int j = t; j < nj; j += blockDim.x) atomicAdd(&hist[255 - a.job_bucket[j]], 1);
@@ -194,6 +241,14 @@ hipError_t launch_key_jobs(const KeyArgs &a, int ntop, int nbot, const ContractJ
     hipLaunchKernelGGL(k_key_jobs, dim3((unsigned)(threads > 0 ? (threads + 255) / 256 : 1)), dim3(256), 0, stream,
                        a, ntop, nbot, top, bot, jobs, kinf);
     hipLaunchKernelGGL(k_key_order, dim3(1), dim3(1024), 0, stream, a, ntop + nbot);
+    return hipGetLastError();
+}
+
+hipError_t launch_key_reset(const KeyArgs &a, int ntop, int nbot, hipStream_t stream)
+{
+    const int64_t threads = (int64_t)(ntop + nbot) * 64;
+    hipLaunchKernelGGL(k_key_reset, dim3((unsigned)(threads > 0 ? (threads + 255) / 256 : 1)), dim3(256), 0, stream,
+                       a, ntop, nbot);
     return hipGetLastError();
 }
 

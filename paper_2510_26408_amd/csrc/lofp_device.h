@@ -251,7 +251,8 @@ struct BoundsJob {
     int16_t *lo, *hi;
     int32_t *infeasible;
 };
-hipError_t launch_bounds_multi(int count, const BoundsJob *jobs, hipStream_t stream);
+// max_span: the largest (D+1)(m-1) over the jobs (sizes the LDS of a wave).
+hipError_t launch_bounds_multi(int count, const BoundsJob *jobs, int max_span, hipStream_t stream);
 // lds_bytes: dynamic LDS per block (max over jobs); max_states: max over jobs
 hipError_t launch_contract_multi(int count, const ContractJob *jobs, size_t lds_bytes, int max_states,
                                  bool state_in_lds, bool fp32, unsigned long long *stat_transitions,
@@ -261,6 +262,8 @@ hipError_t launch_contract_multi(int count, const ContractJob *jobs, size_t lds_
 // Largest state over the jobs (one thread per job), atomically maxed into *mx.
 hipError_t launch_multi_sizes(int count, const ContractJob *jobs, int *mx, hipStream_t stream);
 
+constexpr unsigned long long kKeyEmpty = ~0ULL;   // an empty hash slot
+constexpr int kKeySubs = 64;   // claim counters per half (spread the atomics)
 // Grouping of a batch by the halves of T (split contraction), per half h:
 // a hash table over the distinct half-rows, whose slots carry the group's
 // key number and the hull of its feasible members' intervals.
@@ -269,12 +272,14 @@ struct KeyArgs {
     const int32_t *T;              // [B][m]
     const int16_t *lo, *hi;        // per pattern [B][span]
     const int32_t *infeasible;     // [B]
-    int *table;                    // [2][cap] -1, or the group's lowest member p
+    unsigned long long *table;     // [2][cap] kKeyEmpty, or the row's hash (high
+                                   // 32 bits) above the group's lowest member p
                                    // (p + B if p has the wrong photon number)
     int *slot;                     // [2][B] each pattern's slot
     int *slot_key;                 // [2][cap] key number of a claimed slot
-    int *key_slot;                 // [2][B] slot of each key
-    int *count;                    // [2] keys per half (zeroed by the jobs kernel)
+    int *key_slot;                 // [2][kKeySubs][B] claimed slots per sub-counter
+    int *count;                    // [2][kKeySubs] claims per sub-counter (slot
+                                   // mod kKeySubs); zeroed by the order kernel
     int *hlo, *hhi;                // [2][cap][span] int32 hull per slot
     int16_t *klo, *khi;            // per key intervals (top keys at 0, bottom at B)
     unsigned long long *counters;  // [8] zeroed by the jobs kernel
@@ -290,6 +295,8 @@ hipError_t launch_keys(const KeyArgs &a, hipStream_t stream);
 // Leaves the table, the slot hulls and the counts empty for the next call.
 hipError_t launch_key_jobs(const KeyArgs &a, int ntop, int nbot, const ContractJob &top, const ContractJob &bot,
                            ContractJob *jobs, int32_t *kinf, hipStream_t stream);
+// Empties the table, the slot hulls and the counts without making jobs.
+hipError_t launch_key_reset(const KeyArgs &a, int ntop, int nbot, hipStream_t stream);
 struct JoinArgs {
     int B, m, n, D;
     const int16_t *lo, *hi;          // per pattern [B][span]

@@ -20,7 +20,11 @@ __device__ void bounds_wave(int m, int D, int n, const int32_t *__restrict__ S, 
                             const uint8_t *__restrict__ cut_gate, int16_t *__restrict__ Lg, int16_t *__restrict__ Hg,
                             int32_t *__restrict__ inf)
 {
-    __shared__ int16_t L[kBoundsLds], H[kBoundsLds];
+    // the two interval arrays in dynamic LDS sized to the largest span of
+    // the launch (a few hundred bytes), so a CU holds as many waves as it can
+    extern __shared__ int16_t bounds_lds[];
+    const int nc_ = m - 1, span_ = (D + 1) * nc_;
+    int16_t *L = bounds_lds, *H = bounds_lds + span_;
     __shared__ int sS[kMaxModes], sT[kMaxModes];
     __shared__ int s_bad;
     const int tid = threadIdx.x;
@@ -135,9 +139,10 @@ hipError_t launch_bounds(int B, int m, int D, int n, const int32_t *S, const int
                          int32_t *infeasible, hipStream_t stream)
 {
     if (B == 0) return hipSuccess;
-    if ((D + 1) * (m - 1) <= kBoundsLds) {
-        hipLaunchKernelGGL(k_bounds, dim3(B), dim3(64), 0, stream, B, m, D, n, S, T, fr_lo, fr_hi, br_lo, br_hi,
-                           cut_gate, lo, hi, infeasible);
+    const int span = (D + 1) * (m - 1);
+    if (span <= kBoundsLds) {
+        hipLaunchKernelGGL(k_bounds, dim3(B), dim3(64), (size_t)2 * span * sizeof(int16_t), stream, B, m, D, n, S,
+                           T, fr_lo, fr_hi, br_lo, br_hi, cut_gate, lo, hi, infeasible);
     } else {
         hipLaunchKernelGGL(k_bounds_big, dim3((B + 63) / 64), dim3(64), 0, stream, B, m, D, n, S, T, fr_lo, fr_hi,
                            br_lo, br_hi, cut_gate, lo, hi, infeasible);
@@ -168,10 +173,12 @@ __global__ __launch_bounds__(64) void k_bounds_multi(int count, const BoundsJob 
     *j.infeasible = propagate_bounds(j.m, j.D, j.n, j.cut_gate, j.lo, j.hi);
 }
 
-hipError_t launch_bounds_multi(int count, const BoundsJob *jobs, hipStream_t stream)
+hipError_t launch_bounds_multi(int count, const BoundsJob *jobs, int max_span, hipStream_t stream)
 {
     if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bounds_multi, dim3(count), dim3(64), 0, stream, count, jobs);
+    const int lds_span = max_span < kBoundsLds ? max_span : kBoundsLds;
+    hipLaunchKernelGGL(k_bounds_multi, dim3(count), dim3(64), (size_t)2 * lds_span * sizeof(int16_t), stream, count,
+                       jobs);
     return hipGetLastError();
 }
 

@@ -220,6 +220,7 @@ lofp_status launch_batch(Batch &b, int fp32, bool checked = false)
     b.bj.resize(count);
     b.cj.resize(count);
     size_t ws_off = 0;
+    int max_span = 1;
     for (int i = 0; i < count; ++i) {
         const Req &r = b.reqs[i];
         const lofp_circuit_s &c = *r.c;
@@ -248,11 +249,13 @@ lofp_status launch_batch(Batch &b, int fp32, bool checked = false)
         K.state_out = nullptr;
         K.state_cap = 0;
         K.stats = 0;
+        K.out_remap = 0;
         ws_off += (size_t)2 * r.est;
+        max_span = std::max(max_span, (c.D + 1) * (c.m - 1));
     }
     HIPCHK(upload(b.d_bj, b.bj, s));
     HIPCHK(upload(b.d_cj, b.cj, s));
-    HIPCHK(launch_bounds_multi(count, b.d_bj.as<BoundsJob>(), s));
+    HIPCHK(launch_bounds_multi(count, b.d_bj.as<BoundsJob>(), max_span, s));
     const size_t lds = contract_job_lds_bytes(max_vars, max_m, (int)max_est, in_lds);
     unsigned long long *ctr = b.d_ctr.as<unsigned long long>();
     HIPCHK(launch_contract_multi(count, b.d_cj.as<ContractJob>(), lds, (int)max_est, in_lds, fp32 != 0, ctr,
