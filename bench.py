@@ -292,13 +292,13 @@ def _serve(lofp, reqs, circs, precision, rate_hz=0.0, n_warm=0):
     return amps, bounds, lats, wall, st
 
 
-def serve_variant(lofp, workloads, n_req=2000, n_warm=200, rate_frac=0.5):
+def serve_variant(lofp, workloads, n_req=10000, n_warm=1000, rate_fracs=(0.25, 0.5, 0.75)):
     """Served mixed requests: m in {12,16,24}, n=m/2, depth in {4,6,8}, a fresh
-    circuit and pattern per request.  The FP32-product form (FP64 sums) with
-    its per-result bound, a result whose bound exceeds 1e-6 |amp| recomputed in
-    FP64; beside it the FP64 form.  First the saturated throughput (everything
-    submitted at once), then Poisson arrivals at rate_frac of it; p50/p99 from
-    submit to completion."""
+    circuit and pattern per request.  The FP64 form, and the FP32-product form
+    (FP64 sums) with its per-result bound, a result whose bound exceeds
+    1e-6 |amp| recomputed in FP64.  First the saturated throughput (everything
+    submitted at once), then Poisson arrivals at fractions of it; p50/p99 from
+    submit to completion, after the warm-up requests."""
     reqs = workloads.served_requests(n_req + n_warm, rate_hz=1.0, seed=7)
     circs = [lofp.Circuit(r.m, r.layers) for r in reqs]
     out = {"requests": n_req, "warmup": n_warm}
@@ -314,27 +314,30 @@ def serve_variant(lofp, workloads, n_req=2000, n_warm=200, rate_frac=0.5):
                              "median_rel_err_vs_c128": float(np.median(rel_raw)),
                              "median_bound_over_amp": float(np.median(ratio)),
                              "certifiable_at_1e-6": float((ratio <= 1e-6).mean())}
-    for name, prec in (("fp32_checked", lofp.PREC_FP32), ("fp64", lofp.PREC_FP64)):
+    seed = 8
+    for name, prec, fracs in (("fp64", lofp.PREC_FP64, rate_fracs), ("fp32_checked", lofp.PREC_FP32, (0.5,))):
         # saturated: submit all at once (fresh circuits: the set-up is served too)
         circs_s = [lofp.Circuit(r.m, r.layers) for r in reqs]
         amps, bounds, _, wall, st = _serve(lofp, reqs, circs_s, prec)
         sat = len(reqs) / wall
         rel = float((np.abs(amps - f64)[nz] / np.abs(f64)[nz]).max()) if nz.any() else 0.0
-        # Poisson arrivals at rate_frac * saturated (fresh circuits, new seed)
-        rate = rate_frac * sat
-        reqs2 = workloads.served_requests(n_req + n_warm, rate_hz=rate, seed=8)
-        circs2 = [lofp.Circuit(r.m, r.layers) for r in reqs2]
-        _, _, lats, wall2, st2 = _serve(lofp, reqs2, circs2, prec, rate_hz=rate, n_warm=n_warm)
         rec = {"precision": "fp32 products, fp64 sums, fp64 re-run above 1e-6 |amp|" if prec == lofp.PREC_FP32
-               else "fp64",
-               "saturated_amplitudes_per_s": sat, "rate_hz": rate,
-               "offered_amplitudes_per_s": (n_req + n_warm) / wall2,
-               "p50_ms": float(np.percentile(lats, 50)), "p99_ms": float(np.percentile(lats, 99)),
-               "mean_batch": st2["mean_batch"], "launches": st2["launches"],
-               "max_rel_err_vs_c128": rel}
+               else "fp64", "saturated_amplitudes_per_s": sat, "max_rel_err_vs_c128": rel, "poisson": []}
         if prec == lofp.PREC_FP32:
             rec["fp64_fallback_fraction"] = st["fp64_fallbacks"] / len(reqs)
             rec["max_bound_over_amp"] = float((bounds[nz] / np.abs(amps[nz])).max())
+        for frac in fracs:
+            # Poisson arrivals at frac * saturated (fresh circuits, new seed)
+            rate = frac * sat
+            reqs2 = workloads.served_requests(n_req + n_warm, rate_hz=rate, seed=seed)
+            seed += 1
+            circs2 = [lofp.Circuit(r.m, r.layers) for r in reqs2]
+            _, _, lats, wall2, st2 = _serve(lofp, reqs2, circs2, prec, rate_hz=rate, n_warm=n_warm)
+            rec["poisson"].append({"rate_fraction": frac, "rate_hz": rate,
+                                   "offered_amplitudes_per_s": (n_req + n_warm) / wall2,
+                                   "p50_ms": float(np.percentile(lats, 50)),
+                                   "p99_ms": float(np.percentile(lats, 99)),
+                                   "mean_batch": st2["mean_batch"], "launches": st2["launches"]})
         out[name] = rec
     return out
 

@@ -145,6 +145,35 @@ def bs_sector(theta: float, phi: float, N: int) -> np.ndarray:
     return W
 
 
+def bs_sector_hp(theta: float, phi: float, N: int, dps: int = 40) -> np.ndarray:
+    """The N-photon sector W[y1, x1] from the Appendix's closed-form sum
+    (with the denominator (x2 - y1 + t)!, reading 1), evaluated in `dps`
+    decimal digits with mpmath and rounded to complex128 at the end: a
+    reference for large N, where the same sum in FP64 cancels badly."""
+    import mpmath
+    old = mpmath.mp.dps
+    mpmath.mp.dps = dps
+    try:
+        th, ph = mpmath.mpf(theta), mpmath.mpf(phi)
+        c, s = mpmath.cos(th), mpmath.sin(th)
+        f = [mpmath.factorial(k) for k in range(N + 1)]
+        W = np.zeros((N + 1, N + 1), dtype=np.complex128)
+        for x1 in range(N + 1):
+            x2 = N - x1
+            for y1 in range(N + 1):
+                y2 = N - y1
+                tot = mpmath.mpf(0)
+                for t in range(max(0, y1 - x2), min(x1, y1) + 1):
+                    term = c ** (x2 - y1 + 2 * t) * s ** (x1 + y1 - 2 * t) / (f[t] * f[y1 - t] * f[x1 - t] * f[x2 - y1 + t])
+                    tot += -term if (y1 - t) % 2 else term
+                mag = mpmath.sqrt(f[x1] * f[x2] * f[y1] * f[y2]) * tot
+                z = mag * mpmath.expj(ph * (x1 - y1))
+                W[y1, x1] = complex(z)
+        return W
+    finally:
+        mpmath.mp.dps = old
+
+
 def fock_amplitude(U: np.ndarray, S, T) -> complex:
     """Per(U[T,S]) / sqrt(prod s! prod t!) for any square matrix U (rows = outputs)."""
     U = np.asarray(U, dtype=np.complex128)

@@ -246,7 +246,7 @@ lofp_status init_circuits(const std::vector<std::pair<lofp_circuit_s *, int>> &l
     char *base = static_cast<char *>(blk->p);
     fill(h, base);
     std::vector<TableJob> jobs;
-    int64_t max_entries = 0;
+    int max_gates = 0;
     for (Part &P : parts) {
         lofp_circuit_s &c = *P.c;
         if (P.table) {
@@ -257,14 +257,14 @@ lofp_status init_circuits(const std::vector<std::pair<lofp_circuit_s *, int>> &l
             set_view(c.d_table, base + const_bytes + P.tab_off, tb);
             J.table = c.d_table.as<double2>();
             jobs.push_back(J);
-            max_entries = std::max<int64_t>(max_entries, (int64_t)c.G * P.stride);
+            max_gates = std::max(max_gates, c.G);
         }
     }
     h.resize(const_bytes, 0);
     if (!jobs.empty()) std::memcpy(h.data() + jobs_off, jobs.data(), jobs.size() * sizeof(TableJob));
     HIPCHK(hipMemcpyAsync(base, h.data(), const_bytes, hipMemcpyHostToDevice, s));
     HIPCHK(launch_build_tables_multi((int)jobs.size(), reinterpret_cast<const TableJob *>(base + jobs_off),
-                                     max_entries, s));
+                                     max_gates, s));
     for (Part &P : parts) {
         lofp_circuit_s &c = *P.c;
         c.blocks.push_back(blk);

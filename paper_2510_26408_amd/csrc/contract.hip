@@ -77,7 +77,116 @@ __device__ __forceinline__ int magic_div(int e, int4 g)
 }
 constexpr int kDescChunk = 16;   // step layouts built per pass
 
-// MAGIC: also the magic multipliers (wide blocks decode with them)
+// Step layouts of up to kDescChunk steps, sixteen lanes per step (lane q owns
+// digit q: its strides by prefix products over the lanes, its magic
+// multiplier); the step's own fields are written by the group's first lane.
+// MAGIC: also the magic multipliers (wide blocks decode with them).
+template <bool MAGIC, int BS>
+__device__ void build_descs(const ContractStep *steps, int nk, const int *vlo, const int *vrad, const int *spre,
+                            const int *tpre, int n, StepDesc *descs)
+{
+    static_assert(kMaxActive == 16, "one lane per digit in groups of 16");
+    const int q = threadIdx.x & 15;
+    for (int k = threadIdx.x >> 4; k < nk; k += BS / 16) {
+        const ContractStep &st = steps[k];
+        StepDesc &d = descs[k];
+        const int n_new = st.n_new, n_old = st.n_old;
+        // stride of old digit q: product of the old radii before it
+        const int ro = q < n_old ? vrad[st.old_vars[q]] : 1;
+        int oin = ro;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            const int y = __shfl_up(oin, o, 16);
+            if (q >= o) oin *= y;
+        }
+        int ostr = __shfl_up(oin, 1, 16);
+        if (q == 0) ostr = 1;
+        // stride of new digit q (saturating: 2^30 marks a state too large)
+        const long long rn = q < n_new ? vrad[st.new_vars[q]] : 1;
+        long long nin = rn;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            const long long y = __shfl_up(nin, o, 16);
+            if (q >= o) nin = nin * y < (1LL << 31) ? nin * y : (1LL << 31);
+        }
+        long long nex = __shfl_up(nin, 1, 16);
+        if (q == 0) nex = 1;
+        const int nsi = nex < (1 << 30) ? (int)nex : (1 << 30);
+        const int src = q < n_new ? st.new_to_old[q] : -1;
+        const int ms_src = __shfl(ostr, src >= 0 ? src : 0, 16);
+        const int ms = src >= 0 ? ms_src : 0;
+        // magic = ceil(2^sh / nsi), only where entries get decoded: a stride of
+        // 0 (an empty interval: no entries) or above 2^22 (a state too large to
+        // run) never divides.  A double quotient, then exact integer fix-ups;
+        // below 2^53 the quotient is off by at most one, so each runs at most
+        // once.
+        int sh = 0;
+        unsigned long long mg = 0;
+        if (MAGIC && nsi >= 1 && nsi <= (1 << 22)) {
+            const int l = nsi > 1 ? 32 - __clz(nsi - 1) : 0;   // ceil(log2 nsi)
+            sh = 31 + l;
+            const unsigned long long two_sh = 1ULL << sh, dn = (unsigned long long)nsi;
+            mg = (unsigned long long)((double)two_sh / (double)nsi);
+            if (mg * dn < two_sh) ++mg;
+            if (mg > 1 && (mg - 1) * dn >= two_sh) --mg;
+        }
+        d.dig[q] = make_int4(nsi, ms, (int)(unsigned)mg, sh);
+        d.ninv[q] = 1.0f / (float)nsi;
+        // old strides of the summed versions
+        const int so0 = st.n_sum > 0 ? st.sum_to_old[0] : -1, so1 = st.n_sum > 1 ? st.sum_to_old[1] : -1;
+        const int ss0 = __shfl(ostr, so0 >= 0 ? so0 : 0, 16), ss1 = __shfl(ostr, so1 >= 0 ? so1 : 0, 16);
+        const long long ntot = __shfl(nin, 15, 16);
+        if (q != 0) continue;
+        d.new_size = ntot < (1 << 30) ? (int)ntot : (1 << 30);
+        d.n_new = n_new;
+        d.gate = st.gate;
+        d.srad0 = 1; d.srad1 = 1; d.sstr0 = 0; d.sstr1 = 0;
+        int slo[2] = {0, 0};
+        if (st.n_sum > 0) {
+            const int v = st.sum_vars[0];
+            d.srad0 = vrad[v]; slo[0] = vlo[v]; d.sstr0 = so0 >= 0 ? ss0 : 0;
+        }
+        if (st.n_sum > 1) {
+            const int v = st.sum_vars[1];
+            d.srad1 = vrad[v]; slo[1] = vlo[v]; d.sstr1 = so1 >= 0 ? ss1 : 0;
+        }
+        // each reference as k + (digit j) + c0 i0 + c1 i1
+        int K[4], J[4], C0[4], C1[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int kind = st.ref_kind[k], arg = st.ref_arg[k];
+            J[k] = -1; C0[k] = 0; C1[k] = 0;
+            if (kind == CREF_NEW) {
+                K[k] = vlo[st.new_vars[arg]];
+                J[k] = arg;
+            } else if (kind == CREF_SUM) {
+                K[k] = slo[arg & 1];
+                C0[k] = arg == 0;
+                C1[k] = arg == 1;
+            } else {
+                K[k] = kind == CREF_ZERO ? 0 : kind == CREF_N ? n : kind == CREF_SPRE ? spre[arg] : tpre[arg];
+            }
+        }
+        // x1 = before - below, y1 = after - below, N = above - below
+        d.kx = K[0] - K[2]; d.ky = K[1] - K[2]; d.kn = K[3] - K[2];
+        d.cx0 = C0[0] - C0[2]; d.cy0 = C0[1] - C0[2]; d.cn0 = C0[3] - C0[2];
+        d.cx1 = C1[0] - C1[2]; d.cy1 = C1[1] - C1[2]; d.cn1 = C1[3] - C1[2];
+        int w[3][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int below = J[2] == j;
+            w[0][j] = (J[0] == j) - below;
+            w[1][j] = (J[1] == j) - below;
+            w[2][j] = (J[3] == j) - below;
+        }
+        d.wx = make_int4(w[0][0], w[0][1], w[0][2], w[0][3]);
+        d.wy = make_int4(w[1][0], w[1][1], w[1][2], w[1][3]);
+        d.wn = make_int4(w[2][0], w[2][1], w[2][2], w[2][3]);
+    }
+}
+
+// Step layout of one step by one thread (small blocks, where sixteen lanes
+// per step would take several passes).  MAGIC: also the magic multipliers.
 template <bool MAGIC>
 __device__ inline void build_desc(const ContractStep &st, const int *vlo, const int *vrad, const int *spre,
                                   const int *tpre, int n, StepDesc &d)
@@ -348,7 +457,7 @@ __device__ int job_max_state(const ContractJob &g, unsigned char *smem)
 // transitions with a nonzero source into *stat_transitions.
 template <bool COUNT, bool F32, bool LDS_STATE, int BS, bool STATS>
 __device__ void contract_run(const ContractJob &g, unsigned char *smem, unsigned long long *stat_transitions,
-                             int32_t *overflow)
+                             int32_t *overflow, unsigned char *stage_lds = nullptr)
 {
     const int nc = g.m - 1;
     const int *vlo = reinterpret_cast<const int *>(smem);
@@ -368,9 +477,27 @@ __device__ void contract_run(const ContractJob &g, unsigned char *smem, unsigned
     for (int si = 0; si < g.nsteps; ++si) {
         const int slot = si % kDescChunk;
         if (slot == 0) {
-            // layouts of the next steps, one thread per step
-            for (int k = threadIdx.x; k < kDescChunk && si + k < g.nsteps; k += BS)
-                build_desc<(BS >= 512)>(g.steps[si + k], vlo, vrad, spre, tpre, g.n, desc[k]);
+            // layouts of the next steps, from the steps copied into LDS by
+            // the whole block (the next state buffer is free until the step
+            // writes it; a job whose state is in global memory gets an LDS
+            // area from its caller)
+            const int nk = g.nsteps - si < kDescChunk ? g.nsteps - si : kDescChunk;
+            const ContractStep *src = g.steps + si;
+            unsigned char *stg = LDS_STATE ? reinterpret_cast<unsigned char *>(bufB) : stage_lds;
+            if (stg && (!LDS_STATE || (size_t)g.max_states * sizeof(double2) >= kDescChunk * sizeof(ContractStep))) {
+                const int nw = nk * (int)(sizeof(ContractStep) / sizeof(int));
+                const int *s4 = reinterpret_cast<const int *>(src);
+                int *d4 = reinterpret_cast<int *>(stg);
+                for (int i = threadIdx.x; i < nw; i += BS) d4[i] = s4[i];
+                __syncthreads();
+                src = reinterpret_cast<const ContractStep *>(stg);
+            }
+            if (BS >= 256) {
+                build_descs<(BS >= 512), BS>(src, nk, vlo, vrad, spre, tpre, g.n, desc);
+            } else {
+                for (int k = threadIdx.x; k < nk; k += BS)
+                    build_desc<(BS >= 512)>(src[k], vlo, vrad, spre, tpre, g.n, desc[k]);
+            }
             __syncthreads();
         }
         const StepDesc &d = desc[slot];
@@ -504,7 +631,10 @@ __global__ __launch_bounds__(BS, multi_waves_per_simd<BS>()) void k_contract_mul
             j.max_states = ov.lds_states;
             contract_run<ABS, F32 || ABS, true, BS, STATS>(j, smem, stat_transitions, overflow);
         } else {
-            contract_run<ABS, F32 || ABS, false, BS, STATS>(j, smem, stat_transitions, overflow);
+            // the LDS its state would have used stages the step programs
+            unsigned char *stg = (size_t)ov.lds_states * 2 * sizeof(double2) >= kDescChunk * sizeof(ContractStep)
+                                     ? smem + job_lds_head(j.nvars, j.m - 1) : nullptr;
+            contract_run<ABS, F32 || ABS, false, BS, STATS>(j, smem, stat_transitions, overflow, stg);
         }
         return;
     }

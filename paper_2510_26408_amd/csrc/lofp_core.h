@@ -167,26 +167,4 @@ LOFP_HD int64_t rank_state(int m, int n, const int32_t *E, const uint8_t *A)
     return s;
 }
 
-// ----------------------------------------------------- beam-splitter table
-// Appendix, with the denominator (x2 - y1 + t)! (the printed (y1 - x2 + t)! is
-// a typo: the exponent of U22 in the same sum is x2 - y1 + t, and only this
-// choice makes each photon-number sector unitary).  For the matrix of
-// Eq. (bs_matrix) every term carries the same phase e^{i phi (x1 - y1)}, so
-//   W = e^{i phi (x1-y1)} sqrt(x1! x2! y1! y2!) *
-//       sum_t (-1)^{y1-t} c^{x2-y1+2t} s^{x1+y1-2t} / (t!(y1-t)!(x1-t)!(x2-y1+t)!)
-// with c = cos(theta), s = sin(theta), 0^0 = 1.
-LOFP_HD double ipow(double b, int e)
-{
-    double r = 1.0;
-    for (int i = 0; i < e; ++i) r *= b;
-    return r;
-}
-
-LOFP_HD double fact(int k)
-{
-    double f = 1.0;
-    for (int i = 2; i <= k; ++i) f *= (double)i;
-    return f;
-}
-
 }  // namespace lofp

@@ -53,13 +53,13 @@ __device__ __forceinline__ int find_pattern(const int64_t *off, int B, int64_t k
 // a2: transition tables for every gate and every sector N <= n_tab.
 hipError_t launch_build_tables(int G, int n_tab, const double *theta, const double *phi,
                                double2 *table, hipStream_t stream);
-// The same for many circuits at once (max_entries: largest G * stride).
+// The same for many circuits at once (max_gates: largest G).
 struct TableJob {
     int G, n_tab, stride;
     const double *theta, *phi;
     double2 *table;
 };
-hipError_t launch_build_tables_multi(int count, const TableJob *jobs, int64_t max_entries, hipStream_t stream);
+hipError_t launch_build_tables_multi(int count, const TableJob *jobs, int max_gates, hipStream_t stream);
 
 // a1: per-pattern cut bounds.
 hipError_t launch_bounds(int B, int m, int D, int n, const int32_t *S, const int32_t *T,

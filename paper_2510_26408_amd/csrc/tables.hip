@@ -1,80 +1,106 @@
 // tables.hip -- beam-splitter transition tables (Appendix), FP64.
 //
-// One thread per table entry.  Layout per gate: sectors N = 0..n_tab, each an
-// (N+1) x (N+1) block stored x1-major: entry (x1, y1) of sector N sits at
-// sector_offset(N) + x1 * (N+1) + y1 and holds <y1, N-y1| BS |x1, N-x1>.
+// Layout per gate: sectors N = 0..n_tab, each an (N+1) x (N+1) block stored
+// x1-major: entry (x1, y1) of sector N sits at sector_offset(N) + x1 * (N+1)
+// + y1 and holds <y1, N-y1| BS |x1, N-x1>; one zero entry closes the gate.
+//
+// The Appendix gives each entry as an alternating sum over t, whose terms
+// grow like binomial coefficients while the entry stays below one, so in
+// FP64 the sum loses about log2(max term) bits (3e-13 absolute near N = 30,
+// 8e-12 near N = 40).  The tables are built instead from the same splitter
+// acting on creation operators (the construction the Appendix starts from):
+// a photon added to the upper input mode maps to U_aa a+ + U_ba b+ on the
+// outputs, so
+//   <y1, y2| BS |x1 + 1, x2> = ( U_aa sqrt(y1) <y1 - 1, y2| BS |x1, x2>
+//                              + U_ba sqrt(y2) <y1, y2 - 1| BS |x1, x2> ) / sqrt(x1 + 1)
+// and likewise for a photon added to the lower input with U_ab, U_bb.  The
+// photon is always added to the fuller input mode (x1 >= x2: upper), so the
+// factors sqrt(y) / sqrt(x) stay near one and rounding errors grow slowly
+// (2.5e-14 at N = 64, where adding every photon on the upper side, or the
+// closed form, loses 1e-8 or more).  With c = cos theta, s = sin theta the
+// single-photon matrix of Eq. (bs_matrix) is U_aa = U_bb = c,
+// U_ba = s e^{i phi} (upper in, lower out), U_ab = -s e^{-i phi}.
 #include "lofp_device.h"
 
 namespace lofp {
 
-// Entry idx of gate g's table (theta, phi of that gate).
-__device__ double2 table_entry(int n_tab, int idx, double theta, double phi)
+// All sectors of one gate's table by one block, in order of N (each sector
+// reads the previous one, written by the same block before a barrier).
+__device__ void build_gate_table(int n_tab, double theta, double phi, double2 *__restrict__ tab)
 {
-    if (idx >= sector_offset(n_tab + 1)) return make_double2(0.0, 0.0);   // the zero slot
-    int N = 0;
-    while (N < n_tab && sector_offset(N + 1) <= idx) ++N;
-    const int rem = idx - sector_offset(N);
-    const int x1 = rem / (N + 1), y1 = rem - x1 * (N + 1);
-    const int x2 = N - x1, y2 = N - y1;
-    double s, c;
+    double s, c, sp, cp;
     sincos(theta, &s, &c);
-    // sum over t of (-1)^{y1-t} c^{x2-y1+2t} s^{x1+y1-2t} / (t!(y1-t)!(x1-t)!(x2-y1+t)!)
-    const int tlo = (y1 - x2) > 0 ? (y1 - x2) : 0;
-    const int thi = x1 < y1 ? x1 : y1;
-    double sum = 0.0;
-    for (int t = tlo; t <= thi; ++t) {
-        double term = ipow(c, x2 - y1 + 2 * t) * ipow(s, x1 + y1 - 2 * t) /
-                      (fact(t) * fact(y1 - t) * fact(x1 - t) * fact(x2 - y1 + t));
-        sum += ((y1 - t) & 1) ? -term : term;
+    sincos(phi, &sp, &cp);
+    const double2 u_aa = make_double2(c, 0.0), u_bb = u_aa;
+    const double2 u_ba = make_double2(s * cp, s * sp);     // upper in, lower out
+    const double2 u_ab = make_double2(-s * cp, s * sp);    // lower in, upper out: -s e^{-i phi}
+    if (threadIdx.x == 0) {
+        tab[0] = make_double2(1.0, 0.0);                    // sector 0: the vacuum
+        tab[sector_offset(n_tab + 1)] = make_double2(0.0, 0.0);   // the zero slot
     }
-    const double mag = sqrt(fact(x1) * fact(x2) * fact(y1) * fact(y2)) * sum;
-    double sp, cp;
-    sincos(phi * (double)(x1 - y1), &sp, &cp);
-    return make_double2(mag * cp, mag * sp);
+    __syncthreads();
+    for (int N = 1; N <= n_tab; ++N) {
+        const double2 *prev = tab + sector_offset(N - 1);
+        double2 *cur = tab + sector_offset(N);
+        for (int k = threadIdx.x; k < (N + 1) * (N + 1); k += blockDim.x) {
+            const int x1 = k / (N + 1), x2 = N - x1, y1 = k - x1 * (N + 1), y2 = N - y1;
+            // add the last photon to the fuller input; px1 is the upper input
+            // of the sector N - 1 entry it starts from
+            const bool up = x1 > 0 && x1 >= x2;
+            const int px1 = up ? x1 - 1 : x1;
+            const double2 ua = up ? u_aa : u_ab, ub = up ? u_ba : u_bb;
+            const double inv = 1.0 / sqrt((double)(up ? x1 : x2));
+            double2 acc = make_double2(0.0, 0.0);
+            if (y1 > 0) {   // the new photon leaves through the upper output
+                const double2 t = cmul(ua, prev[px1 * N + (y1 - 1)]);
+                const double r = sqrt((double)y1);
+                acc = make_double2(t.x * r, t.y * r);
+            }
+            if (y2 > 0) {   // through the lower output
+                const double2 t = cmul(ub, prev[px1 * N + y1]);
+                const double r = sqrt((double)y2);
+                acc.x = fma(t.x, r, acc.x);
+                acc.y = fma(t.y, r, acc.y);
+            }
+            cur[k] = make_double2(acc.x * inv, acc.y * inv);
+        }
+        __syncthreads();
+    }
 }
 
-__global__ void k_build_tables(int G, int n_tab, int stride, const double *__restrict__ theta,
-                               const double *__restrict__ phi, double2 *__restrict__ table)
+// One block per gate.
+__global__ __launch_bounds__(256) void k_build_tables(int G, int n_tab, int stride, const double *__restrict__ theta,
+                                                      const double *__restrict__ phi, double2 *__restrict__ table)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= (int64_t)G * stride) return;
-    const int g = (int)(k / stride);
-    const int idx = (int)(k - (int64_t)g * stride);
-    table[k] = table_entry(n_tab, idx, theta[g], phi[g]);
+    const int g = blockIdx.x;
+    if (g >= G) return;
+    build_gate_table(n_tab, theta[g], phi[g], table + (int64_t)g * stride);
 }
 
-// Tables of many circuits: blockIdx.y picks the circuit.
-__global__ void k_build_tables_multi(const TableJob *__restrict__ jobs)
+// Tables of many circuits: blockIdx.y picks the circuit, blockIdx.x the gate.
+__global__ __launch_bounds__(256) void k_build_tables_multi(const TableJob *__restrict__ jobs)
 {
     const TableJob j = jobs[blockIdx.y];
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= (int64_t)j.G * j.stride) return;
-    const int g = (int)(k / j.stride);
-    const int idx = (int)(k - (int64_t)g * j.stride);
-    j.table[k] = table_entry(j.n_tab, idx, j.theta[g], j.phi[g]);
+    const int g = blockIdx.x;
+    if (g >= j.G) return;
+    build_gate_table(j.n_tab, j.theta[g], j.phi[g], j.table + (int64_t)g * j.stride);
 }
 
 hipError_t launch_build_tables(int G, int n_tab, const double *theta, const double *phi,
                                double2 *table, hipStream_t stream)
 {
+    if (G == 0) return hipSuccess;
     const int stride = sector_offset(n_tab + 1) + 1;
-    const int64_t total = (int64_t)G * stride;
-    if (total == 0) return hipSuccess;
-    const int block = 256;
-    const int grid = (int)((total + block - 1) / block);
-    hipLaunchKernelGGL(k_build_tables, dim3(grid), dim3(block), 0, stream, G, n_tab, stride, theta, phi,
-                       table);
+    hipLaunchKernelGGL(k_build_tables, dim3(G), dim3(256), 0, stream, G, n_tab, stride, theta, phi, table);
     return hipGetLastError();
 }
 
-hipError_t launch_build_tables_multi(int count, const TableJob *jobs, int64_t max_entries, hipStream_t stream)
+hipError_t launch_build_tables_multi(int count, const TableJob *jobs, int max_gates, hipStream_t stream)
 {
-    if (count == 0 || max_entries == 0) return hipSuccess;
-    const int block = 256;
+    if (count == 0 || max_gates == 0) return hipSuccess;
     for (int base = 0; base < count; base += 65535) {
         const int n = count - base < 65535 ? count - base : 65535;
-        hipLaunchKernelGGL(k_build_tables_multi, dim3((unsigned)((max_entries + block - 1) / block), n), dim3(block),
-                           0, stream, jobs + base);
+        hipLaunchKernelGGL(k_build_tables_multi, dim3((unsigned)max_gates, n), dim3(256), 0, stream, jobs + base);
     }
     return hipGetLastError();
 }

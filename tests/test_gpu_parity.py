@@ -54,6 +54,19 @@ def test_tables_match_oracle():
             check(got, want, 1e-14 * max(1, N))
 
 
+@pytest.mark.parametrize("N", [12, 24, 36, 48, 64])
+def test_tables_at_high_photon_number(N):
+    """Sectors up to the 64-photon limit against the closed-form sum in 40
+    digits (the FP64 closed form would be off by 1e-11 at N = 40 and by 1e-8
+    at N = 64; the recurrence the tables use stays near 1e-14)."""
+    pytest.importorskip("mpmath")
+    c = lofp.Circuit(2, [[(0, 1, 0.91, 2.2)], [(0, 1, 0.35, -1.3)]])
+    for g, (th, ph) in enumerate(((0.91, 2.2), (0.35, -1.3))):
+        got = c.bs_table(g, N)                      # [x1, y1]
+        want = oracle.bs_sector_hp(th, ph, N).T     # [x1, y1]
+        check(got, want, 2e-15 * (N + 1))
+
+
 def test_table_special_angles():
     layers = [[(0, 1, 0.0, 1.0)], [(0, 1, math.pi / 2, 0.4)], [(0, 1, math.pi / 4, 2.0)]]
     c = lofp.Circuit(2, layers)

@@ -242,3 +242,21 @@ def test_absolute_form_bounds_amplitude_and_vanishes_with_paths():
         amp = oracle.amplitude(m, S, T, circ)
         assert a >= abs(amp) - 1e-14
         assert (a > 0) == (oracle.path_count_bruteforce(m, S, T, circ) > 0)
+
+
+# ------------------------------------------------ high-precision sectors
+def test_high_precision_sector_matches_permanent_form():
+    """The closed-form sum in 40 digits equals the permanent-based sector (a
+    different formula) for small N."""
+    pytest.importorskip("mpmath")
+    for (th, ph) in ((0.3, 1.1), (1.2, -0.4), (math.pi / 4, 2.5)):
+        for N in range(0, 7):
+            a = oracle.bs_sector_hp(th, ph, N)
+            b = oracle.bs_sector(th, ph, N)
+            assert np.abs(a - b).max() < 1e-15
+
+
+def test_high_precision_sector_unitary_at_large_n():
+    pytest.importorskip("mpmath")
+    W = oracle.bs_sector_hp(0.83, 0.6, 30)
+    assert np.abs(W @ W.conj().T - np.eye(31)).max() < 1e-14
