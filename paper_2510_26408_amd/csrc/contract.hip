@@ -293,7 +293,8 @@ __device__ inline void build_desc(const ContractStep &st, const int *vlo, const 
 // Decoding an entry into its digits: small blocks keep the step's strides in
 // registers (an unrolled loop, float-reciprocal quotients); wide blocks, which
 // run more waves per SIMD and so have fewer registers per lane, read each
-// digit's stride and magic multiplier from the step layout in LDS.
+// digit's stride and magic multiplier from the step layout in LDS, two
+// digits per loop pass so their reads overlap.
 template <bool COUNT, bool F32, int BS, bool STATS>
 __device__ __forceinline__ void step_entries(const StepDesc &d, const double2 *__restrict__ bufA,
                                              double2 *__restrict__ bufB, const gdouble *__restrict__ W,
@@ -318,7 +319,7 @@ __device__ __forceinline__ void step_entries(const StepDesc &d, const double2 *_
         int rem = e, base_old = 0;
         int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
         if (kRolled) {
-#pragma nounroll
+#pragma unroll 2
             for (int q = n_new - 1; q >= 0; --q) {
                 const int4 g = d.dig[q];
                 const int dq = magic_div(rem, g);
