@@ -632,6 +632,9 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
 // is contracted once and every pattern is finished by a dot product of its two
 // halves over the crossing versions.  The grouping runs on the device; the
 // host reads back the two key counts (one synchronisation) to size the launch.
+// Batch sizes that take the split without sharing, for parallelism.
+constexpr int kSplitSmallMin = 256, kSplitSmallMax = 1024;
+
 lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
                                lofp_c128 *out_dev, int fp32, hipStream_t s, lofp_stats *st, bool count_work,
                                Timer &tm, bool &used, bool &bounds_done)
@@ -693,7 +696,13 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     HIPCHK(hipStreamSynchronize(s));
     int ntop = 0, nbot = 0;
     for (int i = 0; i < kKeySubs; ++i) { ntop += c.h_pin[i]; nbot += c.h_pin[kKeySubs + i]; }
-    if ((int64_t)(ntop + nbot) * 4 > (int64_t)B * 3) {
+    // Split when the halves are shared (at most 3/4 as many halves as
+    // patterns), or when the batch is small enough that one job per pattern
+    // would leave most of the GPU idle (up to four 64-lane jobs per CU): the
+    // two halves then run side by side at half the steps each.
+    const bool shared = (int64_t)(ntop + nbot) * 4 <= (int64_t)B * 3;
+    const bool small = B >= kSplitSmallMin && B <= kSplitSmallMax;
+    if (!shared && !small) {
         // little sharing: contract per pattern (the bounds are in place)
         HIPCHK(launch_key_reset(ka, ntop, nbot, s));
         HIPCHK(hipMemsetAsync(ka.count, 0, 2 * kKeySubs * sizeof(int), s));

@@ -399,13 +399,24 @@ def test_split_contraction_invalid_rows_and_no_sharing():
     assert got[5] == 0 and got[9] == 0
     ok = np.array([i for i in range(len(Ts)) if i not in (5, 9)])
     check(got[ok[:128]], oracle_amps(wl.m, wl.S, Ts[ok[:128]], wl.layers))
-    # bunched patterns share no halves: the call falls back to one contraction per pattern
-    wl3 = workloads.make("c3", seed=4, batch=256)
+    # bunched patterns share few halves: a large batch falls back to one
+    # contraction per pattern ...
+    wl3 = workloads.make("c3", seed=4, batch=2048)
     c3 = lofp.Circuit(wl3.m, wl3.layers)
     st3 = lofp.Stats()
     got3 = c3.amplitudes(wl3.S, wl3.Ts, lofp.make_opts(method=lofp.METHOD_CONTRACT), st3)
     assert st3.split_top_keys == 0
     check(got3[:64], oracle_amps(wl3.m, wl3.S, wl3.Ts[:64], wl3.layers))
+    # ... while a batch of 256 to 1024 patterns is split for parallelism
+    wl4 = workloads.make("c3", seed=4, batch=300)
+    c4 = lofp.Circuit(wl4.m, wl4.layers)
+    st4 = lofp.Stats()
+    got4 = c4.amplitudes(wl4.S, wl4.Ts, lofp.make_opts(method=lofp.METHOD_CONTRACT), st4)
+    assert st4.split_top_keys > 0
+    check(got4[:64], oracle_amps(wl4.m, wl4.S, wl4.Ts[:64], wl4.layers))
+    unsplit = np.concatenate([c4.amplitudes(wl4.S, wl4.Ts[i:i + 32], lofp.make_opts(method=lofp.METHOD_CONTRACT))
+                              for i in range(0, 64, 32)])
+    check(got4[:64], unsplit, 1e-14)
 
 
 def _brickwork(m, depth, seed):
