@@ -672,15 +672,17 @@ hipError_t launch_multi_sizes(int count, const ContractJob *jobs, int *mx, hipSt
     return hipGetLastError();
 }
 
-// Join of a split contraction, one wave per pattern: the sum over the
+// Join of a split contraction, one block per pattern: the sum over the
 // pattern's own box of crossing versions of TOP(versions) * BOT(versions),
 // each state addressed by value through its key's interval layout.  Both
 // states list the crossing versions in the same order, so neighbouring lanes
 // read neighbouring entries of both.
 // NS: the number of crossing versions (a compile-time count, so the set-up
-// loads are all issued together and the digit loop has no branches).
+// loads are all issued together and the digit loop has no branches).  Two
+// waves per pattern: the kernel's time is the longest box's gather chain.
+constexpr int kJoinBlock = 128;
 template <int NS>
-__global__ __launch_bounds__(64) void k_join(JoinArgs g)
+__global__ __launch_bounds__(kJoinBlock) void k_join(JoinArgs g)
 {
     const int p = blockIdx.x;
     const int nc = g.m - 1, span = (g.D + 1) * nc;
@@ -721,7 +723,7 @@ __global__ __launch_bounds__(64) void k_join(JoinArgs g)
     const gdouble *BS_ = (const gdouble *)(g.bot_state + (int64_t)bk * g.state_cap);
     CSum sr{0.0, 0.0}, si{0.0, 0.0};
 #pragma unroll 4
-    for (int e = threadIdx.x; e < box; e += 64) {
+    for (int e = threadIdx.x; e < box; e += kJoinBlock) {
         int rem = e, ti = 0, bi = 0;
 #pragma unroll
         for (int q = NS - 1; q >= 0; --q) {
@@ -742,7 +744,15 @@ __global__ __launch_bounds__(64) void k_join(JoinArgs g)
         csum_merge(sr, b);
         csum_merge(si, c);
     }
-    if (threadIdx.x == 0) g.out[p] = make_double2(sr.s + sr.c, si.s + si.c);
+    // the waves' partial sums, merged in wave order
+    __shared__ CSum part[2][kJoinBlock / 64];
+    if ((threadIdx.x & 63) == 0) { part[0][threadIdx.x >> 6] = sr; part[1][threadIdx.x >> 6] = si; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        CSum a = part[0][0], b = part[1][0];
+        for (int w = 1; w < kJoinBlock / 64; ++w) { csum_merge(a, part[0][w]); csum_merge(b, part[1][w]); }
+        g.out[p] = make_double2(a.s + a.c, b.s + b.c);
+    }
 }
 
 template <int... N>
@@ -750,7 +760,7 @@ static void launch_join_ns(const JoinArgs &a, hipStream_t stream, std::integer_s
 {
     using K = void (*)(JoinArgs);
     static const K table[] = {k_join<N>...};
-    hipLaunchKernelGGL(table[a.nshared], dim3(a.B), dim3(64), 0, stream, a);
+    hipLaunchKernelGGL(table[a.nshared], dim3(a.B), dim3(kJoinBlock), 0, stream, a);
 }
 
 hipError_t launch_join(const JoinArgs &a, hipStream_t stream)
