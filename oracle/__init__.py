@@ -267,6 +267,29 @@ def evolve(m: int, S, circuit) -> Dict[Tuple[int, ...], complex]:
     return state
 
 
+def evolve_hp(m: int, S, circuit, dps: int = 40) -> Dict[Tuple[int, ...], complex]:
+    """Full output state of |S> like :func:`evolve`, with each splitter's
+    sectors from :func:`bs_sector_hp` (40-digit closed form) instead of the
+    permanent, so many photons per mode stay affordable; small m only."""
+    state: Dict[Tuple[int, ...], complex] = {tuple(int(s) for s in S): 1.0 + 0j}
+    sectors: Dict[Tuple[int, int], np.ndarray] = {}
+    for g, (a, b, th, ph) in enumerate(circuit):
+        new: Dict[Tuple[int, ...], complex] = {}
+        for conf, amp in state.items():
+            x1, x2 = conf[a], conf[b]
+            N = x1 + x2
+            if (g, N) not in sectors:
+                sectors[(g, N)] = bs_sector_hp(th, ph, N, dps)
+            W = sectors[(g, N)]
+            for y1 in range(N + 1):
+                c = list(conf)
+                c[a], c[b] = y1, N - y1
+                c = tuple(c)
+                new[c] = new.get(c, 0j) + amp * W[y1, x1]
+        state = new
+    return state
+
+
 def path_count_bruteforce(m: int, S, T, circuit) -> int:
     """Number of valid paths of Eq. (1): sequences of per-BS output splits that
     start at S and end at T.  Counting form of :func:`evolve`."""

@@ -553,3 +553,22 @@ def test_device_bounds_equal_host_bounds(case):
             nfeas += 1
             assert np.array_equal(lo[p], hl) and np.array_equal(hi[p], hh), p
     assert not feas[3] and nfeas > 0
+
+
+# ----------------------------------------------------- high photon density
+@pytest.mark.parametrize("m,D,S", [(3, 4, (12, 0, 8)), (4, 5, (10, 4, 0, 10))])
+def test_high_photon_density_all_outputs(m, D, S):
+    """Many photons per mode (20 and 24 photons in 3 and 4 modes): every output
+    pattern by the contraction and by the path sum against an evolution with
+    40-digit splitter sectors; the probabilities sum to one."""
+    pytest.importorskip("mpmath")
+    layers = _brickwork(m, D, seed=70 + m)
+    circ = flat(layers)
+    want_state = oracle.evolve_hp(m, S, circ)
+    Ts = np.array(oracle.all_patterns(m, sum(S)), dtype=np.int32)
+    want = np.array([want_state.get(tuple(t), 0j) for t in Ts])
+    c = lofp.Circuit(m, layers)
+    for method in (lofp.METHOD_CONTRACT, lofp.METHOD_PATHSUM):
+        got = c.amplitudes(np.array(S, np.int32), Ts, lofp.make_opts(method=method))
+        check(got, want)
+        assert abs(np.sum(np.abs(got) ** 2) - 1.0) < 1e-12

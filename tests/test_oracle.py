@@ -260,3 +260,16 @@ def test_high_precision_sector_unitary_at_large_n():
     pytest.importorskip("mpmath")
     W = oracle.bs_sector_hp(0.83, 0.6, 30)
     assert np.abs(W @ W.conj().T - np.eye(31)).max() < 1e-14
+
+
+def test_high_precision_evolution_matches_ryser():
+    """The evolution with 40-digit sectors equals Ryser's amplitudes on a
+    small circuit (a third route to the same numbers) and conserves norm."""
+    pytest.importorskip("mpmath")
+    m, D = 4, 3
+    circ = flat(brick(m, D, 60))
+    S = (2, 0, 1, 1)
+    st = oracle.evolve_hp(m, S, circ)
+    assert abs(sum(abs(v) ** 2 for v in st.values()) - 1.0) < 1e-13
+    for T in oracle.all_patterns(m, sum(S)):
+        assert abs(st.get(tuple(T), 0) - oracle.amplitude(m, S, T, circ)) < 1e-14
