@@ -50,10 +50,8 @@ __device__ __forceinline__ int find_pattern(const int64_t *off, int B, int64_t k
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `stream` and return the hipError_t of the launch.
 
-// a2: transition tables for every gate and every sector N <= n_tab.
-hipError_t launch_build_tables(int G, int n_tab, const double *theta, const double *phi,
-                               double2 *table, hipStream_t stream);
-// The same for many circuits at once (max_gates: largest G).
+// a2: transition tables for every gate and every sector N <= n_tab of many
+// circuits at once (max_gates: largest G).
 struct TableJob {
     int G, n_tab, stride;
     const double *theta, *phi;

@@ -68,15 +68,6 @@ __device__ void build_gate_table(int n_tab, double theta, double phi, double2 *_
     }
 }
 
-// One block per gate.
-__global__ __launch_bounds__(256) void k_build_tables(int G, int n_tab, int stride, const double *__restrict__ theta,
-                                                      const double *__restrict__ phi, double2 *__restrict__ table)
-{
-    const int g = blockIdx.x;
-    if (g >= G) return;
-    build_gate_table(n_tab, theta[g], phi[g], table + (int64_t)g * stride);
-}
-
 // Tables of many circuits: blockIdx.y picks the circuit, blockIdx.x the gate.
 __global__ __launch_bounds__(256) void k_build_tables_multi(const TableJob *__restrict__ jobs)
 {
@@ -84,15 +75,6 @@ __global__ __launch_bounds__(256) void k_build_tables_multi(const TableJob *__re
     const int g = blockIdx.x;
     if (g >= j.G) return;
     build_gate_table(j.n_tab, j.theta[g], j.phi[g], j.table + (int64_t)g * j.stride);
-}
-
-hipError_t launch_build_tables(int G, int n_tab, const double *theta, const double *phi,
-                               double2 *table, hipStream_t stream)
-{
-    if (G == 0) return hipSuccess;
-    const int stride = sector_offset(n_tab + 1) + 1;
-    hipLaunchKernelGGL(k_build_tables, dim3(G), dim3(256), 0, stream, G, n_tab, stride, theta, phi, table);
-    return hipGetLastError();
 }
 
 hipError_t launch_build_tables_multi(int count, const TableJob *jobs, int max_gates, hipStream_t stream)
