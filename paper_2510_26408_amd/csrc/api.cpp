@@ -631,7 +631,8 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
 // bottom half only through modes rs+1..m-1, so each distinct top (bottom) part
 // is contracted once and every pattern is finished by a dot product of its two
 // halves over the crossing versions.  The grouping runs on the device; the
-// host reads back the two key counts (one synchronisation) to size the launch.
+// host reads back the key claim counts (one synchronisation) to size the
+// launch.
 // Batch sizes that take the split without sharing, for parallelism.
 constexpr int kSplitSmallMin = 256, kSplitSmallMax = 1024;
 
