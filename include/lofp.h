@@ -180,7 +180,8 @@ lofp_status lofp_bs_table(lofp_circuit c, int32_t gate, int32_t N, lofp_c128 *ou
  * Eq. (1) summed by the frontier split (forward and backward merged
  * frontiers, Schroedinger-Feynman interpolation of Sec. I) and depth-first
  * enumeration of the middle layers (method PATHSUM), or by the mode-axis
- * contraction of Sec. II.C (method CONTRACT). */
+ * contraction of Sec. II.C (method CONTRACT).  Batches above 4096 patterns
+ * run in passes of 4096 (stats then sum over the passes). */
 lofp_status lofp_amplitudes_device(lofp_circuit c, const int32_t *S, int32_t batch,
                                    const int32_t *T_dev, lofp_c128 *out_dev,
                                    const lofp_opts *opts, void *stream, lofp_stats *stats);
