@@ -61,8 +61,6 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     dp = ctypes.POINTER(ctypes.c_double)
     ip = ctypes.POINTER(ctypes.c_int)
-    lib.orc_bs_matrix.argtypes = [ctypes.c_double, ctypes.c_double, dp]
-    lib.orc_bs_matrix.restype = None
     lib.orc_permanent_ryser.argtypes = [ctypes.c_int, dp, dp, dp]
     lib.orc_permanent_brute.argtypes = [ctypes.c_int, dp, dp]
     lib.orc_bs_amplitude.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
@@ -94,13 +92,6 @@ def _circ_arrays(circuit: Sequence[Tuple[int, int, float, float]]):
     th = np.ascontiguousarray([c[2] for c in circuit], dtype=np.float64)
     ph = np.ascontiguousarray([c[3] for c in circuit], dtype=np.float64)
     return ma, mb, th, ph
-
-
-def bs_matrix(theta: float, phi: float) -> np.ndarray:
-    """Eq. (bs_matrix) as a 2x2 complex array (rows = outputs, cols = inputs)."""
-    out = np.zeros(8, dtype=np.float64)
-    _load().orc_bs_matrix(theta, phi, _dptr(out))
-    return (out[0::2] + 1j * out[1::2]).reshape(2, 2)
 
 
 def permanent(a: np.ndarray, with_bound: bool = False):

@@ -22,7 +22,6 @@
  * also returns an a-posteriori bound on its own rounding error.
  *
  * Functions:
- *   orc_bs_matrix        Eq. (bs_matrix)
  *   orc_permanent_ryser  Ryser's formula, Gray-code subset order
  *   orc_permanent_brute  sum over all permutations (definition; tiny n)
  *   orc_bs_amplitude     Appendix: single-BS amplitude as the permanent of the
@@ -51,19 +50,9 @@ static lcx csub(lcx a, lcx b) { return cx(a.re - b.re, a.im - b.im); }
 static lcx cmul(lcx a, lcx b) { return cx(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re); }
 static ld cabs_l(lcx a) { return sqrtl(a.re * a.re + a.im * a.im); }
 
-/* Eq. (bs_matrix): [[cos t, -e^{-i p} sin t], [e^{i p} sin t, cos t]].
- * Output layout: U11.re U11.im U12.re U12.im U21.re U21.im U22.re U22.im,
- * with U_{ij}: row i = output mode, column j = input mode (1 = upper). */
-void orc_bs_matrix(double theta, double phi, double *U)
-{
-    ld c = cosl((ld)theta), s = sinl((ld)theta);
-    ld cp = cosl((ld)phi), sp = sinl((ld)phi);
-    U[0] = (double)c;         U[1] = 0.0;
-    U[2] = (double)(-cp * s); U[3] = (double)(sp * s);   /* -e^{-ip} s */
-    U[4] = (double)(cp * s);  U[5] = (double)(sp * s);   /*  e^{+ip} s */
-    U[6] = (double)c;         U[7] = 0.0;
-}
-
+/* Eq. (bs_matrix): [[cos t, -e^{-i p} sin t], [e^{i p} sin t, cos t]],
+ * B[0] = U11, B[1] = U12, B[2] = U21, B[3] = U22 with row = output mode,
+ * column = input mode (1 = upper). */
 static void bs_matrix_l(double theta, double phi, lcx B[4])
 {
     ld c = cosl((ld)theta), s = sinl((ld)theta);
