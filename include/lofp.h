@@ -58,8 +58,10 @@ typedef struct {
 
 /* Opaque circuit handle.  Owns a copy of the layer list, the light-cone
  * (reach) tables and, once a device call has been made, the device copy of
- * the beam-splitter transition tables.  Immutable after creation; calls on
- * one handle from several threads are serialised internally. */
+ * the beam-splitter transition tables and the workspace of its calls.
+ * Immutable after creation; calls on one handle from several threads are
+ * serialised internally, and a call on one stream waits (on the device) for
+ * the previous call's work on the handle when that ran on another stream. */
 typedef struct lofp_circuit_s *lofp_circuit;
 
 enum {
@@ -91,7 +93,11 @@ typedef struct {
     int32_t count_work;       /* with stats: also count the work done
                                  (stats->transitions); the counting kernels
                                  run slower, so timed calls leave it 0       */
-    int32_t reserved;
+    int32_t state_limit;      /* contraction: at most this many entries per
+                                 state buffer (0 = as large as the state
+                                 needs).  A result whose state would exceed
+                                 the limit is NaN + NaN i; the call returns
+                                 ENOMEM when stats are passed              */
     double fp32_rtol;         /* multi-circuit FP32 form: a result whose
                                  rounding bound exceeds fp32_rtol * |amp| is
                                  recomputed in FP64 (0 = 1e-6)               */
@@ -180,8 +186,10 @@ lofp_status lofp_bs_table(lofp_circuit c, int32_t gate, int32_t N, lofp_c128 *ou
  * Eq. (1) summed by the frontier split (forward and backward merged
  * frontiers, Schroedinger-Feynman interpolation of Sec. I) and depth-first
  * enumeration of the middle layers (method PATHSUM), or by the mode-axis
- * contraction of Sec. II.C (method CONTRACT).  Batches above 4096 patterns
- * run in passes of 4096 (stats then sum over the passes). */
+ * contraction of Sec. II.C (method CONTRACT).  Batches above 32768 patterns
+ * run in passes of 32768 (stats then sum over the passes).  A result whose
+ * contraction state did not fit its buffers (see opts->state_limit) is
+ * NaN + NaN i; with stats the call then returns ENOMEM. */
 lofp_status lofp_amplitudes_device(lofp_circuit c, const int32_t *S, int32_t batch,
                                    const int32_t *T_dev, lofp_c128 *out_dev,
                                    const lofp_opts *opts, void *stream, lofp_stats *stats);

@@ -551,11 +551,13 @@ lofp_status ready_on_stream(lofp_circuit_s &c, hipStream_t s)
 
 lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
                                lofp_c128 *out_dev, int fp32, hipStream_t s, lofp_stats *st, bool count_work,
-                               Timer &tm, bool &used, bool &bounds_done);
+                               int state_limit, Timer &tm, bool &used, bool &bounds_done);
 
+// state_limit > 0: no state buffer holds more entries (a result whose state
+// would is NaN; ENOMEM when statistics are read back).
 lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
                          lofp_c128 *out_dev, int count_only, int fp32, hipStream_t s, lofp_stats *st,
-                         bool count_work, Timer &tm, bool allow_split = true)
+                         bool count_work, int state_limit, Timer &tm, bool allow_split = true)
 {
     lofp_status rc = prepare_program(c, s);
     if (rc != LOFP_OK) return rc;
@@ -564,7 +566,7 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
     bool bounds_done = false;
     if (!count_only && allow_split && B >= 64) {
         bool used = false;
-        rc = run_contract_split(c, S, n, B, T_dev, out_dev, fp32, s, st, count_work, tm, used, bounds_done);
+        rc = run_contract_split(c, S, n, B, T_dev, out_dev, fp32, s, st, count_work, state_limit, tm, used, bounds_done);
         if (rc != LOFP_OK || used) return rc;
     }
     if (!bounds_done) {
@@ -612,6 +614,7 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
             a.ws = c.d_ws.as<double2>();
         }
     }
+    if (state_limit > 0 && a.max_states > state_limit) a.max_states = state_limit;
     tm.mark();
     HIPCHK(launch_contract(a, s));
     tm.mark();
@@ -638,7 +641,7 @@ constexpr int kSplitSmallMin = 256, kSplitSmallMax = 1024;
 
 lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
                                lofp_c128 *out_dev, int fp32, hipStream_t s, lofp_stats *st, bool count_work,
-                               Timer &tm, bool &used, bool &bounds_done)
+                               int state_limit, Timer &tm, bool &used, bool &bounds_done)
 {
     used = false;
     bounds_done = false;
@@ -660,38 +663,41 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     // group the patterns by their two halves of T
     int cap = 1;
     while (cap < 4 * B) cap <<= 1;   // load factor <= 1/4: short probe runs
-    const void *old_tab = c.d_ktab.p, *old_hull = c.d_khull.p, *old_cnt = c.d_kcnt.p;
-    HIPCHK(ensure(c.d_ktab, (size_t)2 * cap * sizeof(unsigned long long)));
+    // the table, slot keys and hulls keep the layout of the largest capacity
+    // seen on this circuit (key_layout.h), so a smaller batch only touches
+    // rows that earlier calls left empty
+    const KeyLayoutPlan kl = plan_key_layout(c.klay, cap, span);
+    HIPCHK(ensure(c.d_ktab, kl.table_bytes));
     HIPCHK(ensure(c.d_kslot, (size_t)2 * B * sizeof(int)));
-    HIPCHK(ensure(c.d_kof, (size_t)2 * cap * sizeof(int)));
+    HIPCHK(ensure(c.d_kof, kl.slot_key_bytes));
     HIPCHK(ensure(c.d_krep, (size_t)2 * kKeySubs * B * sizeof(int)));
     HIPCHK(ensure(c.d_kcnt, 2 * kKeySubs * sizeof(int)));
-    HIPCHK(ensure(c.d_khull, (size_t)2 * 2 * cap * span * sizeof(int)));
+    HIPCHK(ensure(c.d_khull, kl.hull_bytes));
     HIPCHK(ensure(c.d_klohi, (size_t)2 * 2 * B * span * sizeof(int16_t)));
-    if (c.d_ktab.p != old_tab || c.d_khull.p != old_hull || c.d_kcnt.p != old_cnt) c.ktab_clean = false;
     KeyArgs ka{};
-    ka.B = B; ka.m = m; ka.n = n; ka.rs = rs; ka.cap = cap; ka.span = span;
+    ka.B = B; ka.m = m; ka.n = n; ka.rs = rs; ka.cap = cap; ka.span = span; ka.stride = kl.stride;
     ka.T = T_dev;
     ka.lo = c.d_lo.as<int16_t>(); ka.hi = c.d_hi.as<int16_t>();
     ka.infeasible = c.d_inf.as<int32_t>();
     ka.table = c.d_ktab.as<unsigned long long>(); ka.slot = c.d_kslot.as<int>();
     ka.slot_key = c.d_kof.as<int>(); ka.key_slot = c.d_krep.as<int>(); ka.count = c.d_kcnt.as<int>();
-    ka.hlo = c.d_khull.as<int>(); ka.hhi = ka.hlo + (size_t)2 * cap * span;
+    ka.hlo = c.d_khull.as<int>(); ka.hhi = ka.hlo + key_hull_hi_offset(kl.stride, span);
     ka.klo = c.d_klohi.as<int16_t>(); ka.khi = ka.klo + (size_t)2 * B * span;
     ka.counters = c.d_counters.as<unsigned long long>();
     HIPCHK(ensure(c.d_korder, (size_t)2 * 2 * B * sizeof(int)));
     ka.job_bucket = c.d_korder.as<int>();
     ka.order = ka.job_bucket + 2 * B;
     // the table, the slot hulls and the counts are left empty by the jobs
-    // kernel of each call; they are cleared here only when new or when a
-    // previous call stopped before that kernel
-    if (!c.ktab_clean) {
-        HIPCHK(hipMemsetAsync(ka.table, 0xFF, (size_t)2 * cap * sizeof(unsigned long long), s));
-        HIPCHK(hipMemsetAsync(ka.hlo, 0x7F, (size_t)2 * cap * span * sizeof(int), s));
-        HIPCHK(hipMemsetAsync(ka.hhi, 0xFF, (size_t)2 * cap * span * sizeof(int), s));
+    // (or reset) kernel of each call; they are cleared here only when laid
+    // out anew or when a previous call stopped before that kernel
+    if (kl.clear) {
+        const size_t rows = (size_t)2 * kl.stride;
+        HIPCHK(hipMemsetAsync(ka.table, 0xFF, rows * sizeof(unsigned long long), s));
+        HIPCHK(hipMemsetAsync(ka.hlo, 0x7F, rows * span * sizeof(int), s));
+        HIPCHK(hipMemsetAsync(ka.hhi, 0xFF, rows * span * sizeof(int), s));
         HIPCHK(hipMemsetAsync(ka.count, 0, 2 * kKeySubs * sizeof(int), s));
     }
-    c.ktab_clean = false;
+    c.klay.clean = false;
     HIPCHK(launch_keys(ka, s));
     HIPCHK(hipMemcpyAsync(c.h_pin, c.d_kcnt.p, 2 * kKeySubs * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -707,7 +713,7 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
         // little sharing: contract per pattern (the bounds are in place)
         HIPCHK(launch_key_reset(ka, ntop, nbot, s));
         HIPCHK(hipMemsetAsync(ka.count, 0, 2 * kKeySubs * sizeof(int), s));
-        c.ktab_clean = true;
+        c.klay.clean = true;
         return LOFP_OK;
     }
     used = true;
@@ -737,9 +743,9 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
             bj.out_pos |= (uint64_t)(std::find(tl.begin(), tl.end(), bl[q2]) - tl.begin()) << (4 * q2);
     }
     HIPCHK(ensure(c.d_jobs, (size_t)std::max(nj, 1) * sizeof(ContractJob)));
-    HIPCHK(ensure(c.d_kinf, (size_t)std::max(nj, 1) * sizeof(int32_t)));
+    HIPCHK(ensure(c.d_kinf, (size_t)2 * std::max(nj, 1) * sizeof(int32_t)));   // per job: no path, overflow
     HIPCHK(launch_key_jobs(ka, ntop, nbot, tj, bj, c.d_jobs.as<ContractJob>(), c.d_kinf.as<int32_t>(), s));
-    c.ktab_clean = true;
+    c.klay.clean = true;
     unsigned long long *ctr = c.d_counters.as<unsigned long long>();   // zeroed by k_key_jobs
     int mx;
     if (cap_s <= (1 << 20)) {
@@ -753,6 +759,7 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
         if (mx > (1 << 22)) return fail(LOFP_ENOMEM, "contraction state exceeds 2^22 entries");
         mx = std::max(mx, 1);
     }
+    if (state_limit > 0 && mx > state_limit) mx = state_limit;
     // LDS budget of a job (a few jobs per CU), of which what the descriptors
     // and interval arrays leave holds the two state buffers; a job whose own
     // largest state does not fit keeps them in its workspace slice
@@ -778,7 +785,7 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     ja.B = B; ja.m = m; ja.n = n; ja.D = c.D;
     ja.lo = c.d_lo.as<int16_t>(); ja.hi = c.d_hi.as<int16_t>();
     ja.infeasible = c.d_inf.as<int32_t>();
-    ja.slot = ka.slot; ja.slot_key = ka.slot_key; ja.cap = cap;
+    ja.slot = ka.slot; ja.slot_key = ka.slot_key; ja.stride = kl.stride;
     ja.tlo = ka.klo; ja.thi = ka.khi;
     ja.blo = ka.klo + (size_t)B * span; ja.bhi = ka.khi + (size_t)B * span;
     ja.nshared = (int)sp->top.live_out.size();
@@ -789,6 +796,8 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     ja.top_state = c.d_kstate.as<double2>();
     ja.bot_state = c.d_kstate.as<double2>() + (size_t)ntop * mx;
     ja.state_cap = mx;
+    ja.top_ovf = c.d_kinf.as<int32_t>() + nj;
+    ja.bot_ovf = ja.top_ovf + ntop;
     ja.out = reinterpret_cast<double2 *>(out_dev);
     HIPCHK(launch_join(ja, s));
     tm.mark();
@@ -1170,6 +1179,7 @@ lofp_status lofp_circuit_destroy(lofp_circuit c)
     for (DevBuf *b : bufs) release(*b);
     if (c->h_pin) (void)hipHostFree(c->h_pin);
     if (c->ready_ev) (void)hipEventDestroy(c->ready_ev);
+    if (c->last_ev) (void)hipEventDestroy(c->last_ev);
     delete c;
     return LOFP_OK;
 }
@@ -1234,6 +1244,8 @@ lofp_status lofp_bounds_batch(lofp_circuit c, const int32_t *S, int32_t batch, c
     hipStream_t s = nullptr;
     rc = device_init(*c, n, s);
     if (rc != LOFP_OK) return rc;
+    StreamUse use(*c, s);
+    HIPCHK(use.begin());
     std::vector<int32_t> Sv(S, S + c->m);
     if (Sv != c->S_dev) {
         HIPCHK(upload(c->d_S, Sv, s));
@@ -1281,11 +1293,11 @@ lofp_status lofp_bs_table(lofp_circuit c, int32_t gate, int32_t N, lofp_c128 *ou
     return LOFP_OK;
 }
 
-// Largest batch one pass takes; larger batches run in passes of this size,
-// which keeps every launch within the sizes the tests cover (a pass of
-// 32768 patterns through the split contraction faulted the device once, with
-// the cause not yet found).
-constexpr int kMaxPass = 4096;
+// Largest batch one pass takes; larger batches run in passes of this size.
+// It bounds the per-call workspace of the split contraction, whose grouping
+// keeps a hash slot and a hull row of 2 x span ints per four patterns of the
+// batch (about 280 MiB at this size on the 16-mode, depth-8 workload).
+constexpr int kMaxPass = 32768;
 
 lofp_status lofp_amplitudes_device(lofp_circuit c, const int32_t *S, int32_t batch, const int32_t *T_dev,
                                    lofp_c128 *out_dev, const lofp_opts *opts, void *stream, lofp_stats *stats)
@@ -1335,6 +1347,8 @@ lofp_status lofp_amplitudes_device(lofp_circuit c, const int32_t *S, int32_t bat
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = device_init(*c, n, s);
     if (rc != LOFP_OK) return rc;
+    StreamUse use(*c, s);
+    HIPCHK(use.begin());
     std::vector<int32_t> Sv(S, S + c->m);
     if (Sv != c->S_dev) {
         HIPCHK(upload(c->d_S, Sv, s));
@@ -1362,7 +1376,7 @@ lofp_status lofp_amplitudes_device(lofp_circuit c, const int32_t *S, int32_t bat
         inner.on = tm.on;
         inner.s = s;
         rc = run_contract(*c, S, n, batch, T_dev, out_dev, 0, o.precision == LOFP_PREC_FP32, s, stats,
-                          o.count_work != 0, inner);
+                          o.count_work != 0, o.state_limit, inner);
         if (rc == LOFP_OK && stats && tm.on) {
             // bounds (and key hulls), contraction kernel, join of split halves
             stats->ms_plan = inner.ms(0, 1);
@@ -1434,6 +1448,8 @@ lofp_status lofp_path_counts(lofp_circuit c, const int32_t *S, int32_t batch, co
     hipStream_t s = nullptr;
     rc = device_init(*c, n, s);
     if (rc != LOFP_OK) return rc;
+    StreamUse use(*c, s);
+    HIPCHK(use.begin());
     std::vector<int32_t> Sv(S, S + c->m);
     if (Sv != c->S_dev) {
         HIPCHK(upload(c->d_S, Sv, s));
@@ -1444,7 +1460,7 @@ lofp_status lofp_path_counts(lofp_circuit c, const int32_t *S, int32_t batch, co
     HIPCHK(hipMemcpyAsync(c->d_T.p, T, (size_t)batch * c->m * sizeof(int32_t), hipMemcpyHostToDevice, s));
     Timer tm;
     lofp_stats st{};
-    rc = run_contract(*c, S, n, batch, c->d_T.as<int32_t>(), c->d_out.as<lofp_c128>(), 1, 0, s, &st, false, tm);
+    rc = run_contract(*c, S, n, batch, c->d_T.as<int32_t>(), c->d_out.as<lofp_c128>(), 1, 0, s, &st, false, 0, tm);
     if (rc != LOFP_OK) return rc;
     std::vector<double2> h(batch);
     HIPCHK(hipMemcpyAsync(h.data(), c->d_out.p, (size_t)batch * sizeof(double2), hipMemcpyDeviceToHost, s));

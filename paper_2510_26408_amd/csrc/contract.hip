@@ -47,6 +47,24 @@ __device__ __forceinline__ int qdiv(int a, int d, float inv)
 // global loads with a 32-bit offset rather than flat ones)
 typedef const double __attribute__((address_space(1))) gdouble;
 
+// A result that could not be computed (a state larger than its buffers):
+// NaN in both parts, so no caller takes it for an amplitude.
+__device__ __forceinline__ double2 nan2()
+{
+    return make_double2(__builtin_nan(""), __builtin_nan(""));
+}
+
+// A job whose state does not fit its buffers stops (whole block, uniform
+// condition): the launch's overflow flag, the job's own flag and a NaN in
+// its amplitude record it.
+__device__ __forceinline__ void job_overflow(const ContractJob &g, int32_t *overflow)
+{
+    if (threadIdx.x != 0) return;
+    atomicOr(overflow, 1);
+    if (g.ovf) *g.ovf = 1;
+    if (g.out) *g.out = nan2();
+}
+
 // Per-step layout, built once per job from the step program and the job's
 // intervals (all values uniform over the block).  New entry e decodes into
 // digits d_q = (e / nstr[q]) mod rad_q; the old entry it reads sits at
@@ -469,6 +487,11 @@ __device__ void contract_run(const ContractJob &g, unsigned char *smem, unsigned
     off = (off + 15) & ~(size_t)15;
     StepDesc *desc = reinterpret_cast<StepDesc *>(smem + off);
     double2 *bufA, *bufB;
+    if (!LDS_STATE && g.ws == nullptr) {
+        // no global workspace was planned for this job
+        job_overflow(g, overflow);
+        return;
+    }
     if (LDS_STATE) bufA = reinterpret_cast<double2 *>(smem + job_lds_head(g.nvars, nc));
     else bufA = g.ws;
     bufB = bufA + g.max_states;
@@ -504,7 +527,7 @@ __device__ void contract_run(const ContractJob &g, unsigned char *smem, unsigned
         const StepDesc &d = desc[slot];
         const int new_size = d.new_size;
         if (new_size > g.max_states) {
-            if (threadIdx.x == 0) atomicOr(overflow, 1);
+            job_overflow(g, overflow);
             return;
         }
         step_entries<COUNT, F32, BS, STATS>(d, bufA, bufB, (const gdouble *)(g.table + (int64_t)d.gate * g.tab_stride),
@@ -516,7 +539,7 @@ __device__ void contract_run(const ContractJob &g, unsigned char *smem, unsigned
     if (g.state_out) {
         // half of a split contraction: hand the state over instead of summing it
         if (cur_size > g.state_cap) {
-            if (threadIdx.x == 0) atomicOr(overflow, 1);
+            job_overflow(g, overflow);
             return;
         }
         if (!g.out_remap || g.nsteps == 0) {
@@ -597,6 +620,7 @@ __global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
     j.state_out = nullptr;
     j.state_cap = 0;
     j.stats = g.stats;
+    j.ovf = nullptr;
     if (!contract_setup<BS>(j, smem)) return;
     contract_run<COUNT, F32, LDS_STATE, BS, STATS>(j, smem, g.stat_transitions, g.overflow);
 }
@@ -690,7 +714,8 @@ __global__ __launch_bounds__(kJoinBlock) void k_join(JoinArgs g)
         if (threadIdx.x == 0) g.out[p] = make_double2(0.0, 0.0);
         return;
     }
-    const int tk = g.slot_key[g.slot[p]], bk = g.slot_key[g.cap + g.slot[g.B + p]];
+    const int tk = g.slot_key[key_slot_index(0, g.stride, g.slot[p])];
+    const int bk = g.slot_key[key_slot_index(1, g.stride, g.slot[g.B + p])];
     const int16_t *plo = g.lo + (int64_t)p * span, *phi = g.hi + (int64_t)p * span;
     const int16_t *tlo = g.tlo + (int64_t)tk * span, *thi = g.thi + (int64_t)tk * span;
     const int16_t *blo = g.blo + (int64_t)bk * span, *bhi = g.bhi + (int64_t)bk * span;
@@ -706,18 +731,32 @@ __global__ __launch_bounds__(kJoinBlock) void k_join(JoinArgs g)
     int pstr[NS > 0 ? NS : 1], toff[NS > 0 ? NS : 1], tstr[NS > 0 ? NS : 1], boff[NS > 0 ? NS : 1];
     int bstr[NS > 0 ? NS : 1];
     float pinv[NS > 0 ? NS : 1];
-    int box = 1, ts = 1, bs = 1;
+    int box = 1;
+    int64_t ts = 1, bs = 1;
+    bool fits = !g.top_ovf[tk] && !g.bot_ovf[bk];
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
         pstr[q] = box;
         pinv[q] = 1.0f / (float)box;
         toff[q] = pl[q] - tl[q];          // state digit = pattern digit + offset
         boff[q] = pl[q] - bl[q];
-        tstr[q] = ts;
-        bstr[q] = bs;
-        ts *= th[q] - tl[q] + 1;
-        bs *= bh[q] - bl[q] + 1;
+        tstr[q] = (int)ts;
+        bstr[q] = (int)bs;
+        ts *= th[q] >= tl[q] ? th[q] - tl[q] + 1 : 0;
+        bs *= bh[q] >= bl[q] ? bh[q] - bl[q] + 1 : 0;
+        ts = ts < (1LL << 40) ? ts : (1LL << 40);
+        bs = bs < (1LL << 40) ? bs : (1LL << 40);
         box *= ph[q] >= pl[q] ? ph[q] - pl[q] + 1 : 0;
+        box = box < (1 << 30) ? box : (1 << 30);
+        // a feasible pattern's box lies inside both keys' boxes (each key's
+        // box is the hull of its members' boxes)
+        fits = fits && (ph[q] < pl[q] || (pl[q] >= tl[q] && ph[q] <= th[q] && pl[q] >= bl[q] && ph[q] <= bh[q]));
+    }
+    // both states must be as large as their keys' boxes say
+    fits = fits && ts <= g.state_cap && bs <= g.state_cap;
+    if (!fits) {
+        if (threadIdx.x == 0) g.out[p] = nan2();
+        return;
     }
     const gdouble *TS = (const gdouble *)(g.top_state + (int64_t)tk * g.state_cap);
     const gdouble *BS_ = (const gdouble *)(g.bot_state + (int64_t)bk * g.state_cap);

@@ -140,6 +140,9 @@ struct lofp_circuit_s {
     bool pending_init = false;
     hipEvent_t ready_ev = nullptr;
     hipStream_t ready_stream = nullptr;
+    // end of the last call's work on the per-call buffers below, and its stream
+    hipEvent_t last_ev = nullptr;
+    hipStream_t last_stream = nullptr;
     bool prog_built = false;
     bool prog_on_device = false;
     std::string prog_error;
@@ -164,7 +167,7 @@ struct lofp_circuit_s {
     DevBuf d_ktab, d_kslot, d_kof, d_krep, d_kcnt, d_khull, d_klohi, d_kinf, d_jobs, d_kstate, d_korder;
     std::vector<std::shared_ptr<lofp::host::SharedBlock>> blocks;   // pooled set-up blocks in use
     int32_t *h_pin = nullptr;              // small pinned readback buffer
-    bool ktab_clean = false;               // key hash table known to be empty
+    lofp::KeyLayoutState klay;             // layout of the key table and hulls
     std::vector<int32_t> S_dev;            // the S now held in d_S
     // S-only bounds of the last S asked for, and the state bounds under them
     // (the whole program; each split program by its split cut)
@@ -204,6 +207,37 @@ struct Timer {
     }
 };
 
+
+// The per-call buffers of a circuit serve every call on it, whatever its
+// stream: a call first makes its stream wait for the previous call's work
+// when that ran on another stream, and on leaving records where its own work
+// ends (enqueued or not, whatever the status).
+class StreamUse {
+public:
+    StreamUse(lofp_circuit_s &c, hipStream_t s) : c_(c), s_(s) {}
+    StreamUse(const StreamUse &) = delete;
+    StreamUse &operator=(const StreamUse &) = delete;
+    hipError_t begin()
+    {
+        armed_ = true;
+        if (c_.last_ev && c_.last_stream != s_) return hipStreamWaitEvent(s_, c_.last_ev, 0);
+        return hipSuccess;
+    }
+    ~StreamUse()
+    {
+        if (!armed_) return;
+        if (!c_.last_ev && hipEventCreateWithFlags(&c_.last_ev, hipEventDisableTiming) != hipSuccess) {
+            c_.last_ev = nullptr;
+            return;
+        }
+        if (hipEventRecord(c_.last_ev, s_) == hipSuccess) c_.last_stream = s_;
+    }
+
+private:
+    lofp_circuit_s &c_;
+    hipStream_t s_;
+    bool armed_ = false;
+};
 
 lofp_status check_S(const lofp_circuit_s &c, const int32_t *S, int &n);
 // S-only bounds of S, cached on the circuit (the caller holds its lock).

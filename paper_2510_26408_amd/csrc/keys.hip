@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void k_key_insert(KeyArgs a)
     const unsigned v = (unsigned)(tot == a.n ? p : p + a.B);
     const unsigned long long hv = (h >> 32) << 32;
     const unsigned long long mine_e = hv | v;
-    unsigned long long *tab = a.table + (int64_t)half * a.cap;
+    unsigned long long *tab = a.table + key_slot_index(half, a.stride, 0);
     uint32_t j = (uint32_t)h & (uint32_t)(a.cap - 1);
     // at most B rows per half and cap >= 4B slots: a free slot is always found
     for (int probe = 0; probe < a.cap; ++probe) {
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_key_insert(KeyArgs a)
     if (lane == 0) a.slot[gw] = (int)j;
     if (a.infeasible[p]) return;
     // the slot's hull of its feasible members' intervals
-    const int64_t row = ((int64_t)half * a.cap + j) * a.span;
+    const int64_t row = key_hull_row(half, a.stride, j, a.span);
     for (int i = lane; i < a.span; i += 64) {
         atomicMin(&a.hlo[row + i], (int)a.lo[(int64_t)p * a.span + i]);
         atomicMax(&a.hhi[row + i], (int)a.hi[(int64_t)p * a.span + i]);
@@ -124,8 +124,8 @@ __global__ __launch_bounds__(256) void k_key_jobs(KeyArgs a, int ntop, int nbot,
     if (w >= ntop + nbot) return;
     const int half = w >= ntop, k = half ? w - ntop : w;
     const int sl = key_slot_of(a, half, k);
-    if (lane == 0) a.slot_key[(int64_t)half * a.cap + sl] = k;
-    const int64_t srow = ((int64_t)half * a.cap + sl) * a.span;
+    if (lane == 0) a.slot_key[key_slot_index(half, a.stride, sl)] = k;
+    const int64_t srow = key_hull_row(half, a.stride, sl, a.span);
     const int64_t krow = ((int64_t)half * a.B + k) * a.span;
     for (int i = lane; i < a.span; i += 64) {
         int l = a.hlo[srow + i], h = a.hhi[srow + i];
@@ -155,11 +155,11 @@ __global__ __launch_bounds__(256) void k_key_jobs(KeyArgs a, int ntop, int nbot,
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) work += __shfl_xor(work, o, 64);
     for (int i = lane; i < a.span; i += 64) {
-        a.hlo[srow + i] = 0x7f7f7f7f;
-        a.hhi[srow + i] = -1;
+        a.hlo[srow + i] = kHullEmptyLo;
+        a.hhi[srow + i] = kHullEmptyHi;
     }
     if (lane != 0) return;
-    unsigned long long *tab = a.table + (int64_t)half * a.cap;
+    unsigned long long *tab = a.table + key_slot_index(half, a.stride, 0);
     const int rv = (int)(unsigned)tab[sl];
     tab[sl] = kKeyEmpty;
     a.job_bucket[w] = work > 1.0f ? min(255, (int)(8.0f * log2f(work))) : 0;
@@ -169,6 +169,8 @@ __global__ __launch_bounds__(256) void k_key_jobs(KeyArgs a, int ntop, int nbot,
     J.hi = a.khi + krow;
     J.infeasible = kinf + w;
     kinf[w] = 0;
+    J.ovf = kinf + ntop + nbot + w;   // the join reads it
+    kinf[ntop + nbot + w] = 0;
     J.out = nullptr;
     jobs[w] = J;
 }
@@ -184,12 +186,12 @@ __global__ __launch_bounds__(256) void k_key_reset(KeyArgs a, int ntop, int nbot
     if (w >= ntop + nbot) return;
     const int half = w >= ntop, k = half ? w - ntop : w;
     const int sl = key_slot_of(a, half, k);
-    const int64_t srow = ((int64_t)half * a.cap + sl) * a.span;
+    const int64_t srow = key_hull_row(half, a.stride, sl, a.span);
     for (int i = lane; i < a.span; i += 64) {
-        a.hlo[srow + i] = 0x7f7f7f7f;
-        a.hhi[srow + i] = -1;
+        a.hlo[srow + i] = kHullEmptyLo;
+        a.hhi[srow + i] = kHullEmptyHi;
     }
-    if (lane == 0) a.table[(int64_t)half * a.cap + sl] = kKeyEmpty;
+    if (lane == 0) a.table[key_slot_index(half, a.stride, sl)] = kKeyEmpty;
 }
 
 // One block: the jobs in decreasing work bucket (a counting sort; the order

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "key_layout.h"
 #include "lofp_core.h"
 
 namespace lofp {
@@ -228,6 +229,8 @@ struct ContractJob {
     int out_remap;               // state_out in another variable order: the
     uint64_t out_pos;            // final state's variable q goes to place
                                  // (out_pos >> 4q) & 15
+    int32_t *ovf;                // set to 1 when the job's state did not fit
+                                 // its buffers (nullptr: not recorded)
 };
 // Per-launch overrides for key jobs of a split contraction (0 / nullptr: use
 // the job's own fields): one state size for every job, and per-job slices of
@@ -260,25 +263,25 @@ hipError_t launch_contract_multi(int count, const ContractJob *jobs, size_t lds_
 // Largest state over the jobs (one thread per job), atomically maxed into *mx.
 hipError_t launch_multi_sizes(int count, const ContractJob *jobs, int *mx, hipStream_t stream);
 
-constexpr unsigned long long kKeyEmpty = ~0ULL;   // an empty hash slot
 constexpr int kKeySubs = 64;   // claim counters per half (spread the atomics)
 // Grouping of a batch by the halves of T (split contraction), per half h:
 // a hash table over the distinct half-rows, whose slots carry the group's
 // key number and the hull of its feasible members' intervals.
 struct KeyArgs {
     int B, m, n, rs, cap, span;
+    int64_t stride;                // rows per half of the layout (>= cap; key_layout.h)
     const int32_t *T;              // [B][m]
     const int16_t *lo, *hi;        // per pattern [B][span]
     const int32_t *infeasible;     // [B]
-    unsigned long long *table;     // [2][cap] kKeyEmpty, or the row's hash (high
+    unsigned long long *table;     // [2][stride] kKeyEmpty, or the row's hash (high
                                    // 32 bits) above the group's lowest member p
                                    // (p + B if p has the wrong photon number)
     int *slot;                     // [2][B] each pattern's slot
-    int *slot_key;                 // [2][cap] key number of a claimed slot
+    int *slot_key;                 // [2][stride] key number of a claimed slot
     int *key_slot;                 // [2][kKeySubs][B] claimed slots per sub-counter
     int *count;                    // [2][kKeySubs] claims per sub-counter (slot
                                    // mod kKeySubs); zeroed by the order kernel
-    int *hlo, *hhi;                // [2][cap][span] int32 hull per slot
+    int *hlo, *hhi;                // [2][stride][span] int32 hull per slot
     int16_t *klo, *khi;            // per key intervals (top keys at 0, bottom at B)
     unsigned long long *counters;  // [8] zeroed by the jobs kernel
     int *job_bucket;               // [2B] cost bucket of each job
@@ -300,8 +303,8 @@ struct JoinArgs {
     const int16_t *lo, *hi;          // per pattern [B][span]
     const int32_t *infeasible;
     const int32_t *slot;             // [2][B] each pattern's slot per half
-    const int32_t *slot_key;         // [2][cap] key number of each slot
-    int cap;
+    const int32_t *slot_key;         // [2][stride] key number of each slot
+    int64_t stride;                  // rows per half of the slot layout
     const int16_t *tlo, *thi;        // per top key [ntop][span]
     const int16_t *blo, *bhi;        // per bottom key [nbot][span]
     int nshared;
@@ -310,6 +313,7 @@ struct JoinArgs {
                                      // both states are laid out in that order
     const double2 *top_state, *bot_state;
     int state_cap;
+    const int32_t *top_ovf, *bot_ovf; // per key: its job's state did not fit
     double2 *out;
 };
 hipError_t launch_join(const JoinArgs &a, hipStream_t stream);

@@ -250,6 +250,7 @@ lofp_status launch_batch(Batch &b, int fp32, bool checked = false)
         K.state_cap = 0;
         K.stats = 0;
         K.out_remap = 0;
+        K.ovf = nullptr;
         ws_off += (size_t)2 * r.est;
         max_span = std::max(max_span, (c.D + 1) * (c.m - 1));
     }
@@ -479,11 +480,15 @@ lofp_status lofp_amplitudes_multi(int32_t count, const lofp_request *req, lofp_c
     tm.mark();
     HIPCHK(hipStreamSynchronize(b.s));
     std::memcpy(out, b.h_out, count * sizeof(lofp_c128));
-    if (stats) {
+    {
+        // the call has synchronised: an overflow (its results are NaN) is
+        // reported whether or not statistics were asked for
         unsigned long long h[2];
         HIPCHK(hipMemcpy(h, b.d_ctr.p, sizeof(h), hipMemcpyDeviceToHost));
         if (h[1]) return fail(LOFP_ENOMEM, "contraction workspace overflow");
-        stats->transitions = (int64_t)h[0];
+        if (stats) stats->transitions = (int64_t)h[0];
+    }
+    if (stats) {
         if (tm.on) stats->ms_total = stats->ms_contract = tm.ms(0, 1);
     }
     for (int i = 0; i < count && err_bound; ++i) err_bound[i] = std::nan("");

@@ -45,7 +45,7 @@ class C128(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("precision", ctypes.c_int32), ("fwd_layer", ctypes.c_int32),
                 ("bwd_layer", ctypes.c_int32), ("record_timing", ctypes.c_int32),
-                ("frontier_budget_kb", ctypes.c_int32), ("count_work", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("frontier_budget_kb", ctypes.c_int32), ("count_work", ctypes.c_int32), ("state_limit", ctypes.c_int32),
                 ("fp32_rtol", ctypes.c_double)]
 
 
@@ -142,13 +142,14 @@ def _ip(a: np.ndarray):
 
 def make_opts(method: int = METHOD_AUTO, precision: int = PREC_FP64, fwd_layer: int = -1, bwd_layer: int = -1,
               record_timing: bool = False, frontier_budget_kb: int = 0, count_work: bool = False,
-              fp32_rtol: float = 0.0) -> Opts:
+              fp32_rtol: float = 0.0, state_limit: int = 0) -> Opts:
     o = Opts()
     o.method, o.precision, o.fwd_layer, o.bwd_layer = method, precision, fwd_layer, bwd_layer
     o.record_timing = 1 if record_timing else 0
     o.frontier_budget_kb = frontier_budget_kb
     o.count_work = 1 if count_work else 0
     o.fp32_rtol = fp32_rtol
+    o.state_limit = state_limit
     return o
 
 

@@ -574,9 +574,6 @@ def test_high_photon_density_all_outputs(m, D, S):
         assert abs(np.sum(np.abs(got) ** 2) - 1.0) < 1e-12
 
 
-@pytest.mark.skip(reason="a single 32768-pattern pass through the split contraction faulted the GPU; the cause "
-                         "is not found yet, and calls now run batches above 4096 in passes of 4096; kept off the "
-                         "GPU until the cause is shown")
 def test_split_contraction_large_batch():
     """32768 patterns in one call (eight times the benchmark batch): the
     grouping, job and join grids at that size; a sample against the oracle,
@@ -593,3 +590,112 @@ def test_split_contraction_large_batch():
     check(got[:4096], part, 1e-14)
     again = c.amplitudes(wl.S, wl.Ts, lofp.make_opts(method=lofp.METHOD_CONTRACT))
     assert np.array_equal(got, again)
+
+
+def test_split_contraction_shrinking_batches_on_one_circuit():
+    """One circuit, split batches of falling size in a row (4096, then 904
+    and 1000 patterns split for parallelism, then 300): each call's grouping
+    reuses the table and hull layout of the first, and every result equals the
+    unsplit contraction of the same rows (and the oracle on a sample)."""
+    wl = workloads.make("c2", seed=6)
+    c = lofp.Circuit(wl.m, wl.layers)
+    opts = lofp.make_opts(method=lofp.METHOD_CONTRACT)
+    unsplit = np.concatenate([c.amplitudes(wl.S, wl.Ts[i:i + 32], opts) for i in range(0, 1024, 32)])
+    for lo_, hi_ in ((0, 4096), (100, 1004), (0, 1000), (700, 1000)):
+        st = lofp.Stats()
+        got = c.amplitudes(wl.S, wl.Ts[lo_:hi_], opts, st)
+        assert st.split_top_keys > 0 and st.split_bottom_keys > 0, (lo_, hi_)
+        assert not np.isnan(got).any()
+        k = min(hi_, 1024) - lo_
+        if k > 0:
+            check(got[:k], unsplit[lo_:lo_ + k], 1e-14)
+    idx = np.random.default_rng(8).choice(1024, 32, replace=False)
+    check(unsplit[idx], oracle_amps(wl.m, wl.S, wl.Ts[idx], wl.layers))
+
+
+def test_split_contraction_batch_in_two_passes():
+    """A batch above the pass size (32768 + 1024 patterns) runs in two passes
+    on one circuit, the second smaller: rows equal the same rows computed in
+    chunks of at most 4096, stats sum over the passes, a sample equals the
+    oracle."""
+    wl = workloads.make("c2", seed=11, batch=33792)
+    c = lofp.Circuit(wl.m, wl.layers)
+    opts = lofp.make_opts(method=lofp.METHOD_CONTRACT)
+    st = lofp.Stats()
+    got = c.amplitudes(wl.S, wl.Ts, opts, st)
+    assert st.batch == wl.batch and not np.isnan(got).any()
+    chunks, keys = [], [0, 0]
+    for i in range(0, wl.batch, 4096):
+        sc = lofp.Stats()
+        chunks.append(c.amplitudes(wl.S, wl.Ts[i:i + 4096], opts, sc))
+        keys[0] += sc.split_top_keys
+        keys[1] += sc.split_bottom_keys
+    check(got, np.concatenate(chunks), 1e-14)
+    # the two passes share more halves than nine chunks do
+    assert 0 < st.split_top_keys <= keys[0] and 0 < st.split_bottom_keys <= keys[1]
+    idx = np.random.default_rng(12).choice(wl.batch, 32, replace=False)
+    check(got[idx], oracle_amps(wl.m, wl.S, wl.Ts[idx], wl.layers))
+
+
+@pytest.mark.parametrize("batch", [16, 300])
+def test_contraction_overflow_is_nan_without_stats_and_enomem_with(batch):
+    """A state larger than its buffers (forced from the host with a state
+    limit of two entries): without stats every affected result is NaN, with
+    stats the call returns ENOMEM; the next call without the limit is right.
+    16 patterns take one contraction per pattern, 300 the split contraction
+    (whose jobs then have neither LDS room nor a workspace: they stop)."""
+    wl = workloads.make("c2", seed=13, batch=batch)
+    c = lofp.Circuit(wl.m, wl.layers)
+    want = oracle_amps(wl.m, wl.S, wl.Ts, wl.layers)
+    tight = lofp.make_opts(method=lofp.METHOD_CONTRACT, state_limit=2)
+    got = c.amplitudes(wl.S, wl.Ts, tight)
+    live = np.abs(want) > 0
+    assert live.sum() > 0 and np.isnan(got[live]).all()
+    with pytest.raises(lofp.LofpError) as e:
+        c.amplitudes(wl.S, wl.Ts, tight, lofp.Stats())
+    assert e.value.status == lofp.ENOMEM
+    check(c.amplitudes(wl.S, wl.Ts, lofp.make_opts(method=lofp.METHOD_CONTRACT)), want)
+
+
+def test_c5_full_batch_split_for_parallelism():
+    """The 32-mode, depth-6 workload at its full 512 patterns, in the launch
+    the benchmark times (the batch split into top and bottom halves for
+    parallelism): 64 patterns against the oracle, all 512 against the
+    unsplit contraction."""
+    wl = workloads.make("c5", seed=0)
+    assert wl.batch == 512
+    c = lofp.Circuit(wl.m, wl.layers)
+    st = lofp.Stats()
+    got = c.amplitudes(wl.S, wl.Ts, lofp.make_opts(), st)
+    assert st.method_used == lofp.METHOD_CONTRACT and st.split_top_keys > 0
+    idx = np.random.default_rng(14).choice(wl.batch, 64, replace=False)
+    check(got[idx], oracle_amps(wl.m, wl.S, wl.Ts[idx], wl.layers))
+    ref = np.concatenate([c.amplitudes(wl.S, wl.Ts[i:i + 32], lofp.make_opts(method=lofp.METHOD_CONTRACT))
+                          for i in range(0, wl.batch, 32)])
+    check(got, ref, 1e-14)
+
+
+def test_fp32_depth_first_products_within_bound():
+    """The depth-first kernel's FP32 form (running path products in FP32,
+    frontier values and sums in FP64), with the frontiers at S and T so that
+    every splitter is enumerated: each result lies within the stated FP32
+    bound ((1 + f)^G - 1 + 4 * 2^-53) A_abs of the oracle, and the FP64 form
+    within 1e-12."""
+    items = _small_items(16, seed=41)
+    done = 0
+    for c, m, n, layers, S, T in items:
+        circ = flat(layers)
+        if len(circ) > 16:
+            continue
+        done += 1
+        want = oracle.amplitude(m, S, T, circ)
+        a_abs = oracle.absolute_form(m, S, T, circ)
+        o32 = lofp.make_opts(method=lofp.METHOD_PATHSUM, precision=lofp.PREC_FP32, fwd_layer=0,
+                             bwd_layer=len(layers))
+        st = lofp.Stats()
+        got = c.amplitudes(S, T[None, :], o32, st)[0]
+        assert st.dfs_levels == len(circ)
+        assert abs(got - want) <= _growth(len(circ), n, fp32=True) * a_abs + 1e-300, (abs(got - want), a_abs)
+        o64 = lofp.make_opts(method=lofp.METHOD_PATHSUM, fwd_layer=0, bwd_layer=len(layers))
+        assert abs(c.amplitudes(S, T[None, :], o64)[0] - want) <= ATOL
+    assert done >= 6
