@@ -194,7 +194,30 @@ lofp_status lofp_amplitudes_device(lofp_circuit c, const int32_t *S, int32_t bat
                                    const int32_t *T_dev, lofp_c128 *out_dev,
                                    const lofp_opts *opts, void *stream, lofp_stats *stats);
 
-/* Same, host-memory form: T is host int32[batch*m], out host lofp_c128[batch].
+/* Allocation-free form of lofp_amplitudes_device, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid allocation).  It runs the contraction one pattern
+ * per block (method AUTO or CONTRACT; precision FP64 or FP32; state_limit
+ * honoured; other options ignored) with every per-call buffer carved from
+ * one fixed device array of the library (32 MiB per device, held until the
+ * process ends); it calls no device allocation routine.
+ * S: host int32[m].  T_dev: device int32[batch*m].  out_dev: device
+ * lofp_c128[batch].  stream: hipStream_t (NULL = default).  Stream-ordered,
+ * no synchronisation.  A result whose state did not fit is NaN + NaN i.
+ * All calls on one device share the array, which keeps the last call's
+ * contents: calls that overlap on one device race (order them on one stream
+ * or synchronise between them).
+ * Errors: EINVAL for null arguments, a batch whose buffers exceed the array
+ * (the message gives the bytes needed), or a circuit whose tables and step
+ * program are not yet on the device for this photon number (make one
+ * lofp_amplitudes_device call with the contraction first); ENOTSUP for the
+ * path-sum method or a state beyond 2^22 entries. */
+lofp_status lofp_amplitudes_device_noalloc(lofp_circuit c, const int32_t *S, int32_t batch,
+                                           const int32_t *T_dev, lofp_c128 *out_dev,
+                                           const lofp_opts *opts, void *stream);
+
+/* Host-memory form of lofp_amplitudes_device: T is host int32[batch*m], out
+ * host lofp_c128[batch].
  * Copies in and out and synchronises; for convenience, not for timing. */
 lofp_status lofp_amplitudes(lofp_circuit c, const int32_t *S, int32_t batch, const int32_t *T,
                             lofp_c128 *out, const lofp_opts *opts, lofp_stats *stats);

@@ -24,7 +24,7 @@ EXPORTED = (
     "lofp_last_error", "lofp_version", "lofp_circuit_create", "lofp_circuit_destroy", "lofp_light_cone",
     "lofp_bounds", "lofp_bounds_batch", "lofp_bs_table", "lofp_amplitudes_device", "lofp_amplitudes", "lofp_amplitude",
     "lofp_path_counts", "lofp_amplitudes_multi", "lofp_server_create", "lofp_server_submit",
-    "lofp_server_result", "lofp_server_get_stats", "lofp_server_destroy",
+    "lofp_server_result", "lofp_server_get_stats", "lofp_server_destroy", "lofp_amplitudes_device_noalloc",
 )
 
 
@@ -121,6 +121,7 @@ def load():
                                        ctypes.POINTER(ctypes.c_int32)]
     lib.lofp_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     lib.lofp_server_destroy.argtypes = [vp]
+    lib.lofp_amplitudes_device_noalloc.argtypes = [vp, i32p, ctypes.c_int32, vp, vp, ctypes.POINTER(Opts), vp]
     for f in EXPORTED[2:]:
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -246,6 +247,24 @@ class Circuit:
                                              ctypes.byref(opts) if opts is not None else None,
                                              ctypes.c_void_p(stream.cuda_stream),
                                              ctypes.byref(stats) if stats is not None else None))
+
+    def amplitudes_device_noalloc(self, S, T_dev, out_dev, opts: Optional[Opts] = None, stream=None) -> None:
+        """The allocation-free form of :meth:`amplitudes_device` (contraction
+        per pattern, per-call buffers in the library's fixed device scratch).
+        The circuit must have been set up by an earlier contraction call."""
+        import torch
+
+        S = _i32(S)
+        assert T_dev.dtype == torch.int32 and T_dev.is_contiguous() and T_dev.shape[-1] == self.m
+        assert out_dev.dtype == torch.complex128 and out_dev.is_contiguous()
+        B = int(T_dev.shape[0])
+        assert out_dev.numel() >= B
+        if stream is None:
+            stream = torch.cuda.current_stream(T_dev.device)
+        _check(load().lofp_amplitudes_device_noalloc(self._h, _ip(S), B, ctypes.c_void_p(T_dev.data_ptr()),
+                                                     ctypes.c_void_p(out_dev.data_ptr()),
+                                                     ctypes.byref(opts) if opts is not None else None,
+                                                     ctypes.c_void_p(stream.cuda_stream)))
 
     def amplitude(self, S, T) -> complex:
         S, T = _i32(S), _i32(T)
