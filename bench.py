@@ -76,8 +76,17 @@ def main():
     counts = circ.path_counts(wl.S, wl.Ts)
     paths_per_step = float(counts.sum())
 
-    ms, per_step, s_work, amps = measure(lofp, circ, wl, T, out, stream, method, args.fwd_layer, args.bwd_layer,
-                                         args.steps, args.warmup)
+    eager_ms, per_step, s_work, amps = measure(lofp, circ, wl, T, out, stream, method, args.fwd_layer,
+                                               args.bwd_layer, args.steps, args.warmup)
+    # the production form: the call tuned once and captured as a graph, each
+    # step one replay of the whole call (contraction only; the path sum sizes
+    # its frontiers on the host)
+    graph = None
+    if method != lofp.METHOD_PATHSUM and s_work["method_used"] == lofp.METHOD_CONTRACT:
+        graph = measure_graph(lofp, circ, wl, T, out, stream, args.steps, args.warmup)
+    ms = graph["ms_per_step"] if graph else eager_ms
+    if graph:
+        amps = graph["produced"]
 
     # parity on a sample (oracle = plain definition, CPU)
     import oracle
@@ -116,7 +125,13 @@ def main():
         "dfs_levels": s0["dfs_levels"],
         "dfs_leaves_per_step": leaves,
         "dfs_edges_per_step": edges,
+        "eager_ms_per_step": eager_ms,
     }
+    if graph:
+        res["config"]["form"] = "graph replay of the tuned call"
+        res["graph"] = {k: v for k, v in graph.items() if k != "produced"}
+    else:
+        res["config"]["form"] = "eager call"
 
     # roofline of the dominant kernel, from HIP events on the launch stream
     used = s0["method_used"]
@@ -126,8 +141,14 @@ def main():
         res["roofline"] = contract_roofline(kname, avg("ms_contract"), s0["transitions"])
         res["split_keys"] = [s0["split_top_keys"], s0["split_bottom_keys"]]
         res["max_state"] = s0["max_state"]
+        # evaluated work beside the represented paths: transitions per second
+        # of the whole step and of the contraction kernel
+        res["transitions_per_step"] = s0["transitions"]
+        res["transitions_per_s"] = s0["transitions"] / (ms * 1e-3)
     else:
         res["roofline"] = pathsum_roofline(s0, avg)
+        res["leaves_per_s"] = leaves / (ms * 1e-3)
+        res["edges_per_s"] = edges / (ms * 1e-3)
     if args.calib_copy_mib > 0:
         nb = args.calib_copy_mib * (1 << 20)
         xa = torch.ones(nb // 4, dtype=torch.float32, device=dev)
@@ -139,6 +160,8 @@ def main():
 
     if not args.no_latency:
         res["latency_single_ms"] = single_latency(circ, wl, T, out, method, stream, torch, lofp)
+        if graph:
+            res["latency_single_graph_ms"] = single_latency_graph(circ, wl, T, stream, torch, lofp)
     if not args.no_variants:
         res["variants"] = variants(lofp, workloads, torch, dev, stream)
 
@@ -159,6 +182,65 @@ def single_latency(circ, wl, T, out, method, stream, torch, lofp):
         lat.append((time.perf_counter() - a) * 1e3)
     lat = np.array(lat[10:])
     return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}
+
+
+def single_latency_graph(circ, wl, T, stream, torch, lofp):
+    """Latency of one pattern through a captured call (p50/p99 over 50
+    replays, new pattern copied into the captured buffer each time)."""
+    T1 = T[:1].clone()
+    o1 = torch.zeros(1, dtype=torch.complex128, device=T.device)
+    g = lofp.Graph(circ, wl.S, T1, o1, lofp.make_opts(method=lofp.METHOD_CONTRACT))
+    lat = []
+    try:
+        for i in range(60):
+            T1.copy_(T[i:i + 1])
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            g.launch(stream)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - a) * 1e3)
+    finally:
+        g.close()
+    lat = np.array(lat[10:])
+    return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}
+
+
+def measure_graph(lofp, circ, wl, T, out, stream, steps, warmup):
+    """The tuned call captured as a graph: `steps` replays timed after
+    `warmup`; the tuned choice and the eager tuned call's time beside it."""
+    import torch
+
+    opts = lofp.make_opts(method=lofp.METHOD_CONTRACT, autotune=True)
+    st = lofp.Stats()
+    circ.amplitudes_device(wl.S, T, out, opts, stream=stream, stats=st)   # tunes (first call)
+    for _ in range(warmup):
+        circ.amplitudes_device(wl.S, T, out, opts, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        circ.amplitudes_device(wl.S, T, out, opts, stream=stream)
+    torch.cuda.synchronize()
+    eager_tuned = (time.perf_counter() - t0) * 1e3 / steps
+    timed = lofp.make_opts(method=lofp.METHOD_CONTRACT, autotune=True, record_timing=True)
+    st = lofp.Stats()
+    circ.amplitudes_device(wl.S, T, out, timed, stream=stream, stats=st)
+    g = lofp.Graph(circ, wl.S, T, out, opts)
+    try:
+        for _ in range(warmup):
+            g.launch(stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.launch(stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        produced = out.cpu().numpy()
+    finally:
+        g.close()
+    return {"ms_per_step": ms, "eager_tuned_ms_per_step": eager_tuned, "tuned_split_cut": st.split_cut,
+            "tuned_lds_kb": st.lds_kb, "tuned_split": bool(st.split_top_keys > 0),
+            "tuned_phases_ms": {"ms_plan": st.ms_plan, "ms_contract": st.ms_contract, "ms_join": st.ms_reduce},
+            "produced": produced}
 
 
 def traffic_for(kernel: str):
@@ -237,20 +319,28 @@ def run_variant(lofp, workloads, torch, dev, stream, name, method, steps=5, fwd=
     circ = lofp.Circuit(wl.m, wl.layers)
     T = torch.from_numpy(wl.Ts).to(dev)
     o = torch.zeros(wl.batch, dtype=torch.complex128, device=dev)
-    ms, sts, s0, _ = measure(lofp, circ, wl, T, o, stream, method, fwd, bwd, steps, 2)
+    ms, sts, s0, produced = measure(lofp, circ, wl, T, o, stream, method, fwd, bwd, steps, 2)
     paths = float(circ.path_counts(wl.S, wl.Ts).sum())
+    import oracle
+    idx = np.random.default_rng(2).choice(wl.batch, min(64, wl.batch), replace=False)
+    ref, _ = oracle.amplitudes(wl.m, wl.S, wl.Ts[idx], wl.flat_circuit(), nthreads=host_threads())
     avg = lambda k: float(np.mean([s[k] for s in sts]))
     out = {"workload": wl.note, "batch": wl.batch, "ms_per_step": ms, "amplitudes_per_s": wl.batch / (ms * 1e-3),
            "paths_per_s": paths / (ms * 1e-3),
+           "max_abs_err_vs_oracle_sample": float(np.abs(produced[idx] - ref).max()),
            "phases_ms": {k: avg(k) for k in ("ms_plan", "ms_forward", "ms_backward", "ms_dfs", "ms_reduce",
                                              "ms_contract", "ms_total")}}
     if method == lofp.METHOD_CONTRACT:
         out["transitions"] = s0["transitions"]
+        out["transitions_per_s"] = s0["transitions"] / (ms * 1e-3)
         kname = "k_contract_multi" if s0["split_top_keys"] > 0 else "k_contract"
         out["roofline"] = contract_roofline(kname, avg("ms_contract"), s0["transitions"])
     else:
         out.update({k: s0[k] for k in ("fwd_layer", "bwd_layer", "dfs_levels", "frontier_states",
                                         "backward_states", "bfs_states", "dfs_leaves", "dfs_edges")})
+        out["leaves_per_s"] = s0["dfs_leaves"] / (ms * 1e-3)
+        out["edges_per_s"] = s0["dfs_edges"] / (ms * 1e-3)
+        out["bfs_states_per_s"] = s0["bfs_states"] / (ms * 1e-3)
         out["roofline"] = pathsum_roofline(s0, avg)
     return out
 
@@ -265,7 +355,39 @@ def variants(lofp, workloads, torch, dev, stream):
             "contract_c1": run_variant(lofp, workloads, torch, dev, stream, "c1", lofp.METHOD_CONTRACT, steps=50),
             "contract_c3": run_variant(lofp, workloads, torch, dev, stream, "c3", lofp.METHOD_CONTRACT, steps=20),
             "contract_c5": run_variant(lofp, workloads, torch, dev, stream, "c5", lofp.METHOD_CONTRACT, steps=20),
+            "contract_c5_multi": c5_multi_variant(lofp, workloads, torch),
             "served_c4": serve_variant(lofp, workloads)}
+
+
+def c5_multi_variant(lofp, workloads, torch, R=64, steps=5):
+    """The 32-mode, depth-6 workload as R independent circuits (seeds 0..R-1)
+    x 512 patterns each, all in one multi-circuit launch (one contraction job
+    per pattern, every job with its own circuit's tables): the device time of
+    that launch from HIP events, and its FP64 rate from the transitions the
+    same jobs make (counted by single-circuit calls of the per-pattern
+    contraction, 32 patterns at a time)."""
+    wls = [workloads.make("c5", seed=r) for r in range(R)]
+    circs = [lofp.Circuit(w.m, w.layers) for w in wls]
+    items = [(c, w.S, T) for c, w in zip(circs, wls) for T in w.Ts]
+    lofp.amplitudes_multi(items[:64])   # set-up of every circuit's tables is not timed below
+    lofp.amplitudes_multi(items)
+    ms = []
+    for _ in range(steps):
+        st = lofp.Stats()
+        lofp.amplitudes_multi(items, lofp.make_opts(record_timing=True), st)
+        ms.append(st.ms_contract)
+    ms_k = float(np.median(ms))
+    trans = 0
+    for c, w in zip(circs[:8], wls[:8]):
+        for i in range(0, w.batch, 32):
+            st = lofp.Stats()
+            c.amplitudes(w.S, w.Ts[i:i + 32], lofp.make_opts(method=lofp.METHOD_CONTRACT, count_work=True), st)
+            trans += st.transitions
+    trans_all = trans * R / 8.0   # counted on 8 of the R circuits, scaled
+    rl = contract_roofline("k_contract_multi (multi-circuit)", ms_k, trans_all)
+    return {"circuits": R, "patterns_per_circuit": wls[0].batch, "jobs": len(items), "device_ms": ms_k,
+            "amplitudes_per_s": len(items) / (ms_k * 1e-3), "transitions_est": trans_all,
+            "transitions_counted_on_circuits": 8, "roofline": rl}
 
 
 def _serve(lofp, reqs, circs, precision, rate_hz=0.0, n_warm=0):

@@ -10,8 +10,9 @@
  *
  * Conventions (all calls):
  *   - Modes are numbered 0..m-1 from the top of the circuit.
- *   - A beam splitter acts on the adjacent modes (a, a+1); mode a is its upper
- *     port (index 1 in Eq. (bs_matrix)), theta and phi are the two angles of
+ *   - A beam splitter acts on two modes a < b, usually adjacent (b = a + 1);
+ *     mode a is its upper port (index 1 in Eq. (bs_matrix)), theta and phi
+ *     are the two angles of
  *     Eq. (bs_matrix): [[cos t, -e^{-i p} sin t], [e^{i p} sin t, cos t]],
  *     rows = output ports, columns = input ports.
  *   - Layers are applied in the order given; inside a layer beam splitters
@@ -26,7 +27,7 @@
  *     not depend on the other patterns of the batch.
  *
  * Limits: m <= 32 modes and total photon number n <= 64 (LOFP_ENOTSUP
- * otherwise).  Non-adjacent pairs are rejected with LOFP_ENOTSUP.
+ * otherwise).
  */
 #ifndef LOFP_H
 #define LOFP_H
@@ -46,7 +47,7 @@ typedef enum {
     LOFP_EDEVICE = 4   /* HIP runtime error (message names the call)        */
 } lofp_status;
 
-/* One beam splitter, Eq. (bs_matrix).  b must equal a + 1. */
+/* One beam splitter, Eq. (bs_matrix), on modes a < b. */
 typedef struct {
     int32_t a, b;
     double theta, phi;
@@ -101,6 +102,15 @@ typedef struct {
     double fp32_rtol;         /* multi-circuit FP32 form: a result whose
                                  rounding bound exceeds fp32_rtol * |amp| is
                                  recomputed in FP64 (0 = 1e-6)               */
+    int32_t autotune;         /* contraction of a batch of >= 64 patterns: 1 =
+                                 on the first call for this circuit, S and
+                                 batch size, time the candidate ways to
+                                 contract it (split cut, LDS per job, split
+                                 or one job per pattern) on the device and
+                                 keep the fastest for later calls with
+                                 autotune = 1 (that first call synchronises
+                                 the stream); 0 = the default way          */
+    int32_t reserved;
 } lofp_opts;
 
 /* Per-call statistics (filled when a non-null pointer is passed). */
@@ -129,6 +139,9 @@ typedef struct {
     int32_t split_top_keys;   /* contraction split across the batch: distinct  */
     int32_t split_bottom_keys;/*   top / bottom halves of T (0 if not split)   */
     int32_t max_state;        /* contraction: entries of the largest state     */
+    int32_t split_cut;        /* split contraction: the top half's last cut    */
+    int32_t lds_kb;           /*   LDS per job (KiB)                           */
+    int32_t tuned;            /* 1 if the way of contracting came from the tuner */
 } lofp_stats;
 
 /* Message for the last non-OK status on this thread ("" if none). */
@@ -141,8 +154,18 @@ const char *lofp_version(void);
  * splitters, stored consecutively in bs (host memory, copied).
  * Sec. II: the interferometer is a list of layers of two-mode beam splitters
  * with parameters (theta, phi).  Does not touch the GPU.
+ * Distant pairs (b > a + 1; Sec. II.A allows connections between distant
+ * modes) are compiled exactly to adjacent splitters: mode b is brought next
+ * to a by exact swaps (theta = -pi/2, phi = 0, tables built with
+ * cos theta = 0) on (b-1, b), ..., (a+1, a+2), the splitter acts on
+ * (a, a+1), and the chain is undone by the inverse swaps (theta = pi/2) in
+ * reverse order; every Fock amplitude is that of the given circuit (up to
+ * rounding), and the light-cone bounds follow the compiled layers.  The
+ * host queries of layers and cuts (lofp_light_cone, lofp_bounds,
+ * lofp_bounds_batch) and lofp_path_counts return ENOTSUP for such circuits.
  * Errors: EINVAL for m < 2, negative lengths, a or b out of range, a >= b,
- * or a mode used twice in one layer; ENOTSUP for b != a + 1 or m > 32. */
+ * or a mode used twice in one layer; ENOTSUP for m > 32 or more than 250
+ * layers after compiling distant pairs. */
 lofp_status lofp_circuit_create(int32_t m, int32_t n_layers, const int32_t *layer_len,
                                 const lofp_bs *bs, lofp_circuit *out);
 
@@ -216,6 +239,27 @@ lofp_status lofp_amplitudes_device_noalloc(lofp_circuit c, const int32_t *S, int
                                            const int32_t *T_dev, lofp_c128 *out_dev,
                                            const lofp_opts *opts, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * One amplitude call captured as a HIP graph (batching: a batch evaluated
+ * again and again pays the host planning and the kernel launches once).
+ * lofp_graph_create makes one ordinary call of lofp_amplitudes_device (the
+ * contraction; opts may ask for autotune) on a private copy of the circuit,
+ * then captures a second call into a graph; the graph reads T_dev and writes
+ * out_dev (device buffers the caller keeps alive and in place) each time it
+ * is launched, with S and the batch size fixed.  The copy owns the graph's
+ * workspace, so later calls on c do not disturb it.  Synchronises at
+ * creation.  Errors: EINVAL for null arguments or batch < 1; ENOTSUP for the
+ * path-sum method, batch > 32768, or a workload whose call needs a host
+ * read-back (a contraction state above 2^20 entries in the split form, or
+ * above 2^22 / beyond 1 GiB of workspace per pattern). */
+typedef struct lofp_graph_s *lofp_graph;
+lofp_status lofp_graph_create(lofp_circuit c, const int32_t *S, int32_t batch, const int32_t *T_dev,
+                              lofp_c128 *out_dev, const lofp_opts *opts, lofp_graph *out);
+/* Launch the captured call on `stream` (hipStream_t; NULL = default).
+ * Launches on one graph must not overlap (they share its workspace). */
+lofp_status lofp_graph_launch(lofp_graph g, void *stream);
+lofp_status lofp_graph_destroy(lofp_graph g);
+
 /* Host-memory form of lofp_amplitudes_device: T is host int32[batch*m], out
  * host lofp_c128[batch].
  * Copies in and out and synchronises; for convenience, not for timing. */
@@ -224,6 +268,27 @@ lofp_status lofp_amplitudes(lofp_circuit c, const int32_t *S, int32_t batch, con
 
 /* One amplitude, host memory, default options. */
 lofp_status lofp_amplitude(lofp_circuit c, const int32_t *S, const int32_t *T, lofp_c128 *out);
+
+/* Every output amplitude of one input (Sec. IV names computing all output
+ * amplitudes as an extension): the C(m+n-1, n) patterns T with
+ * sum(T) = sum(S), in decreasing lexicographic order of (t_0, ..., t_{m-1})
+ * (the first puts every photon in mode 0, the last in mode m-1), each with
+ * <T|U_P|S> computed on the device by lofp_amplitudes_device (opts may be
+ * NULL) in passes of 32768 patterns.  T_out: host int32[capacity*m];
+ * amp_out: host lofp_c128[capacity]; *count receives the number of
+ * patterns.  With both outputs NULL only *count is set.  Synchronises the
+ * default stream.  Errors: EINVAL for a null count, one output NULL, or a
+ * capacity below the count; ENOTSUP above 2^31 patterns. */
+lofp_status lofp_all_outputs(lofp_circuit c, const int32_t *S, int64_t capacity, int32_t *T_out,
+                             lofp_c128 *amp_out, int64_t *count, const lofp_opts *opts);
+
+/* The circuit the library evaluates, host only: each splitter on distant
+ * modes (a, b) is compiled to adjacent ones (see lofp_circuit_create).
+ * *n_layers receives the compiled depth; with layer_len (int32[depth]) and
+ * bs (lofp_bs[capacity]) both non-NULL, the compiled layers are written
+ * (EINVAL if capacity is below the compiled splitter count). */
+lofp_status lofp_circuit_compiled(lofp_circuit c, int32_t *n_layers, int32_t *layer_len, lofp_bs *bs,
+                                  int32_t capacity);
 
 /* Number of valid paths of Eq. (1) for each pattern (conservation-valid
  * sequences of intermediate configurations from S to T_i, counted on the
@@ -290,14 +355,18 @@ typedef struct {
     double mean_batch;      /* requests per launch                            */
     double p50_ms, p99_ms, max_ms;   /* submit-to-completion latency          */
     int64_t fp64_fallbacks; /* FP32 results recomputed in FP64                */
+    int64_t pathsum_fallbacks; /* requests the contraction refused (program or
+                               state too large), summed by the path-sum form
+                               on a planner thread instead                 */
 } lofp_server_stats;
 
 /* Start a server on the current device (opts may be NULL). */
 lofp_status lofp_server_create(const lofp_server_opts *opts, lofp_server *out);
 /* Queue one request (S, T: host int32[m], copied); *ticket identifies it.
  * Lengths and occupations are checked here (EINVAL); the request is planned
- * on the server's thread, so ENOTSUP / ENOMEM for it come from
- * lofp_server_result. */
+ * on the server's thread.  A request the contraction cannot take is summed
+ * by the path-sum form instead (counted in pathsum_fallbacks); if that fails
+ * too, its error (ENOMEM) comes from lofp_server_result. */
 lofp_status lofp_server_submit(lofp_server s, lofp_circuit c, const int32_t *S, const int32_t *T,
                                uint64_t *ticket);
 /* *done = 1 and out / latency_ms / err_bound filled (any may be NULL) once

@@ -210,6 +210,10 @@ lofp_status init_circuits(const std::vector<std::pair<lofp_circuit_s *, int>> &l
             if (P.consts) {
                 std::vector<double> th(c.G), ph(c.G);
                 for (int g = 0; g < c.G; ++g) { th[g] = c.gates[g].theta; ph[g] = c.gates[g].phi; }
+                // exact mode swaps of compiled distant pairs: theta NaN marks
+                // them for the table kernel, phi carries the sign of sin theta
+                for (int g = 0; g < c.G; ++g)
+                    if (c.gate_swap[g]) { th[g] = std::nan(""); ph[g] = c.gate_swap[g] == 1 ? -1.0 : 1.0; }
                 stage(h, 0, dev_base, th, c.d_theta);
                 stage(h, 0, dev_base, ph, c.d_phi);
                 stage(h, 0, dev_base, c.fr_lo, c.d_fr_lo);
@@ -551,22 +555,42 @@ lofp_status ready_on_stream(lofp_circuit_s &c, hipStream_t s)
 
 lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
                                lofp_c128 *out_dev, int fp32, hipStream_t s, lofp_stats *st, bool count_work,
-                               int state_limit, Timer &tm, bool &used, bool &bounds_done);
+                               int state_limit, const SplitCfg &cfg, Timer &tm, bool &used, bool &bounds_done);
+
+// The default split: the middle cut, 52 KiB of LDS per job (three jobs per
+// CU), batches of 256 to 1024 patterns split without shared halves.
+SplitCfg default_split_cfg(const lofp_circuit_s &c)
+{
+    SplitCfg k;
+    k.rs = (c.nc - 1) / 2;
+    return k;
+}
+
+lofp_status run_contract_split_dev(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
+                                   lofp_c128 *out_dev, int fp32, hipStream_t s, lofp_stats *st, bool count_work,
+                                   int state_limit, const SplitCfg &cfg, Timer &tm, bool &used);
 
 // state_limit > 0: no state buffer holds more entries (a result whose state
 // would is NaN; ENOMEM when statistics are read back).
 lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
                          lofp_c128 *out_dev, int count_only, int fp32, hipStream_t s, lofp_stats *st,
-                         bool count_work, int state_limit, Timer &tm, bool allow_split = true)
+                         bool count_work, int state_limit, Timer &tm, bool allow_split = true,
+                         const SplitCfg *cfg_in = nullptr)
 {
     lofp_status rc = prepare_program(c, s);
     if (rc != LOFP_OK) return rc;
     rc = ready_on_stream(c, s);
     if (rc != LOFP_OK) return rc;
     bool bounds_done = false;
-    if (!count_only && allow_split && B >= 64) {
+    const SplitCfg cfg = cfg_in ? *cfg_in : default_split_cfg(c);
+    if (!count_only && allow_split && B >= 64 && cfg.mode != SplitCfg::kPerPattern) {
         bool used = false;
-        rc = run_contract_split(c, S, n, B, T_dev, out_dev, fp32, s, st, count_work, state_limit, tm, used, bounds_done);
+        if (cfg.mode == SplitCfg::kDevice) {
+            rc = run_contract_split_dev(c, S, n, B, T_dev, out_dev, fp32, s, st, count_work, state_limit, cfg, tm, used);
+            if (rc != LOFP_OK || used) return rc;
+        }
+        rc = run_contract_split(c, S, n, B, T_dev, out_dev, fp32, s, st, count_work, state_limit, cfg, tm, used,
+                                bounds_done);
         if (rc != LOFP_OK || used) return rc;
     }
     if (!bounds_done) {
@@ -575,7 +599,7 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
         if (rc != LOFP_OK) return rc;
     }
     unsigned long long *ctr = c.d_counters.as<unsigned long long>();
-    HIPCHK(hipMemsetAsync(ctr, 0, 8 * sizeof(unsigned long long), s));
+    HIPCHK(launch_fill_i32(reinterpret_cast<int32_t *>(ctr), 16, 0, s));   // a kernel: the call may be captured
     ContractArgs a{};
     a.B = B; a.m = c.m; a.n = n; a.D = c.D;
     a.S = c.d_S.as<int32_t>();
@@ -601,7 +625,12 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
     const int64_t max_states = c.sb_prog;
     a.max_states = (int)std::min<int64_t>(max_states, 1 << 22);
     a.ws = nullptr;
-    if (max_states > (1 << 22) || contract_lds_bytes(a, true) > 64 * 1024) {
+    if (max_states <= (1 << 22) && contract_lds_bytes(a, true) > 64 * 1024 &&
+        (size_t)B * 2 * a.max_states * sizeof(double2) <= ((size_t)1 << 30)) {
+        // a workspace sized by the S-side bound (no read-back)
+        HIPCHK(ensure(c.d_ws, (size_t)B * 2 * a.max_states * sizeof(double2)));
+        a.ws = c.d_ws.as<double2>();
+    } else if (max_states > (1 << 22) || contract_lds_bytes(a, true) > 64 * 1024) {
         int *d_max = reinterpret_cast<int32_t *>(ctr + 5);
         HIPCHK(launch_contract_sizes(a, d_max, s));
         int mx = 0;
@@ -636,18 +665,17 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
 // halves over the crossing versions.  The grouping runs on the device; the
 // host reads back the key claim counts (one synchronisation) to size the
 // launch.
-// Batch sizes that take the split without sharing, for parallelism.
-constexpr int kSplitSmallMin = 256, kSplitSmallMax = 1024;
 
 lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
                                lofp_c128 *out_dev, int fp32, hipStream_t s, lofp_stats *st, bool count_work,
-                               int state_limit, Timer &tm, bool &used, bool &bounds_done)
+                               int state_limit, const SplitCfg &cfg, Timer &tm, bool &used, bool &bounds_done)
 {
     used = false;
     bounds_done = false;
     const int m = c.m, nc = c.nc, span = (c.D + 1) * nc;
     if (nc < 4 || c.D < 2) return LOFP_OK;
-    const int rs = (nc - 1) / 2;
+    const int rs = cfg.rs;
+    if (rs < 0 || rs > nc - 2) return LOFP_OK;
     SplitProgram *sp = get_split(c, rs);
     if (!sp->top.error.empty() || !sp->bot.error.empty()) return LOFP_OK;
     if (!sp->on_device) {
@@ -671,7 +699,7 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     HIPCHK(ensure(c.d_kslot, (size_t)2 * B * sizeof(int)));
     HIPCHK(ensure(c.d_kof, kl.slot_key_bytes));
     HIPCHK(ensure(c.d_krep, (size_t)2 * kKeySubs * B * sizeof(int)));
-    HIPCHK(ensure(c.d_kcnt, 2 * kKeySubs * sizeof(int)));
+    HIPCHK(ensure(c.d_kcnt, (2 * kKeySubs + 4) * sizeof(int)));   // as the device-decided form lays it out
     HIPCHK(ensure(c.d_khull, kl.hull_bytes));
     HIPCHK(ensure(c.d_klohi, (size_t)2 * 2 * B * span * sizeof(int16_t)));
     KeyArgs ka{};
@@ -708,7 +736,7 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     // would leave most of the GPU idle (up to four 64-lane jobs per CU): the
     // two halves then run side by side at half the steps each.
     const bool shared = (int64_t)(ntop + nbot) * 4 <= (int64_t)B * 3;
-    const bool small = B >= kSplitSmallMin && B <= kSplitSmallMax;
+    const bool small = B >= cfg.small_min && B <= cfg.small_max;
     if (!shared && !small) {
         // little sharing: contract per pattern (the bounds are in place)
         HIPCHK(launch_key_reset(ka, ntop, nbot, s));
@@ -763,7 +791,7 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     // LDS budget of a job (a few jobs per CU), of which what the descriptors
     // and interval arrays leave holds the two state buffers; a job whose own
     // largest state does not fit keeps them in its workspace slice
-    const size_t lds_job = std::min<size_t>(max_lds_per_block(), (size_t)LOFP_SPLIT_LDS_KB * 1024);
+    const size_t lds_job = std::min<size_t>(max_lds_per_block(), (size_t)cfg.lds_kb * 1024);
     const size_t lds_fixed = contract_job_lds_bytes(c.nvars, m, 0, true);
     const int64_t room = lds_job > lds_fixed ? (int64_t)((lds_job - lds_fixed) / (2 * sizeof(double2))) : 0;
     const int lds_states = (int)std::min<int64_t>(mx, room);
@@ -808,10 +836,261 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
         if (h[4]) return fail(LOFP_ENOMEM, "contraction workspace overflow");
         st->transitions = (int64_t)h[3];
         st->max_state = mx;
+        st->split_cut = rs;
+        st->lds_kb = cfg.lds_kb;
         st->split_top_keys = ntop;
         st->split_bottom_keys = nbot;
     }
     return LOFP_OK;
+}
+
+// The split contraction with every launch sized for the worst case and the
+// split decided on the device (launch_key_jobs_dev): no host read-back and no
+// memset, so the call can be captured in a graph.  Sizes come from the
+// S-side intervals only (they contain every pattern's).  The per-pattern
+// contraction is launched too and runs only when the device did not split.
+// Leaves used = false, with nothing enqueued, where those sizes are too
+// large (the host-sized form then runs).
+lofp_status run_contract_split_dev(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
+                                   lofp_c128 *out_dev, int fp32, hipStream_t s, lofp_stats *st, bool count_work,
+                                   int state_limit, const SplitCfg &cfg, Timer &tm, bool &used)
+{
+    used = false;
+    const int m = c.m, nc = c.nc, span = (c.D + 1) * nc;
+    if (nc < 4 || c.D < 2) return LOFP_OK;
+    const int rs = cfg.rs;
+    if (rs < 0 || rs > nc - 2) return LOFP_OK;
+    SplitProgram *sp = get_split(c, rs);
+    if (!sp->top.error.empty() || !sp->bot.error.empty()) return LOFP_OK;
+    s_only_cached(c, S, n);
+    auto sit = c.sb_split.find(rs);
+    if (sit == c.sb_split.end())
+        sit = c.sb_split.emplace(rs, std::max(steps_state_bound(c, sp->top.steps, c.sb_lo, c.sb_hi),
+                                              steps_state_bound(c, sp->bot.steps, c.sb_lo, c.sb_hi))).first;
+    const int64_t cap_s = sit->second;
+    if (cap_s > (1 << 20)) return LOFP_OK;
+    if (c.sb_prog < 0) c.sb_prog = program_state_bound(c, c.sb_lo, c.sb_hi);
+    if (c.sb_prog > (1 << 22)) return LOFP_OK;
+    // the final state of a half: its crossing versions over their S-side ranges
+    int64_t fin = 1;
+    for (int v : sp->top.live_out) {
+        const size_t i = (size_t)c.var_time[v] * nc + c.var_cut[v];
+        fin *= std::max(1, c.sb_hi[i] - c.sb_lo[i] + 1);
+    }
+    int mx = (int)std::max<int64_t>(cap_s, 1);
+    int fin_cap = (int)std::max<int64_t>(std::min<int64_t>(fin, cap_s), 1);
+    int pp_states = (int)std::max<int64_t>(c.sb_prog, 1);
+    if (state_limit > 0) {
+        mx = std::min(mx, state_limit);
+        fin_cap = std::min(fin_cap, state_limit);
+        pp_states = std::min(pp_states, state_limit);
+    }
+    // the per-pattern contraction (runs only if the device does not split)
+    ContractArgs pa{};
+    pa.B = B; pa.m = m; pa.n = n; pa.D = c.D;
+    pa.nvars = c.nvars;
+    pa.max_states = pp_states;
+    const bool pp_lds = contract_lds_bytes(pa, true) <= 64 * 1024;
+    const size_t pp_ws = pp_lds ? 0 : (size_t)B * 2 * pp_states * sizeof(double2);
+    if (pp_ws > ((size_t)1 << 30)) return LOFP_OK;
+    used = true;
+    if (!sp->on_device) {
+        HIPCHK(upload(sp->d_top, sp->top.steps, s));
+        HIPCHK(upload(sp->d_bot, sp->bot.steps, s));
+        sp->on_device = true;
+    }
+    tm.mark();
+    lofp_status rc = run_bounds(c, B, n, T_dev, s);
+    if (rc != LOFP_OK) return rc;
+    int cap = 1;
+    while (cap < 4 * B) cap <<= 1;
+    const KeyLayoutPlan kl = plan_key_layout(c.klay, cap, span);
+    HIPCHK(ensure(c.d_ktab, kl.table_bytes));
+    HIPCHK(ensure(c.d_kslot, (size_t)2 * B * sizeof(int)));
+    HIPCHK(ensure(c.d_kof, kl.slot_key_bytes));
+    HIPCHK(ensure(c.d_krep, (size_t)2 * kKeySubs * B * sizeof(int)));
+    HIPCHK(ensure(c.d_kcnt, (2 * kKeySubs + 4) * sizeof(int)));   // claim counts, then the decision words
+    HIPCHK(ensure(c.d_khull, kl.hull_bytes));
+    HIPCHK(ensure(c.d_klohi, (size_t)2 * 2 * B * span * sizeof(int16_t)));
+    HIPCHK(ensure(c.d_korder, (size_t)2 * 2 * B * sizeof(int)));
+    HIPCHK(ensure(c.d_jobs, (size_t)2 * B * sizeof(ContractJob)));
+    HIPCHK(ensure(c.d_kinf, (size_t)4 * B * sizeof(int32_t)));
+    HIPCHK(ensure(c.d_kstate, (size_t)2 * B * fin_cap * sizeof(double2)));
+    KeyArgs ka{};
+    ka.B = B; ka.m = m; ka.n = n; ka.rs = rs; ka.cap = cap; ka.span = span; ka.stride = kl.stride;
+    ka.T = T_dev;
+    ka.lo = c.d_lo.as<int16_t>(); ka.hi = c.d_hi.as<int16_t>();
+    ka.infeasible = c.d_inf.as<int32_t>();
+    ka.table = c.d_ktab.as<unsigned long long>(); ka.slot = c.d_kslot.as<int>();
+    ka.slot_key = c.d_kof.as<int>(); ka.key_slot = c.d_krep.as<int>(); ka.count = c.d_kcnt.as<int>();
+    ka.hlo = c.d_khull.as<int>(); ka.hhi = ka.hlo + key_hull_hi_offset(kl.stride, span);
+    ka.klo = c.d_klohi.as<int16_t>(); ka.khi = ka.klo + (size_t)2 * B * span;
+    ka.counters = c.d_counters.as<unsigned long long>();
+    ka.job_bucket = c.d_korder.as<int>();
+    ka.order = ka.job_bucket + 2 * B;
+    ka.ctl = ka.count + 2 * kKeySubs;
+    ka.small_min = cfg.small_min;
+    ka.small_max = cfg.small_max;
+    if (kl.clear) {
+        // fill kernels rather than memsets (the call may be captured)
+        const size_t rows = (size_t)2 * kl.stride;
+        HIPCHK(launch_fill_i32(reinterpret_cast<int32_t *>(ka.table), rows * 2, -1, s));
+        HIPCHK(launch_fill_i32(ka.hlo, rows * span, kHullEmptyLo, s));
+        HIPCHK(launch_fill_i32(ka.hhi, rows * span, kHullEmptyHi, s));
+        HIPCHK(launch_fill_i32(ka.count, 2 * kKeySubs, 0, s));
+    }
+    c.klay.clean = false;
+    HIPCHK(launch_keys(ka, s));
+    ContractJob tj{};
+    tj.m = m; tj.n = n; tj.D = c.D; tj.nvars = c.nvars; tj.tab_stride = c.tab_stride; tj.fp32 = fp32;
+    tj.var_cut = c.d_var_cut.as<int32_t>(); tj.var_time = c.d_var_time.as<int32_t>();
+    tj.table = c.d_table.as<double2>(); tj.S = c.d_S.as<int32_t>();
+    tj.stats = st != nullptr && count_work;
+    ContractJob bj = tj;
+    tj.nsteps = (int)sp->top.steps.size(); tj.steps = sp->d_top.as<ContractStep>();
+    bj.nsteps = (int)sp->bot.steps.size(); bj.steps = sp->d_bot.as<ContractStep>();
+    {
+        const std::vector<int> &tl = sp->top.live_out, &bl = sp->bot.live_out;
+        bj.out_remap = 1;
+        bj.out_pos = 0;
+        for (size_t q2 = 0; q2 < bl.size(); ++q2)
+            bj.out_pos |= (uint64_t)(std::find(tl.begin(), tl.end(), bl[q2]) - tl.begin()) << (4 * q2);
+    }
+    HIPCHK(launch_key_jobs_dev(ka, tj, bj, c.d_jobs.as<ContractJob>(), c.d_kinf.as<int32_t>(),
+                               c.d_kstate.as<double2>(), fin_cap, s));
+    c.klay.clean = true;
+    unsigned long long *ctr = c.d_counters.as<unsigned long long>();   // zeroed by the jobs kernel
+    const size_t lds_job = std::min<size_t>(max_lds_per_block(), (size_t)cfg.lds_kb * 1024);
+    const size_t lds_fixed = contract_job_lds_bytes(c.nvars, m, 0, true);
+    const int64_t room = lds_job > lds_fixed ? (int64_t)((lds_job - lds_fixed) / (2 * sizeof(double2))) : 0;
+    const int lds_states = (int)std::min<int64_t>(mx, room);
+    const bool any_lds = lds_states > 0;
+    const size_t lds_bytes = contract_job_lds_bytes(c.nvars, m, any_lds ? lds_states : 0, any_lds);
+    MultiOverride ov{mx, nullptr, nullptr, fin_cap, lds_states, ka.order};
+    ov.njobs = ka.ctl + 1;
+    if (lds_states < mx) {
+        // jobs whose state does not fit LDS share a pool of workspace slices,
+        // one per job that can be resident
+        const int R = contract_multi_resident_blocks(lds_bytes, any_lds ? lds_states : mx);
+        HIPCHK(ensure(c.d_ws, (size_t)R * 2 * mx * sizeof(double2)));
+        const size_t before = c.d_wspool.cap;
+        HIPCHK(ensure(c.d_wspool, (size_t)R * sizeof(int)));
+        if (c.d_wspool.cap != before) HIPCHK(launch_fill_i32(c.d_wspool.as<int32_t>(), c.d_wspool.cap / sizeof(int), 0, s));
+        ov.ws_base = c.d_ws.as<double2>();
+        ov.ws_pool = c.d_wspool.as<int>();
+        ov.ws_slots = R;
+    }
+    tm.mark();
+    HIPCHK(launch_contract_multi(2 * B, c.d_jobs.as<ContractJob>(), lds_bytes, any_lds ? lds_states : mx, any_lds,
+                                 fp32 != 0, ctr + 3, reinterpret_cast<int32_t *>(ctr + 4), s, ov,
+                                 st != nullptr && count_work));
+    pa.S = c.d_S.as<int32_t>();
+    pa.T = T_dev;
+    pa.lo = c.d_lo.as<int16_t>(); pa.hi = c.d_hi.as<int16_t>();
+    pa.infeasible = c.d_inf.as<int32_t>();
+    pa.var_cut = c.d_var_cut.as<int32_t>();
+    pa.var_time = c.d_var_time.as<int32_t>();
+    pa.nsteps = (int)c.steps.size();
+    pa.steps = c.d_steps.as<ContractStep>();
+    pa.table = c.d_table.as<double2>(); pa.tab_stride = c.tab_stride;
+    pa.out = reinterpret_cast<double2 *>(out_dev);
+    pa.fp32 = fp32;
+    pa.stat_transitions = ctr + 3;
+    pa.overflow = reinterpret_cast<int32_t *>(ctr + 4);
+    pa.stats = st != nullptr && count_work;
+    pa.skip = ka.ctl;
+    if (!pp_lds) {
+        HIPCHK(ensure(c.d_ws2, pp_ws));
+        pa.ws = c.d_ws2.as<double2>();
+    }
+    HIPCHK(launch_contract(pa, s));
+    tm.mark();
+    JoinArgs ja{};
+    ja.B = B; ja.m = m; ja.n = n; ja.D = c.D;
+    ja.lo = c.d_lo.as<int16_t>(); ja.hi = c.d_hi.as<int16_t>();
+    ja.infeasible = c.d_inf.as<int32_t>();
+    ja.slot = ka.slot; ja.slot_key = ka.slot_key; ja.stride = kl.stride;
+    ja.tlo = ka.klo; ja.thi = ka.khi;
+    ja.blo = ka.klo + (size_t)B * span; ja.bhi = ka.khi + (size_t)B * span;
+    ja.nshared = (int)sp->top.live_out.size();
+    for (int q = 0; q < ja.nshared; ++q) {
+        const int v = sp->top.live_out[q];
+        ja.cidx[q] = c.var_time[v] * nc + c.var_cut[v];
+    }
+    ja.top_state = c.d_kstate.as<double2>();
+    ja.bot_state = ja.top_state + (size_t)B * fin_cap;
+    ja.state_cap = fin_cap;
+    ja.top_ovf = c.d_kinf.as<int32_t>() + 2 * (size_t)B;
+    ja.bot_ovf = ja.top_ovf + B;
+    ja.split_flag = ka.ctl;
+    ja.out = reinterpret_cast<double2 *>(out_dev);
+    HIPCHK(launch_join(ja, s));
+    tm.mark();
+    if (st) {
+        unsigned long long h[8];
+        int ctl[4];
+        HIPCHK(hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(ctl, ka.ctl, sizeof(ctl), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (h[4]) return fail(LOFP_ENOMEM, "contraction workspace overflow");
+        st->transitions = (int64_t)h[3];
+        st->max_state = ctl[0] ? mx : pp_states;
+        st->split_cut = ctl[0] ? rs : 0;
+        st->lds_kb = ctl[0] ? cfg.lds_kb : 0;
+        st->split_top_keys = ctl[0] ? ctl[2] : 0;
+        st->split_bottom_keys = ctl[0] ? ctl[3] : 0;
+    }
+    return LOFP_OK;
+}
+
+// The tuner: times each candidate way of contracting a batch sharing S (the
+// split cut one either side of the middle, 40 / 52 / 64 KiB of LDS per
+// split job, or one job per pattern) on the caller's data, three timed calls
+// after one untimed, and returns the one with the smallest median.  Every
+// candidate computes the same amplitudes (in another order of summation).
+lofp_status tune_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev, lofp_c128 *out_dev,
+                          int fp32, int state_limit, hipStream_t s, SplitCfg &best)
+{
+    std::vector<SplitCfg> cand;
+    const SplitCfg d = default_split_cfg(c);
+    for (int drs : {0, -1, 1})
+        for (int kb : {52, 40, 64}) {
+            SplitCfg k = d;
+            k.rs = d.rs + drs;
+            k.lds_kb = kb;
+            if (k.rs >= 0 && k.rs <= c.nc - 2) cand.push_back(k);
+        }
+    SplitCfg pp = d;
+    pp.mode = SplitCfg::kPerPattern;
+    cand.push_back(pp);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) { (void)hipEventDestroy(e0); return fail(LOFP_EDEVICE, hipGetErrorString(he)); }
+    double best_ms = 1e300;
+    lofp_status rc = LOFP_OK;
+    for (const SplitCfg &k : cand) {
+        Timer off;
+        rc = run_contract(c, S, n, B, T_dev, out_dev, 0, fp32, s, nullptr, false, state_limit, off, true, &k);
+        if (rc != LOFP_OK) break;
+        float t[3];
+        for (int r = 0; r < 3 && rc == LOFP_OK; ++r) {
+            he = hipEventRecord(e0, s);
+            if (he == hipSuccess) rc = run_contract(c, S, n, B, T_dev, out_dev, 0, fp32, s, nullptr, false, state_limit,
+                                                    off, true, &k);
+            if (rc != LOFP_OK) break;
+            if (he == hipSuccess) he = hipEventRecord(e1, s);
+            if (he == hipSuccess) he = hipEventSynchronize(e1);
+            if (he == hipSuccess) he = hipEventElapsedTime(&t[r], e0, e1);
+            if (he != hipSuccess) rc = fail(LOFP_EDEVICE, hipGetErrorString(he));
+        }
+        if (rc != LOFP_OK) break;
+        std::sort(t, t + 3);
+        if (t[1] < best_ms) { best_ms = t[1]; best = k; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }
 
 lofp_status run_pathsum(lofp_circuit_s &c, const int32_t *S, int n, int B, const int32_t *T_dev,
@@ -1092,6 +1371,23 @@ lofp_status run_pathsum(lofp_circuit_s &c, const int32_t *S, int n, int B, const
     return LOFP_OK;
 }
 
+lofp_status clone_circuit(const lofp_circuit_s &c, lofp_circuit_s **out)
+{
+    std::vector<int32_t> lens(std::max(c.D, 1), 0);
+    for (int l = 0; l < c.D; ++l) lens[l] = c.layer_start[l + 1] - c.layer_start[l];
+    lofp_circuit k = nullptr;
+    lofp_status rc = lofp_circuit_create(c.m, c.D, lens.data(), c.gates.empty() ? nullptr : c.gates.data(), &k);
+    if (rc != LOFP_OK) return rc;
+    // the compiled layers hold adjacent pairs only, so the gate order is c's
+    k->gate_swap = c.gate_swap;
+    k->user_gate = c.user_gate;
+    k->user_depth = c.user_depth;
+    k->compiled = c.compiled;
+    k->tuned = c.tuned;
+    *out = k;
+    return LOFP_OK;
+}
+
 }  // namespace host
 }  // namespace lofp
 
@@ -1118,38 +1414,94 @@ lofp_status lofp_circuit_create(int32_t m, int32_t n_layers, const int32_t *laye
         total += layer_len[l];
     }
     if (total > 0 && !bs) return fail(LOFP_EINVAL, "bs is null");
-    auto *c = new lofp_circuit_s();
-    c->m = m;
-    c->D = n_layers;
-    c->nc = m - 1;
-    c->cut_gate.assign((size_t)std::max(n_layers, 1) * c->nc, 0);
-    c->gate_at.assign((size_t)std::max(n_layers, 1) * c->nc, -1);
-    c->layer_start.assign(n_layers + 1, 0);
+    // Check the layers, then compile them to adjacent pairs.  A splitter on
+    // distant modes (a, b) (Sec. II.A allows distant connections) becomes
+    // the exact product P^-1 BS(a, a+1) P, where P moves mode b next to a by
+    // exact swaps [[0, 1], [-1, 0]] (theta = -pi/2, phi = 0) on (b-1, b),
+    // ..., (a+1, a+2) (each maps mode k+1 to +k and mode k to -(k+1)) and
+    // P^-1 is the chain of their inverses (theta = pi/2, phi = 0) in reverse
+    // order: on single-photon states it maps mode a to U11 a + U21 b and
+    // mode b to U12 a + U22 b and fixes every other mode, so every Fock
+    // amplitude is that of the original splitter.  The swaps' tables are
+    // built with cos theta = 0 exactly (a permutation with signs), so they
+    // add no path of nonzero weight.  The adjacent splitters of a layer stay
+    // one layer; each distant one adds its own layers after them (splitters
+    // of one layer commute).
+    std::vector<std::vector<lofp_bs>> ilayers;
+    std::vector<std::vector<uint8_t>> iswap;   // per internal splitter: 0, or 1 / 2 for a swap / its inverse
+    std::vector<int> user_gate;   // internal gate of each user splitter, in application order
+    bool compiled = false;
     int k = 0;
     for (int l = 0; l < n_layers; ++l) {
         std::vector<lofp_bs> layer(bs + k, bs + k + layer_len[l]);
         k += layer_len[l];
         std::vector<int> used(m, 0);
         for (const auto &b : layer) {
-            if (b.a < 0 || b.b < 0 || b.a >= m || b.b >= m || b.a >= b.b) {
-                delete c;
+            if (b.a < 0 || b.b < 0 || b.a >= m || b.b >= m || b.a >= b.b)
                 return fail(LOFP_EINVAL, "beam splitter modes out of range or a >= b");
-            }
-            if (used[b.a] || used[b.b]) {
-                delete c;
-                return fail(LOFP_EINVAL, "mode used twice in one layer");
-            }
+            if (used[b.a] || used[b.b]) return fail(LOFP_EINVAL, "mode used twice in one layer");
             used[b.a] = used[b.b] = 1;
-            if (b.b != b.a + 1) {
-                delete c;
-                return fail(LOFP_ENOTSUP, "only adjacent pairs (a, a+1) are supported");
+        }
+        std::vector<lofp_bs> adj;
+        std::vector<std::pair<int, lofp_bs>> far;   // (position in the layer, splitter)
+        for (size_t i = 0; i < layer.size(); ++i) {
+            if (layer[i].b == layer[i].a + 1) adj.push_back(layer[i]);
+            else far.emplace_back((int)i, layer[i]);
+        }
+        std::stable_sort(adj.begin(), adj.end(), [](const lofp_bs &x, const lofp_bs &y) { return x.a < y.a; });
+        // user gate order inside a layer is by upper mode, as the internal layer stores it
+        std::vector<lofp_bs> order = layer;
+        std::stable_sort(order.begin(), order.end(), [](const lofp_bs &x, const lofp_bs &y) { return x.a < y.a; });
+        int first = 0;
+        for (const auto &L : ilayers) first += (int)L.size();
+        std::map<int, int> gate_of_a;   // upper mode -> internal gate id
+        if (!adj.empty() || far.empty()) {
+            for (size_t i = 0; i < adj.size(); ++i) gate_of_a[adj[i].a] = first + (int)i;
+            first += (int)adj.size();
+            ilayers.push_back(adj);
+            iswap.push_back(std::vector<uint8_t>(adj.size(), 0));
+        }
+        std::stable_sort(far.begin(), far.end(),
+                         [](const std::pair<int, lofp_bs> &x, const std::pair<int, lofp_bs> &y) { return x.second.a < y.second.a; });
+        for (const auto &fb : far) {
+            compiled = true;
+            const lofp_bs &b = fb.second;
+            const double half_pi = 1.5707963267948966;
+            for (int q = b.b - 1; q >= b.a + 1; --q) {
+                ilayers.push_back({lofp_bs{q, q + 1, -half_pi, 0.0}});
+                iswap.push_back({1});
+                ++first;
+            }
+            ilayers.push_back({lofp_bs{b.a, b.a + 1, b.theta, b.phi}});
+            iswap.push_back({0});
+            gate_of_a[b.a] = first++;
+            for (int q = b.a + 1; q <= b.b - 1; ++q) {
+                ilayers.push_back({lofp_bs{q, q + 1, half_pi, 0.0}});
+                iswap.push_back({2});
+                ++first;
             }
         }
-        std::sort(layer.begin(), layer.end(), [](const lofp_bs &x, const lofp_bs &y) { return x.a < y.a; });
+        for (const auto &b : order) user_gate.push_back(gate_of_a[b.a]);
+    }
+    if (ilayers.size() > 250) return fail(LOFP_ENOTSUP, "more than 250 layers after compiling distant pairs");
+    const int D = (int)ilayers.size();
+    auto *c = new lofp_circuit_s();
+    c->m = m;
+    c->D = D;
+    c->nc = m - 1;
+    c->user_depth = n_layers;
+    c->compiled = compiled;
+    c->user_gate = user_gate;
+    c->cut_gate.assign((size_t)std::max(D, 1) * c->nc, 0);
+    c->gate_at.assign((size_t)std::max(D, 1) * c->nc, -1);
+    c->layer_start.assign(D + 1, 0);
+    for (int l = 0; l < D; ++l) {
         c->layer_start[l] = (int)c->gates.size();
-        for (const auto &b : layer) {
+        for (size_t i = 0; i < ilayers[l].size(); ++i) {
+            const lofp_bs &b = ilayers[l][i];
             const int g = (int)c->gates.size();
             c->gates.push_back(b);
+            c->gate_swap.push_back(iswap[l][i]);
             c->gate_cut.push_back(b.a);
             c->gate_layer.push_back(l);
             c->cut_gate[(size_t)l * c->nc + b.a] = 1;
@@ -1157,10 +1509,23 @@ lofp_status lofp_circuit_create(int32_t m, int32_t n_layers, const int32_t *laye
         }
     }
     c->G = (int)c->gates.size();
-    c->layer_start[n_layers] = c->G;
+    c->layer_start[D] = c->G;
     build_reach(*c);
     build_stage_maps(*c);
     *out = c;
+    return LOFP_OK;
+}
+
+lofp_status lofp_circuit_compiled(lofp_circuit c, int32_t *n_layers, int32_t *layer_len, lofp_bs *bs,
+                                  int32_t capacity)
+{
+    if (!c || !n_layers) return fail(LOFP_EINVAL, "null argument");
+    *n_layers = c->D;
+    if (!layer_len && !bs) return LOFP_OK;
+    if (!layer_len || !bs) return fail(LOFP_EINVAL, "layer_len and bs go together");
+    if (capacity < c->G) return fail(LOFP_EINVAL, "bs holds fewer than the compiled splitters");
+    for (int l = 0; l < c->D; ++l) layer_len[l] = c->layer_start[l + 1] - c->layer_start[l];
+    for (int g = 0; g < c->G; ++g) bs[g] = c->gates[g];
     return LOFP_OK;
 }
 
@@ -1173,7 +1538,7 @@ lofp_status lofp_circuit_destroy(lofp_circuit c)
                       &c->d_count, &c->d_slot_stage, &c->d_off, &c->d_coff, &c->d_fa, &c->d_fb, &c->d_ba, &c->d_bb,
                       &c->d_levels, &c->d_tab_mid, &c->d_counters, &c->d_T, &c->d_out, &c->d_ws,
                       &c->d_cfg, &c->d_rankb, &c->d_ktab, &c->d_kslot, &c->d_kof, &c->d_krep, &c->d_kcnt,
-                      &c->d_khull, &c->d_klohi, &c->d_kinf, &c->d_jobs, &c->d_kstate, &c->d_korder};
+                      &c->d_khull, &c->d_klohi, &c->d_kinf, &c->d_jobs, &c->d_kstate, &c->d_korder, &c->d_wspool, &c->d_ws2};
     // pooled blocks are reused at once, so no work of this circuit may be left
     if (c->dev_ready || !c->blocks.empty()) (void)hipDeviceSynchronize();
     for (DevBuf *b : bufs) release(*b);
@@ -1188,6 +1553,7 @@ lofp_status lofp_light_cone(lofp_circuit c, int32_t layer, int32_t mode, int32_t
                             int32_t *fut_lo, int32_t *fut_hi)
 {
     if (!c || !past_lo || !past_hi || !fut_lo || !fut_hi) return fail(LOFP_EINVAL, "null argument");
+    if (c->compiled) return fail(LOFP_ENOTSUP, "host queries of layers and cuts describe circuits of adjacent pairs only");
     if (layer < 0 || layer > c->D || mode < 0 || mode >= c->m) return fail(LOFP_EINVAL, "bad layer or mode");
     int lo = mode, hi = mode;
     for (int t = layer - 1; t >= 0; --t) reach_step(*c, t, lo, hi);
@@ -1204,6 +1570,7 @@ lofp_status lofp_bounds(lofp_circuit c, const int32_t *S, const int32_t *T, int3
                         int32_t *feasible)
 {
     if (!c || !T || !lo || !hi || !feasible) return fail(LOFP_EINVAL, "null argument");
+    if (c->compiled) return fail(LOFP_ENOTSUP, "host queries of layers and cuts describe circuits of adjacent pairs only");
     int n = 0;
     lofp_status rc = check_S(*c, S, n);
     if (rc != LOFP_OK) return rc;
@@ -1232,6 +1599,7 @@ lofp_status lofp_bounds_batch(lofp_circuit c, const int32_t *S, int32_t batch, c
                               int32_t *hi, int32_t *feasible)
 {
     if (!c) return fail(LOFP_EINVAL, "null circuit");
+    if (c->compiled) return fail(LOFP_ENOTSUP, "host queries of layers and cuts describe circuits of adjacent pairs only");
     if (batch < 0) return fail(LOFP_EINVAL, "negative batch");
     if (batch > 0 && (!T || !lo || !hi || !feasible)) return fail(LOFP_EINVAL, "null argument");
     int n = 0;
@@ -1282,7 +1650,9 @@ lofp_status lofp_bounds_batch(lofp_circuit c, const int32_t *S, int32_t batch, c
 lofp_status lofp_bs_table(lofp_circuit c, int32_t gate, int32_t N, lofp_c128 *out)
 {
     if (!c || !out) return fail(LOFP_EINVAL, "null argument");
-    if (gate < 0 || gate >= c->G || N < 0 || N > kMaxPhotons) return fail(LOFP_EINVAL, "bad gate or N");
+    if (gate < 0 || gate >= (int32_t)c->user_gate.size() || N < 0 || N > kMaxPhotons)
+        return fail(LOFP_EINVAL, "bad gate or N");
+    gate = c->user_gate[gate];
     std::lock_guard<std::mutex> lk(c->mu);
     hipStream_t s = nullptr;
     lofp_status rc = device_init(*c, N, s);
@@ -1375,8 +1745,23 @@ lofp_status lofp_amplitudes_device(lofp_circuit c, const int32_t *S, int32_t bat
         Timer inner;
         inner.on = tm.on;
         inner.s = s;
-        rc = run_contract(*c, S, n, batch, T_dev, out_dev, 0, o.precision == LOFP_PREC_FP32, s, stats,
-                          o.count_work != 0, o.state_limit, inner);
+        const int fp32 = o.precision == LOFP_PREC_FP32;
+        const SplitCfg *cfg = nullptr;
+        if (o.autotune && batch >= 64) {
+            // the tuned way for this S, batch size, precision and state limit
+            const lofp_circuit_s::TuneKey key{Sv, {batch, fp32, o.state_limit}};
+            auto it = c->tuned.find(key);
+            if (it == c->tuned.end()) {
+                SplitCfg best = default_split_cfg(*c);
+                rc = tune_contract(*c, S, n, batch, T_dev, out_dev, fp32, o.state_limit, s, best);
+                if (rc != LOFP_OK) return rc;
+                it = c->tuned.emplace(key, best).first;
+            }
+            cfg = &it->second;
+            if (stats) stats->tuned = 1;
+        }
+        rc = run_contract(*c, S, n, batch, T_dev, out_dev, 0, fp32, s, stats, o.count_work != 0, o.state_limit, inner,
+                          true, cfg);
         if (rc == LOFP_OK && stats && tm.on) {
             // bounds (and key hulls), contraction kernel, join of split halves
             stats->ms_plan = inner.ms(0, 1);
@@ -1436,6 +1821,7 @@ lofp_status lofp_amplitude(lofp_circuit c, const int32_t *S, const int32_t *T, l
 lofp_status lofp_path_counts(lofp_circuit c, const int32_t *S, int32_t batch, const int32_t *T, double *counts)
 {
     if (!c) return fail(LOFP_EINVAL, "null circuit");
+    if (c->compiled) return fail(LOFP_ENOTSUP, "path counts of circuits with distant pairs (the compiled circuit has more paths)");
     if (batch < 0) return fail(LOFP_EINVAL, "negative batch");
     if (batch > 0 && (!T || !counts)) return fail(LOFP_EINVAL, "null T or counts");
     if (batch == 0) return LOFP_OK;
@@ -1467,6 +1853,59 @@ lofp_status lofp_path_counts(lofp_circuit c, const int32_t *S, int32_t batch, co
     HIPCHK(hipStreamSynchronize(s));
     for (int p = 0; p < batch; ++p) counts[p] = h[p].x;
     return LOFP_OK;
+}
+
+lofp_status lofp_all_outputs(lofp_circuit c, const int32_t *S, int64_t capacity, int32_t *T_out, lofp_c128 *amp_out,
+                             int64_t *count, const lofp_opts *opts)
+{
+    if (!c || !count) return fail(LOFP_EINVAL, "null circuit or count");
+    int n = 0;
+    lofp_status rc = check_S(*c, S, n);
+    if (rc != LOFP_OK) return rc;
+    // C(m+n-1, n) patterns, exact while it fits (capped at 2^31)
+    const int m = c->m;
+    double cnt = 1.0;
+    for (int i = 1; i <= n; ++i) cnt = cnt * (double)(m - 1 + i) / (double)i;
+    const int64_t total = (int64_t)std::llround(cnt);
+    if (cnt > 2147483647.0) return fail(LOFP_ENOTSUP, "more than 2^31 output patterns");
+    *count = total;
+    if (!T_out && !amp_out) return LOFP_OK;
+    if (!T_out || !amp_out) return fail(LOFP_EINVAL, "T_out and amp_out go together");
+    if (capacity < total) return fail(LOFP_EINVAL, "capacity below the number of output patterns");
+    // decreasing lexicographic order: from (n, 0, ..., 0) to (0, ..., 0, n);
+    // the successor moves one photon from the last nonzero mode before the
+    // end to the next mode and gathers every later photon there
+    std::vector<int32_t> t(m, 0);
+    t[0] = n;
+    for (int64_t p = 0; p < total; ++p) {
+        std::copy(t.begin(), t.end(), T_out + p * m);
+        int i = m - 2;
+        while (i >= 0 && t[i] == 0) --i;
+        if (i < 0) break;
+        int tail = 0;
+        for (int j = i + 1; j < m; ++j) { tail += t[j]; t[j] = 0; }
+        t[i] -= 1;
+        t[i + 1] = tail + 1;
+    }
+    // amplitudes in passes on the default stream
+    const int64_t pass = 32768;
+    DevBuf dT, dO;
+    HIPCHK(ensure(dT, (size_t)std::min(total, pass) * m * sizeof(int32_t)));
+    HIPCHK(ensure(dO, (size_t)std::min(total, pass) * sizeof(lofp_c128)));
+    hipStream_t s = nullptr;
+    for (int64_t off = 0; off < total && rc == LOFP_OK; off += pass) {
+        const int32_t nb = (int32_t)std::min(pass, total - off);
+        hipError_t e = hipMemcpyAsync(dT.p, T_out + off * m, (size_t)nb * m * sizeof(int32_t), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) { rc = fail(LOFP_EDEVICE, hipGetErrorString(e)); break; }
+        rc = lofp_amplitudes_device(c, S, nb, dT.as<int32_t>(), dO.as<lofp_c128>(), opts, s, nullptr);
+        if (rc != LOFP_OK) break;
+        e = hipMemcpyAsync(amp_out + off, dO.p, (size_t)nb * sizeof(lofp_c128), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) rc = fail(LOFP_EDEVICE, hipGetErrorString(e));
+    }
+    release(dT);
+    release(dO);
+    return rc;
 }
 
 }  // extern "C"

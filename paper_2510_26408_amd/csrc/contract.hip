@@ -606,6 +606,7 @@ template <bool COUNT, bool F32, bool LDS_STATE, int BS, bool STATS>
 __global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    if (g.skip && *g.skip) return;   // the batch went to the split contraction
     const int p = blockIdx.x;
     const int nc = g.m - 1, span = (g.D + 1) * nc;
     ContractJob j;
@@ -639,11 +640,12 @@ __global__ __launch_bounds__(BS, multi_waves_per_simd<BS>()) void k_contract_mul
                                                        MultiOverride ov)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    if (ov.njobs && (int)blockIdx.x >= *ov.njobs) return;   // launched for the worst case
     const int jb = ov.order ? ov.order[blockIdx.x] : (int)blockIdx.x;
     ContractJob j = jobs[jb];
     if (ov.max_states > 0) {
         j.max_states = ov.max_states;
-        j.ws = ov.ws_base ? ov.ws_base + (int64_t)jb * 2 * ov.max_states : nullptr;
+        j.ws = ov.ws_base && !ov.ws_pool ? ov.ws_base + (int64_t)jb * 2 * ov.max_states : nullptr;
         if (ov.state_base) {
             j.state_out = ov.state_base + (int64_t)jb * ov.state_cap;
             j.state_cap = ov.state_cap;
@@ -659,7 +661,30 @@ __global__ __launch_bounds__(BS, multi_waves_per_simd<BS>()) void k_contract_mul
             // the LDS its state would have used stages the step programs
             unsigned char *stg = (size_t)ov.lds_states * 2 * sizeof(double2) >= kDescChunk * sizeof(ContractStep)
                                      ? smem + job_lds_head(j.nvars, j.m - 1) : nullptr;
+            // a workspace slice from the pool: at most ws_slots jobs are
+            // resident, so a free slice exists; the probe count is bounded
+            // all the same (a job left without one reports an overflow)
+            __shared__ int s_slot;
+            if (ov.ws_pool) {
+                if (threadIdx.x == 0) {
+                    int got = -1;
+                    for (int p = 0; p < 4 * ov.ws_slots && got < 0; ++p) {
+                        const int sl = (int)((blockIdx.x + (unsigned)p) % (unsigned)ov.ws_slots);
+                        if (atomicCAS(&ov.ws_pool[sl], 0, 1) == 0) got = sl;
+                    }
+                    s_slot = got;
+                }
+                __syncthreads();
+                j.ws = s_slot >= 0 ? ov.ws_base + (int64_t)s_slot * 2 * ov.max_states : nullptr;
+            }
             contract_run<ABS, F32 || ABS, false, BS, STATS>(j, smem, stat_transitions, overflow, stg);
+            if (ov.ws_pool) {
+                __syncthreads();   // every lane is done with the slice
+                if (threadIdx.x == 0 && s_slot >= 0) {
+                    __threadfence();
+                    atomicExch(&ov.ws_pool[s_slot], 0);
+                }
+            }
         }
         return;
     }
@@ -708,6 +733,7 @@ constexpr int kJoinBlock = 128;
 template <int NS>
 __global__ __launch_bounds__(kJoinBlock) void k_join(JoinArgs g)
 {
+    if (g.split_flag && !*g.split_flag) return;   // contracted per pattern instead
     const int p = blockIdx.x;
     const int nc = g.m - 1, span = (g.D + 1) * nc;
     if (g.infeasible[p]) {
@@ -835,6 +861,40 @@ hipError_t launch_contract_sizes(const ContractArgs &a, int *max_size, hipStream
 {
     if (a.B == 0) return hipSuccess;
     hipLaunchKernelGGL(k_contract_sizes, dim3((a.B + 63) / 64), dim3(64), 0, stream, a, max_size);
+    return hipGetLastError();
+}
+
+int contract_multi_resident_blocks(size_t lds_bytes, int max_states)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    const bool wide = contract_block_size(max_states) != 64;
+    const int bs = wide ? 512 : 64;
+    // the instantiations that take the global-state path differ only in
+    // template flags, not in resources that bound residency; query one
+    hipError_t e = wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                              &per_cu, reinterpret_cast<const void *>(k_contract_multi<false, true, 512, false, false>), bs,
+                              lds_bytes)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                              &per_cu, reinterpret_cast<const void *>(k_contract_multi<false, true, 64, false, false>), bs,
+                              lds_bytes);
+    if (e != hipSuccess || per_cu <= 0) per_cu = 2048 / bs;   // waves per CU bound
+    // with a margin: variants compiled with other flags may use fewer registers
+    return cus * per_cu * 2;
+}
+
+__global__ void k_fill_i32(int32_t *p, size_t n, int32_t v)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    const size_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, stream, p, n, v);
     return hipGetLastError();
 }
 

@@ -109,6 +109,16 @@ struct Schedule {
     std::string error;
 };
 
+// How a batch sharing S is contracted (chosen by default or by the tuner).
+struct SplitCfg {
+    enum Mode { kDevice = 0, kHost = 1, kPerPattern = 2 };
+    int mode = kDevice;   // device-decided split, host-sized split, or one job per pattern
+    int rs = 0;           // split cut: the top half holds cuts 0..rs
+    int lds_kb = 52;      // LDS of one job of the split contraction
+    int small_min = 256;  // batch sizes split without shared halves
+    int small_max = 1024;
+};
+
 struct SplitProgram {
     int rs = 0;
     Schedule top, bot;
@@ -126,7 +136,12 @@ struct SplitProgram {
 
 struct lofp_circuit_s {
     using DevBuf = lofp::host::DevBuf;
-    int m = 0, D = 0, G = 0, nc = 0;
+    int m = 0, D = 0, G = 0, nc = 0;       // D, G: layers and splitters as compiled
+    int user_depth = 0;                    // layers as given
+    bool compiled = false;                 // distant pairs compiled to adjacent ones
+    std::vector<int> user_gate;            // internal gate of each given splitter
+    std::vector<uint8_t> gate_swap;        // per splitter: 0, 1 = exact swap
+                                           // [[0,1],[-1,0]], 2 = its inverse
     std::vector<lofp_bs> gates;            // application order
     std::vector<int32_t> gate_cut, gate_layer, layer_start;
     std::vector<uint8_t> cut_gate;         // [D][nc]
@@ -153,6 +168,9 @@ struct lofp_circuit_s {
     std::vector<std::array<lofp::host::FRef, 4>> fac;       // factors in cut-major order
     std::vector<int> fgate, fcut;
     std::map<int, std::unique_ptr<lofp::host::SplitProgram>> splits;
+    // tuned ways of contracting: (S, (batch, fp32, state limit)) -> configuration
+    using TuneKey = std::pair<std::vector<int32_t>, std::array<int, 3>>;
+    std::map<TuneKey, lofp::host::SplitCfg> tuned;
     std::mutex mu;
 
     // device state (lazy)
@@ -165,6 +183,7 @@ struct lofp_circuit_s {
     DevBuf d_S, d_lo, d_hi, d_inf, d_C, d_E, d_count, d_slot_stage, d_off, d_coff, d_fa, d_fb, d_ba, d_bb;
     DevBuf d_levels, d_tab_mid, d_counters, d_T, d_out, d_ws, d_cfg, d_rankb;
     DevBuf d_ktab, d_kslot, d_kof, d_krep, d_kcnt, d_khull, d_klohi, d_kinf, d_jobs, d_kstate, d_korder;
+    DevBuf d_wspool, d_ws2;                // workspace pool flags; per-pattern workspace
     std::vector<std::shared_ptr<lofp::host::SharedBlock>> blocks;   // pooled set-up blocks in use
     int32_t *h_pin = nullptr;              // small pinned readback buffer
     lofp::KeyLayoutState klay;             // layout of the key table and hulls
@@ -219,6 +238,10 @@ public:
     StreamUse &operator=(const StreamUse &) = delete;
     hipError_t begin()
     {
+        // a call being captured into a graph records no events (the graph's
+        // circuit serves that graph alone)
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s_, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return hipSuccess;
         armed_ = true;
         if (c_.last_ev && c_.last_stream != s_) return hipStreamWaitEvent(s_, c_.last_ev, 0);
         return hipSuccess;
@@ -240,6 +263,9 @@ private:
 };
 
 lofp_status check_S(const lofp_circuit_s &c, const int32_t *S, int &n);
+// A new circuit with the same compiled splitters (and exact swaps) as c, and
+// buffers of its own.
+lofp_status clone_circuit(const lofp_circuit_s &c, lofp_circuit_s **out);
 // S-only bounds of S, cached on the circuit (the caller holds its lock).
 void s_only_cached(lofp_circuit_s &c, const int32_t *S, int n);
 void s_only_bounds(const lofp_circuit_s &c, const int32_t *S, int n, std::vector<int16_t> &lo,

@@ -194,6 +194,103 @@ __global__ __launch_bounds__(256) void k_key_reset(KeyArgs a, int ntop, int nbot
     if (lane == 0) a.table[key_slot_index(half, a.stride, sl)] = kKeyEmpty;
 }
 
+// Totals of claimed keys per half (whole wave).
+__device__ __forceinline__ void key_totals(const KeyArgs &a, int &ntop, int &nbot)
+{
+    const int lane = threadIdx.x & 63;
+    int t = a.count[lane], b = a.count[kKeySubs + lane];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        t += __shfl_xor(t, o, 64);
+        b += __shfl_xor(b, o, 64);
+    }
+    ntop = t;
+    nbot = b;
+}
+
+// Device-decided jobs (launch_key_jobs_dev): 2B waves, wave w serves key w
+// of the keys that were claimed.
+__global__ __launch_bounds__(256) void k_key_jobs_dev(KeyArgs a, ContractJob top, ContractJob bot, ContractJob *jobs,
+                                                      int32_t *kinf, double2 *state_base, int state_cap)
+{
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = (int)(gt >> 6);
+    const int lane = threadIdx.x & 63;
+    if (gt < 8) a.counters[gt] = 0;   // the contraction's counters for this call
+    int ntop, nbot;
+    key_totals(a, ntop, nbot);
+    const bool split = (int64_t)(ntop + nbot) * 4 <= (int64_t)a.B * 3 || (a.B >= a.small_min && a.B <= a.small_max);
+    if (gt == 0) {
+        a.ctl[0] = split;
+        a.ctl[1] = split ? ntop + nbot : 0;
+        a.ctl[2] = ntop;
+        a.ctl[3] = nbot;
+    }
+    if (w >= ntop + nbot) return;
+    const int half = w >= ntop, k = half ? w - ntop : w;
+    const int sl = key_slot_of(a, half, k);
+    const int64_t srow = key_hull_row(half, a.stride, sl, a.span);
+    if (!split) {
+        // one contraction per pattern: only empty the slot
+        for (int i = lane; i < a.span; i += 64) {
+            a.hlo[srow + i] = kHullEmptyLo;
+            a.hhi[srow + i] = kHullEmptyHi;
+        }
+        if (lane == 0) a.table[key_slot_index(half, a.stride, sl)] = kKeyEmpty;
+        return;
+    }
+    if (lane == 0) a.slot_key[key_slot_index(half, a.stride, sl)] = k;
+    const int64_t krow = ((int64_t)half * a.B + k) * a.span;
+    for (int i = lane; i < a.span; i += 64) {
+        int l = a.hlo[srow + i], h = a.hhi[srow + i];
+        if (h < 0) { l = 1; h = 0; }   // no feasible member: empty interval
+        a.klo[krow + i] = (int16_t)l;
+        a.khi[krow + i] = (int16_t)h;
+    }
+    const ContractJob &tmpl = half ? bot : top;
+    const int nc = a.m - 1;
+    float work = 0.0f;
+    for (int si = lane; si < tmpl.nsteps; si += 64) {
+        const ContractStep &st = tmpl.steps[si];
+        float e = 1.0f;
+        for (int q = 0; q < st.n_new; ++q) {
+            const int v = st.new_vars[q];
+            const int64_t i = srow + tmpl.var_time[v] * nc + tmpl.var_cut[v];
+            e *= (float)max(0, a.hhi[i] - a.hlo[i] + 1);
+        }
+        for (int q = 0; q < st.n_sum; ++q) {
+            const int v = st.sum_vars[q];
+            const int64_t i = srow + tmpl.var_time[v] * nc + tmpl.var_cut[v];
+            e *= (float)max(1, a.hhi[i] - a.hlo[i] + 1);
+        }
+        work += e;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) work += __shfl_xor(work, o, 64);
+    for (int i = lane; i < a.span; i += 64) {
+        a.hlo[srow + i] = kHullEmptyLo;
+        a.hhi[srow + i] = kHullEmptyHi;
+    }
+    if (lane != 0) return;
+    unsigned long long *tab = a.table + key_slot_index(half, a.stride, 0);
+    const int rv = (int)(unsigned)tab[sl];
+    tab[sl] = kKeyEmpty;
+    a.job_bucket[w] = work > 1.0f ? min(255, (int)(8.0f * log2f(work))) : 0;
+    const int place = half ? a.B + k : k;   // fixed by the half, not by the key counts
+    ContractJob J = tmpl;
+    J.T = a.T + (int64_t)(rv >= a.B ? rv - a.B : rv) * a.m;
+    J.lo = a.klo + krow;
+    J.hi = a.khi + krow;
+    J.infeasible = kinf + w;
+    kinf[w] = 0;
+    J.ovf = kinf + 2 * (int64_t)a.B + place;
+    kinf[2 * (int64_t)a.B + place] = 0;
+    J.out = nullptr;
+    J.state_out = state_base + (int64_t)place * state_cap;
+    J.state_cap = state_cap;
+    jobs[w] = J;
+}
+
 // One block: the jobs in decreasing work bucket (a counting sort; the order
 // inside a bucket is arbitrary and changes no result).
 __global__ __launch_bounds__(1024) void k_key_order(KeyArgs a, int nj)
@@ -201,6 +298,7 @@ __global__ __launch_bounds__(1024) void k_key_order(KeyArgs a, int nj)
     __shared__ int hist[256], start[256];
     __shared__ int wsum[4];
     const int t = threadIdx.x;
+    if (a.ctl) nj = a.ctl[1];   // decided on the device (0 when not split)
     if (t < 2 * kKeySubs) a.count[t] = 0;   // the jobs kernel has read them
     if (t < 256) hist[t] = 0;
     __syncthreads();
@@ -243,6 +341,17 @@ hipError_t launch_key_jobs(const KeyArgs &a, int ntop, int nbot, const ContractJ
     hipLaunchKernelGGL(k_key_jobs, dim3((unsigned)(threads > 0 ? (threads + 255) / 256 : 1)), dim3(256), 0, stream,
                        a, ntop, nbot, top, bot, jobs, kinf);
     hipLaunchKernelGGL(k_key_order, dim3(1), dim3(1024), 0, stream, a, ntop + nbot);
+    return hipGetLastError();
+}
+
+hipError_t launch_key_jobs_dev(const KeyArgs &a, const ContractJob &top, const ContractJob &bot, ContractJob *jobs,
+                               int32_t *kinf, double2 *state_base, int state_cap, hipStream_t stream)
+{
+    if (!a.ctl) return hipErrorInvalidValue;
+    const int64_t threads = 2 * (int64_t)a.B * 64;
+    hipLaunchKernelGGL(k_key_jobs_dev, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, stream, a, top, bot, jobs,
+                       kinf, state_base, state_cap);
+    hipLaunchKernelGGL(k_key_order, dim3(1), dim3(1024), 0, stream, a, 0);
     return hipGetLastError();
 }
 

@@ -50,12 +50,21 @@ LOFP_HD int table_cols(int n) { return n + 2; }
 // ---------------------------------------------------------------- bounds
 // lo/hi: (D+1) x (m-1) arrays, row t = after t layers.  cut_gate[t*(m-1)+r]
 // is nonzero when layer t has a beam splitter on cut r.  On entry lo/hi hold
-// the light-cone intervals (or 0..n); on exit they are propagated.  Returns 1
-// if some interval is empty (no valid path), else 0.
+// the light-cone intervals (or 0..n); on exit they are propagated to the
+// fixed point.  Returns 1 if some interval is empty (no valid path), else 0.
+//
+// The passes run until one changes nothing.  They terminate: every value
+// lies in [0, n] (the light-cone sums are photon counts, and the first pass
+// clamps the ends), lower bounds only grow and upper bounds only shrink, so
+// a pass that changes something moves one of the 2 (D+1)(m-1) values by at
+// least one, which can happen at most 2 (D+1)(m-1) n times.
+LOFP_HD int bound_pass_limit(int m, int D, int n) { return 2 * (D + 1) * (m - 1) * (n + 1) + 2; }
+
 LOFP_HD int propagate_bounds(int m, int D, int n, const uint8_t *cut_gate, int16_t *lo, int16_t *hi)
 {
     const int nc = m - 1;
-    for (int it = 0; it < 4 * (D + m) + 8; ++it) {
+    const int limit = bound_pass_limit(m, D, n);
+    for (int it = 0; it < limit; ++it) {
         int changed = 0;
         for (int t = 0; t <= D; ++t) {
             int16_t *L = lo + t * nc, *H = hi + t * nc;

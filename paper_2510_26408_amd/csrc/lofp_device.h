@@ -208,6 +208,7 @@ struct ContractArgs {
     double2 *ws;              // [B][2][max_states] when the state does not fit LDS
     int32_t *overflow;
     int stats;                // count transitions into stat_transitions
+    const int32_t *skip;      // if set and nonzero: do nothing (the batch was split)
 };
 hipError_t launch_contract(const ContractArgs &a, hipStream_t stream);
 
@@ -243,6 +244,10 @@ struct MultiOverride {
     int lds_states;              // > 0: a job whose own largest state fits this
                                  // many entries keeps it in LDS, others in ws
     const int *order;            // block b runs job order[b] (nullptr: job b)
+    const int *njobs;            // if set: blocks at or past *njobs do nothing
+    int *ws_pool;                // if set: a job needing ws claims one of
+    int ws_slots;                // ws_slots slices (flags 0 = free) instead of
+                                 // using slice `job`
 };
 struct BoundsJob {
     int m, D, n;
@@ -262,6 +267,11 @@ hipError_t launch_contract_multi(int count, const ContractJob *jobs, size_t lds_
                                  bool abs = false);
 // Largest state over the jobs (one thread per job), atomically maxed into *mx.
 hipError_t launch_multi_sizes(int count, const ContractJob *jobs, int *mx, hipStream_t stream);
+// Most blocks of the split contraction kernel that can be resident at once
+// on the current device (sizes a workspace pool claimed per resident job).
+int contract_multi_resident_blocks(size_t lds_bytes, int max_states);
+// Fills n ints with v (a kernel, so that a captured call records no memset).
+hipError_t launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t stream);
 
 constexpr int kKeySubs = 64;   // claim counters per half (spread the atomics)
 // Grouping of a batch by the halves of T (split contraction), per half h:
@@ -286,6 +296,10 @@ struct KeyArgs {
     unsigned long long *counters;  // [8] zeroed by the jobs kernel
     int *job_bucket;               // [2B] cost bucket of each job
     int *order;                    // [2B] jobs by decreasing cost bucket
+    // decided on the device (launches sized for the worst case, no host
+    // read-back): nullptr in the host-sized form
+    int *ctl;                      // [4] split?, jobs, top keys, bottom keys
+    int small_min, small_max;      // batch sizes split without shared halves
 };
 // Insert every pattern's two half-rows; keys are numbered as their slots are
 // claimed, so their numbers (not the results) depend on thread timing.
@@ -298,6 +312,16 @@ hipError_t launch_key_jobs(const KeyArgs &a, int ntop, int nbot, const ContractJ
                            ContractJob *jobs, int32_t *kinf, hipStream_t stream);
 // Empties the table, the slot hulls and the counts without making jobs.
 hipError_t launch_key_reset(const KeyArgs &a, int ntop, int nbot, hipStream_t stream);
+// Device-decided form of launch_key_jobs (a.ctl set): the key counts are read
+// on the device, which decides whether the batch is split (halves shared by
+// at most 3/4 as many keys as patterns, or a batch size in
+// [small_min, small_max]) and records it in a.ctl.  Split: one job per key
+// (2B waves launched), top key k writing its state at state_base + k * cap,
+// bottom key k at state_base + (B + k) * cap, overflow flags at
+// kinf[2B + k] and kinf[3B + k]; then the dispatch order.  Not split: the
+// slots are emptied.  Either way the table, hulls and counts are left empty.
+hipError_t launch_key_jobs_dev(const KeyArgs &a, const ContractJob &top, const ContractJob &bot, ContractJob *jobs,
+                               int32_t *kinf, double2 *state_base, int state_cap, hipStream_t stream);
 struct JoinArgs {
     int B, m, n, D;
     const int16_t *lo, *hi;          // per pattern [B][span]
@@ -314,6 +338,7 @@ struct JoinArgs {
     const double2 *top_state, *bot_state;
     int state_cap;
     const int32_t *top_ovf, *bot_ovf; // per key: its job's state did not fit
+    const int32_t *split_flag;        // if set and zero: the batch was not split
     double2 *out;
 };
 hipError_t launch_join(const JoinArgs &a, hipStream_t stream);

@@ -57,7 +57,10 @@ __device__ void bounds_wave(int m, int D, int n, const int32_t *__restrict__ S, 
         H[i] = (int16_t)h;
     }
     __syncthreads();
-    for (int it = 0; it < 4 * (D + m) + 8; ++it) {
+    // until a pass changes nothing (bound_pass_limit is never reached: it
+    // bounds how many passes can change a value)
+    const int limit = bound_pass_limit(m, D, n);
+    for (int it = 0; it < limit; ++it) {
         int ch = 0;
         for (int t = tid; t <= D; t += 64) {          // rows: order between cuts
             int16_t *Lr = L + t * nc, *Hr = H + t * nc;

@@ -157,7 +157,7 @@ struct Batch {
 // Enqueue one multi-circuit batch on b.s (reqs already planned).  checked:
 // FP32 products plus the absolute form of every request, from which each
 // result's rounding bound follows (rounding_bound).
-lofp_status launch_batch(Batch &b, int fp32, bool checked = false)
+lofp_status launch_batch(Batch &b, int fp32, bool checked = false, Timer *tm = nullptr)
 {
     b.checked = checked && fp32;
     const int count = (int)b.reqs.size();
@@ -259,8 +259,10 @@ lofp_status launch_batch(Batch &b, int fp32, bool checked = false)
     HIPCHK(launch_bounds_multi(count, b.d_bj.as<BoundsJob>(), max_span, s));
     const size_t lds = contract_job_lds_bytes(max_vars, max_m, (int)max_est, in_lds);
     unsigned long long *ctr = b.d_ctr.as<unsigned long long>();
+    if (tm) tm->mark();
     HIPCHK(launch_contract_multi(count, b.d_cj.as<ContractJob>(), lds, (int)max_est, in_lds, fp32 != 0, ctr,
                                  reinterpret_cast<int32_t *>(ctr + 1), s));
+    if (tm) tm->mark();
     if (b.checked) {
         // the absolute form: same jobs, FP64, outputs to d_abs
         HIPCHK(ensure(b.d_abs, count * sizeof(double2)));
@@ -309,6 +311,7 @@ struct lofp_server_s {
     std::vector<std::thread> planners;
     std::unordered_map<uint64_t, DoneRec> done;
     int64_t fp64_fallbacks = 0;
+    int64_t pathsum_fallbacks = 0;         // requests the contraction refused, summed by the path sum
     std::unordered_map<uint64_t, std::pair<lofp_status, std::string>> failed;   // ticket -> planning error
     std::vector<double> latencies;
     std::vector<std::unique_ptr<Batch>> batches;
@@ -419,8 +422,40 @@ void worker_loop(lofp_server_s *sv)
 // Planner threads: requests are planned on the host (program, exact
 // intervals, state bound) off the submitters' and the launcher's threads; a
 // request that cannot run completes with its error.
+// A request the contraction cannot take (its program or its state is too
+// large) is summed by the path-sum form instead, on the planner thread's own
+// stream, which overlaps the batches in flight.
+struct PathsumLane {
+    hipStream_t s = nullptr;
+    DevBuf dT, dO;
+    ~PathsumLane()
+    {
+        release(dT);
+        release(dO);
+        if (s) (void)hipStreamDestroy(s);
+    }
+    lofp_status run(const Req &r, lofp_c128 &out)
+    {
+        if (!s) HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        HIPCHK(ensure(dT, r.T.size() * sizeof(int32_t)));
+        HIPCHK(ensure(dO, sizeof(lofp_c128)));
+        HIPCHK(hipMemcpyAsync(dT.p, r.T.data(), r.T.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        lofp_opts o{};
+        o.method = LOFP_METHOD_PATHSUM;
+        o.fwd_layer = -1;
+        o.bwd_layer = -1;
+        lofp_status rc = lofp_amplitudes_device(r.c, r.S.data(), 1, dT.as<int32_t>(), dO.as<lofp_c128>(), &o, s, nullptr);
+        if (rc != LOFP_OK) return rc;
+        HIPCHK(hipMemcpyAsync(&out, dO.p, sizeof(lofp_c128), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return LOFP_OK;
+    }
+};
+
 void planner_loop(lofp_server_s *sv)
 {
+    (void)hipSetDevice(sv->device);
+    PathsumLane lane;
     for (;;) {
         Req r;
         {
@@ -431,13 +466,28 @@ void planner_loop(lofp_server_s *sv)
             sv->queue.pop_front();
             sv->planning++;
         }
-        const lofp_status rc = plan_request(r);
+        lofp_status rc = plan_request(r);
+        lofp_c128 amp{0.0, 0.0};
+        bool by_pathsum = false;
+        if ((rc == LOFP_ENOTSUP || rc == LOFP_ENOMEM) && r.planned) {
+            // a valid request the contraction refuses: the path sum instead
+            rc = lane.run(r, amp);
+            by_pathsum = rc == LOFP_OK;
+        }
+        const std::string err = rc == LOFP_OK ? std::string() : std::string(lofp_last_error());
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->planning--;
-        if (rc == LOFP_OK) {
+        if (by_pathsum) {
+            const double lat = now_ms() - r.t_submit;
+            sv->done[r.ticket] = {amp, lat, std::nan("")};
+            sv->latencies.push_back(lat);
+            sv->pathsum_fallbacks++;
+            sv->completed++;
+            sv->cv.notify_all();
+        } else if (rc == LOFP_OK) {
             sv->ready.push_back(std::move(r));
         } else {
-            sv->failed[r.ticket] = {rc, lofp_last_error()};
+            sv->failed[r.ticket] = {rc, err};
             sv->completed++;
             sv->cv.notify_all();
         }
@@ -475,7 +525,7 @@ lofp_status lofp_amplitudes_multi(int32_t count, const lofp_request *req, lofp_c
     tm.on = stats && opts && opts->record_timing;
     tm.s = b.s;
     tm.mark();
-    lofp_status rc = launch_batch(b, fp32, fp32);
+    lofp_status rc = launch_batch(b, fp32, fp32, &tm);
     if (rc != LOFP_OK) return rc;
     tm.mark();
     HIPCHK(hipStreamSynchronize(b.s));
@@ -489,7 +539,8 @@ lofp_status lofp_amplitudes_multi(int32_t count, const lofp_request *req, lofp_c
         if (stats) stats->transitions = (int64_t)h[0];
     }
     if (stats) {
-        if (tm.on) stats->ms_total = stats->ms_contract = tm.ms(0, 1);
+        // the whole batch (copies, bounds, contraction), and the contraction kernel
+        if (tm.on) { stats->ms_total = tm.ms(0, 3); stats->ms_contract = tm.ms(1, 2); }
     }
     for (int i = 0; i < count && err_bound; ++i) err_bound[i] = std::nan("");
     if (!fp32) return LOFP_OK;
@@ -623,6 +674,7 @@ lofp_status lofp_server_get_stats(lofp_server sv, lofp_server_stats *st)
     st->launches = sv->launches;
     st->mean_batch = sv->launches ? (double)sv->launched_reqs / (double)sv->launches : 0.0;
     st->fp64_fallbacks = sv->fp64_fallbacks;
+    st->pathsum_fallbacks = sv->pathsum_fallbacks;
     if (!sv->latencies.empty()) {
         std::vector<double> v = sv->latencies;
         std::sort(v.begin(), v.end());

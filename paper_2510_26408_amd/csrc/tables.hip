@@ -26,11 +26,17 @@ namespace lofp {
 
 // All sectors of one gate's table by one block, in order of N (each sector
 // reads the previous one, written by the same block before a barrier).
+// theta NaN marks an exact mode swap (cos theta = 0, sin theta = phi = +-1,
+// no phase), which the host uses to bring distant modes together.
 __device__ void build_gate_table(int n_tab, double theta, double phi, double2 *__restrict__ tab)
 {
     double s, c, sp, cp;
-    sincos(theta, &s, &c);
-    sincos(phi, &sp, &cp);
+    if (isnan(theta)) {
+        s = phi; c = 0.0; sp = 0.0; cp = 1.0;
+    } else {
+        sincos(theta, &s, &c);
+        sincos(phi, &sp, &cp);
+    }
     const double2 u_aa = make_double2(c, 0.0), u_bb = u_aa;
     const double2 u_ba = make_double2(s * cp, s * sp);     // upper in, lower out
     const double2 u_ab = make_double2(-s * cp, s * sp);    // lower in, upper out: -s e^{-i phi}

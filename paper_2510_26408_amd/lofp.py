@@ -25,6 +25,7 @@ EXPORTED = (
     "lofp_bounds", "lofp_bounds_batch", "lofp_bs_table", "lofp_amplitudes_device", "lofp_amplitudes", "lofp_amplitude",
     "lofp_path_counts", "lofp_amplitudes_multi", "lofp_server_create", "lofp_server_submit",
     "lofp_server_result", "lofp_server_get_stats", "lofp_server_destroy", "lofp_amplitudes_device_noalloc",
+    "lofp_all_outputs", "lofp_circuit_compiled", "lofp_graph_create", "lofp_graph_launch", "lofp_graph_destroy",
 )
 
 
@@ -46,7 +47,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("precision", ctypes.c_int32), ("fwd_layer", ctypes.c_int32),
                 ("bwd_layer", ctypes.c_int32), ("record_timing", ctypes.c_int32),
                 ("frontier_budget_kb", ctypes.c_int32), ("count_work", ctypes.c_int32), ("state_limit", ctypes.c_int32),
-                ("fp32_rtol", ctypes.c_double)]
+                ("fp32_rtol", ctypes.c_double), ("autotune", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -58,7 +59,8 @@ class Stats(ctypes.Structure):
                 ("ms_dfs", ctypes.c_double), ("ms_reduce", ctypes.c_double), ("ms_contract", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("method_used", ctypes.c_int32),
                 ("split_top_keys", ctypes.c_int32), ("split_bottom_keys", ctypes.c_int32),
-                ("max_state", ctypes.c_int32)]
+                ("max_state", ctypes.c_int32), ("split_cut", ctypes.c_int32), ("lds_kb", ctypes.c_int32),
+                ("tuned", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("reserved")}
@@ -77,7 +79,7 @@ class ServerOpts(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("launches", ctypes.c_int64),
                 ("mean_batch", ctypes.c_double), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
-                ("max_ms", ctypes.c_double), ("fp64_fallbacks", ctypes.c_int64)]
+                ("max_ms", ctypes.c_double), ("fp64_fallbacks", ctypes.c_int64), ("pathsum_fallbacks", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -122,6 +124,12 @@ def load():
     lib.lofp_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     lib.lofp_server_destroy.argtypes = [vp]
     lib.lofp_amplitudes_device_noalloc.argtypes = [vp, i32p, ctypes.c_int32, vp, vp, ctypes.POINTER(Opts), vp]
+    lib.lofp_all_outputs.argtypes = [vp, i32p, ctypes.c_int64, i32p, ctypes.POINTER(C128),
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(Opts)]
+    lib.lofp_circuit_compiled.argtypes = [vp, i32p, i32p, ctypes.POINTER(BS), ctypes.c_int32]
+    lib.lofp_graph_create.argtypes = [vp, i32p, ctypes.c_int32, vp, vp, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+    lib.lofp_graph_launch.argtypes = [vp, vp]
+    lib.lofp_graph_destroy.argtypes = [vp]
     for f in EXPORTED[2:]:
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -143,7 +151,7 @@ def _ip(a: np.ndarray):
 
 def make_opts(method: int = METHOD_AUTO, precision: int = PREC_FP64, fwd_layer: int = -1, bwd_layer: int = -1,
               record_timing: bool = False, frontier_budget_kb: int = 0, count_work: bool = False,
-              fp32_rtol: float = 0.0, state_limit: int = 0) -> Opts:
+              fp32_rtol: float = 0.0, state_limit: int = 0, autotune: bool = False) -> Opts:
     o = Opts()
     o.method, o.precision, o.fwd_layer, o.bwd_layer = method, precision, fwd_layer, bwd_layer
     o.record_timing = 1 if record_timing else 0
@@ -151,12 +159,14 @@ def make_opts(method: int = METHOD_AUTO, precision: int = PREC_FP64, fwd_layer: 
     o.count_work = 1 if count_work else 0
     o.fp32_rtol = fp32_rtol
     o.state_limit = state_limit
+    o.autotune = 1 if autotune else 0
     return o
 
 
 class Circuit:
     """A circuit handle: ``layers`` is a list of layers, each a list of
-    ``(a, b, theta, phi)`` with b = a + 1 (mode a = upper port)."""
+    ``(a, b, theta, phi)`` with a < b (mode a = upper port; distant pairs are
+    compiled to adjacent ones by the library)."""
 
     def __init__(self, m: int, layers: Sequence[Sequence[Tuple[int, int, float, float]]]):
         lib = load()
@@ -266,6 +276,34 @@ class Circuit:
                                                      ctypes.byref(opts) if opts is not None else None,
                                                      ctypes.c_void_p(stream.cuda_stream)))
 
+    def all_outputs(self, S, opts: Optional[Opts] = None) -> Tuple[np.ndarray, np.ndarray]:
+        """Every output pattern of sum(S) photons (decreasing lexicographic
+        order) and its amplitude: (T [count, m] int32, amp [count] complex128)."""
+        S = _i32(S)
+        lib = load()
+        cnt = ctypes.c_int64()
+        _check(lib.lofp_all_outputs(self._h, _ip(S), 0, None, None, ctypes.byref(cnt), None))
+        Ts = np.zeros((cnt.value, self.m), dtype=np.int32)
+        amps = (C128 * max(1, cnt.value))()
+        _check(lib.lofp_all_outputs(self._h, _ip(S), cnt.value, _ip(Ts), amps, ctypes.byref(cnt),
+                                    ctypes.byref(opts) if opts is not None else None))
+        return Ts, np.frombuffer(amps, dtype=np.complex128)[:cnt.value].copy()
+
+    def compiled_layers(self) -> List[List[Tuple[int, int, float, float]]]:
+        """The adjacent-pair layers the library evaluates (host only)."""
+        lib = load()
+        nl = ctypes.c_int32()
+        _check(lib.lofp_circuit_compiled(self._h, ctypes.byref(nl), None, None, 0))
+        lens = np.zeros(max(1, nl.value), dtype=np.int32)
+        cap = 32 * max(1, nl.value)
+        arr = (BS * cap)()
+        _check(lib.lofp_circuit_compiled(self._h, ctypes.byref(nl), _ip(lens), arr, cap))
+        out, k = [], 0
+        for l in range(nl.value):
+            out.append([(arr[k + i].a, arr[k + i].b, arr[k + i].theta, arr[k + i].phi) for i in range(lens[l])])
+            k += lens[l]
+        return out
+
     def amplitude(self, S, T) -> complex:
         S, T = _i32(S), _i32(T)
         out = C128()
@@ -279,6 +317,42 @@ class Circuit:
         _check(load().lofp_path_counts(self._h, _ip(S), Ts.shape[0], _ip(Ts),
                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out
+
+
+class Graph:
+    """One amplitude call captured as a HIP graph: ``launch()`` re-evaluates
+    the patterns now in ``T_dev`` into ``out_dev`` (both kept alive here)."""
+
+    def __init__(self, circuit: "Circuit", S, T_dev, out_dev, opts: Optional[Opts] = None):
+        import torch
+
+        assert T_dev.dtype == torch.int32 and T_dev.is_contiguous() and T_dev.shape[-1] == circuit.m
+        assert out_dev.dtype == torch.complex128 and out_dev.is_contiguous()
+        self._keep = (circuit, T_dev, out_dev)
+        S = _i32(S)
+        h = ctypes.c_void_p()
+        _check(load().lofp_graph_create(circuit.handle, _ip(S), int(T_dev.shape[0]), ctypes.c_void_p(T_dev.data_ptr()),
+                                        ctypes.c_void_p(out_dev.data_ptr()),
+                                        ctypes.byref(opts) if opts is not None else None, ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None) -> None:
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream(self._keep[1].device)
+        _check(load().lofp_graph_launch(self._h, ctypes.c_void_p(stream.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().lofp_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def amplitudes_multi(items, opts: Optional[Opts] = None, stats: Optional[Stats] = None, bounds: bool = False):

@@ -1,8 +1,13 @@
 """GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
 
-Tolerance: 1e-12 absolute for complex128 amplitudes (the stated target), and
-additionally |gpu - oracle| <= 1e-12 * max(1, |oracle|) * 0 + 1e-12 is checked
-together with a relative bound where the amplitude is not tiny."""
+Tolerance (see check()): every amplitude within 1e-12 absolute of the oracle
+(the stated target) and, where the oracle's values come with its own rounding
+bound eb (Ryser's a-posteriori bound), also within 1e-9 |A| + 1e3 eb: nine
+significant digits wherever the oracle itself resolves them, so a result of
+zero (or a wrong digit) fails for every amplitude the oracle vouches for,
+however small.  Measured on the benchmark workloads the GPU stays two orders
+of magnitude inside both terms (largest relative error 4e-12 where
+eb <= 1e-9 |A|; largest |error| / eb 0.07)."""
 import math
 
 import numpy as np
@@ -13,6 +18,8 @@ from paper_2510_26408_amd import lofp, workloads
 
 pytestmark = pytest.mark.gpu
 ATOL = 1e-12
+RTOL = 1e-9          # relative agreement where the oracle resolves the amplitude
+EB_FACTOR = 1e3      # slack in units of the oracle's own rounding bound
 
 
 def _need_gpu():
@@ -30,15 +37,40 @@ def flat(layers):
     return [bs for l in layers for bs in l]
 
 
+class Want(np.ndarray):
+    """Oracle amplitudes carrying the oracle's rounding bound of each entry
+    (``.eb``, same shape); indexing keeps the two aligned."""
+
+    def __new__(cls, amps, eb):
+        obj = np.asarray(amps).view(cls)
+        obj.eb = np.asarray(eb, dtype=np.float64)
+        return obj
+
+    def __array_finalize__(self, obj):
+        self.eb = getattr(obj, "eb", None)
+
+    def __getitem__(self, k):
+        r = super().__getitem__(k)
+        if isinstance(r, Want) and self.eb is not None:
+            r.eb = self.eb[k]
+        return r
+
+
 def check(got, want, atol=ATOL):
+    eb = getattr(want, "eb", None)
     got, want = np.asarray(got), np.asarray(want)
     err = np.abs(got - want)
     assert err.max() <= atol, (err.max(), int(err.argmax()))
+    if eb is not None and eb.shape == want.shape:
+        lim = RTOL * np.abs(want) + EB_FACTOR * eb
+        bad = np.flatnonzero(err.ravel() > lim.ravel())
+        assert bad.size == 0, ("relative", int(bad[0]), float(err.ravel()[bad[0]]), float(np.abs(want).ravel()[bad[0]]),
+                               float(eb.ravel()[bad[0]]))
 
 
 def oracle_amps(wl_m, S, Ts, layers):
-    amps, _ = oracle.amplitudes(wl_m, S, Ts, flat(layers), nthreads=8)
-    return amps
+    amps, eb, _ = oracle.amplitudes(wl_m, S, Ts, flat(layers), nthreads=8, with_bound=True)
+    return Want(amps, eb)
 
 
 # ------------------------------------------------------------------ tables
@@ -428,30 +460,34 @@ def _brickwork(m, depth, seed):
     return layers
 
 
-def test_server_reports_planning_errors_per_request():
-    """A request the contraction cannot take (too many live cut versions)
-    completes with its own error; the requests around it are unaffected."""
+def test_server_falls_back_to_the_path_sum():
+    """A request the contraction cannot take (too many live cut versions) is
+    summed by the path-sum form on a planner thread and completes with the
+    oracle's amplitude (counted as a path-sum fallback); the requests around
+    it are unaffected and equal their batch values."""
     good = _served(6, seed=11)
     bad_layers = _brickwork(8, 40, seed=12)
     bad = lofp.Circuit(8, bad_layers)
     S = np.array([1, 1, 1, 1, 0, 0, 0, 0], dtype=np.int32)
     T = np.array([0, 0, 0, 0, 1, 1, 1, 1], dtype=np.int32)
+    with pytest.raises(lofp.LofpError) as ei:
+        lofp.amplitudes_multi([(bad, S, T)])
+    assert ei.value.status == lofp.ENOTSUP
     srv = lofp.Server(max_batch=8, streams=2)
     try:
         t_good = [srv.submit(c, r.S, r.T) for c, r in good]
         t_bad = srv.submit(bad, S, T)
         res = [srv.result(t) for t in t_good]
-        with pytest.raises(lofp.LofpError) as ei:
-            srv.result(t_bad)
-        assert ei.value.status == lofp.ENOTSUP
+        amp_bad, lat_bad, _ = srv.result(t_bad)
+        st = srv.stats()
     finally:
         srv.close()
+    assert st["pathsum_fallbacks"] == 1 and lat_bad >= 0
+    assert abs(amp_bad - oracle.amplitude(8, S, T, flat(bad_layers))) <= ATOL
+    assert amp_bad == bad.amplitudes(S, T[None, :], lofp.make_opts(method=lofp.METHOD_PATHSUM))[0]
     want = lofp.amplitudes_multi([(c, r.S, r.T) for c, r in good])
     for (amp, _, _), w in zip(res, want):
         assert amp == w
-    # the single-circuit call still answers it, by the path sum
-    a = bad.amplitudes(S, T[None, :])
-    assert abs(a[0] - oracle.amplitude(8, S, T, flat(bad_layers))) <= ATOL
 
 
 def test_circuit_setup_memory_is_reused_and_tables_grow():
@@ -688,14 +724,176 @@ def test_fp32_depth_first_products_within_bound():
         if len(circ) > 16:
             continue
         done += 1
-        want = oracle.amplitude(m, S, T, circ)
+        want, eb = oracle.amplitude(m, S, T, circ, with_bound=True)
         a_abs = oracle.absolute_form(m, S, T, circ)
         o32 = lofp.make_opts(method=lofp.METHOD_PATHSUM, precision=lofp.PREC_FP32, fwd_layer=0,
                              bwd_layer=len(layers))
         st = lofp.Stats()
         got = c.amplitudes(S, T[None, :], o32, st)[0]
         assert st.dfs_levels == len(circ)
-        assert abs(got - want) <= _growth(len(circ), n, fp32=True) * a_abs + 1e-300, (abs(got - want), a_abs)
+        if a_abs == 0:
+            # no valid path: exactly zero (the permanent's own rounding may not be)
+            assert got == 0 and abs(want) <= eb
+        else:
+            # the stated bound plus the oracle's own rounding bound
+            assert abs(got - want) <= _growth(len(circ), n, fp32=True) * a_abs + eb, (abs(got - want), a_abs)
         o64 = lofp.make_opts(method=lofp.METHOD_PATHSUM, fwd_layer=0, bwd_layer=len(layers))
         assert abs(c.amplitudes(S, T[None, :], o64)[0] - want) <= ATOL
     assert done >= 6
+
+
+# ------------------------------------------------- distant pairs, all outputs
+def _distant_layers(m, depth, rng):
+    """Random layers of disjoint pairs at distance 1 to 4."""
+    layers = []
+    for _ in range(depth):
+        free = list(range(m))
+        layer = []
+        for _ in range(m // 2):
+            a = int(rng.choice(free))
+            cand = [b for b in free if a < b <= a + 4]
+            if not cand:
+                continue
+            b = int(rng.choice(cand))
+            free.remove(a)
+            free.remove(b)
+            layer.append((a, b, float(rng.uniform(0, np.pi / 2)), float(rng.uniform(0, 2 * np.pi))))
+        layers.append(layer)
+    return layers
+
+
+@pytest.mark.parametrize("method", [lofp.METHOD_PATHSUM, lofp.METHOD_CONTRACT, lofp.METHOD_AUTO])
+def test_distant_pairs_match_oracle(method):
+    """Circuits whose layers connect modes up to four apart (compiled by the
+    library to adjacent splitters) against the oracle, which takes the
+    distant splitters as given (Ryser on their composed unitary)."""
+    rng = np.random.default_rng(51)
+    ran = 0
+    for m, D in ((6, 4), (8, 3), (10, 3)):
+        layers = _distant_layers(m, D, rng)
+        S = np.zeros(m, np.int32)
+        S[::2] = 1
+        n = int(S.sum())
+        Ts = np.zeros((40, m), np.int32)
+        for row in Ts:
+            for _ in range(n):
+                row[rng.integers(m)] += 1
+        c = lofp.Circuit(m, layers)
+        try:
+            got = c.amplitudes(S, Ts, lofp.make_opts(method=method))
+        except lofp.LofpError as e:
+            # the swap chains can make the contraction's state too large; the
+            # forced contraction then says so (AUTO takes the path sum)
+            assert method == lofp.METHOD_CONTRACT and e.status == lofp.ENOMEM, e
+            continue
+        ran += 1
+        check(got, oracle_amps(m, S, Ts, layers))
+    assert ran == 3 or (method == lofp.METHOD_CONTRACT and ran >= 1)
+
+
+def test_all_outputs_paper_protocol():
+    """Sec. III.A through the all-outputs call: every output of the four
+    6-mode inputs, in the oracle's pattern order; probabilities sum to one
+    and their total variation distance to the oracle's is below 1e-13."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_correctness_inputs.json")))
+    for k, case in enumerate(g["cases"]):
+        S, D = np.array(case["S"], np.int32), case["depth"]
+        layers = workloads.random_brickwork(g["m"], D, np.random.Generator(np.random.PCG64(60 + k)))
+        c = lofp.Circuit(g["m"], layers)
+        Ts, amps = c.all_outputs(S)
+        assert np.array_equal(Ts, np.array(oracle.all_patterns(g["m"], int(S.sum())), np.int32))
+        want = oracle_amps(g["m"], S, Ts, layers)
+        check(amps, want)
+        p, q = np.abs(amps) ** 2, np.abs(want) ** 2
+        assert abs(p.sum() - 1) < 1e-12
+        assert 0.5 * np.abs(p - q).sum() <= g["tvd_vs_ryser_max"]
+
+
+def test_all_outputs_distant_pairs_and_c2_size():
+    """All outputs of a 7-mode circuit with distant pairs (norm one, oracle
+    parity), and of the 16-mode, depth-8 workload's input: its 490314
+    patterns in passes, the norm within 1e-11 and a sample against the
+    oracle."""
+    rng = np.random.default_rng(71)
+    layers = _distant_layers(7, 4, rng)
+    S = np.array([1, 0, 2, 0, 1, 0, 0], np.int32)
+    c = lofp.Circuit(7, layers)
+    Ts, amps = c.all_outputs(S)
+    check(amps, oracle_amps(7, S, Ts, layers))
+    assert abs(np.sum(np.abs(amps) ** 2) - 1) < 1e-12
+    wl = workloads.make("c2", seed=0, batch=8)
+    c2 = lofp.Circuit(wl.m, wl.layers)
+    Ts2, amps2 = c2.all_outputs(wl.S)
+    assert Ts2.shape == (490314, wl.m) and np.all(Ts2.sum(axis=1) == wl.n)
+    assert abs(np.sum(np.abs(amps2) ** 2) - 1) < 1e-11
+    idx = np.random.default_rng(72).choice(len(Ts2), 48, replace=False)
+    check(amps2[idx], oracle_amps(wl.m, wl.S, Ts2[idx], wl.layers))
+
+
+# ------------------------------------------------ graph capture and the tuner
+def test_graph_replay_equals_eager_tuned_call():
+    """The whole call captured as a graph (split decided on the device, way of
+    contracting chosen by the tuner) replays bit-identical to the eager call
+    with the same tuned choice, with eager work on the same circuit and
+    synchronisations between replays; new T values in the captured buffer are
+    picked up; the tuned and the default way agree to 1e-14."""
+    import torch
+    wl = workloads.make("c2", seed=0)
+    c = lofp.Circuit(wl.m, wl.layers)
+    T = torch.from_numpy(np.ascontiguousarray(wl.Ts)).cuda()
+    opts = lofp.make_opts(method=lofp.METHOD_CONTRACT, autotune=True)
+    eager = torch.zeros(wl.batch, dtype=torch.complex128, device="cuda")
+    st = lofp.Stats()
+    c.amplitudes_device(wl.S, T, eager, opts, stats=st)
+    torch.cuda.synchronize()
+    assert st.tuned == 1
+    ref = eager.cpu().numpy()
+    idx = np.random.default_rng(90).choice(wl.batch, 32, replace=False)
+    check(ref[idx], oracle_amps(wl.m, wl.S, wl.Ts[idx], wl.layers))
+    check(ref, c.amplitudes(wl.S, wl.Ts, lofp.make_opts(method=lofp.METHOD_CONTRACT)), 1e-14)
+    out = torch.zeros(wl.batch, dtype=torch.complex128, device="cuda")
+    g = lofp.Graph(c, wl.S, T, out, opts)
+    try:
+        for r in range(4):
+            out.zero_()
+            g.launch()
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), ref), r
+            c.amplitudes(wl.S, wl.Ts[: 100 + 50 * r])   # eager work on the caller's circuit
+        # new patterns in the captured buffer
+        T2 = workloads.make("c2", seed=3).Ts
+        T.copy_(torch.from_numpy(np.ascontiguousarray(T2)))
+        g.launch()
+        torch.cuda.synchronize()
+        c.amplitudes_device(wl.S, T, eager, opts)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager.cpu().numpy())
+        check(out.cpu().numpy()[:16], oracle_amps(wl.m, wl.S, T2[:16], wl.layers))
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("name,batch", [("c2", 1), ("c5", 512), ("c3", 300)])
+def test_graph_small_and_other_workloads(name, batch):
+    """Captured calls for a single pattern (one contraction per pattern), the
+    32-mode batch and a bunched batch, each replayed twice against the eager
+    call."""
+    import torch
+    wl = workloads.make(name, seed=5, batch=batch)
+    c = lofp.Circuit(wl.m, wl.layers)
+    T = torch.from_numpy(np.ascontiguousarray(wl.Ts)).cuda()
+    out = torch.zeros(wl.batch, dtype=torch.complex128, device="cuda")
+    opts = lofp.make_opts(method=lofp.METHOD_CONTRACT)
+    ref = c.amplitudes(wl.S, wl.Ts, opts)
+    g = lofp.Graph(c, wl.S, T, out, opts)
+    try:
+        for _ in range(2):
+            out.zero_()
+            g.launch()
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), ref)
+    finally:
+        g.close()
+    check(ref[:32], oracle_amps(wl.m, wl.S, wl.Ts[:32], wl.layers))

@@ -50,8 +50,8 @@ def test_validation_errors():
         lofp.Circuit(4, [[(0, 1, 0.1, 0.1), (1, 2, 0.1, 0.1)]])
     assert e.value.status == lofp.EINVAL
     with pytest.raises(lofp.LofpError) as e:
-        lofp.Circuit(4, [[(0, 2, 0.1, 0.1)]])
-    assert e.value.status == lofp.ENOTSUP
+        lofp.Circuit(4, [[(0, 2, 0.1, 0.1), (2, 3, 0.1, 0.1)]])
+    assert e.value.status == lofp.EINVAL
     with pytest.raises(lofp.LofpError) as e:
         lofp.Circuit(4, [[(2, 1, 0.1, 0.1)]])
     assert e.value.status == lofp.EINVAL
@@ -131,3 +131,53 @@ def test_infeasible_when_photon_numbers_differ():
     T[0] += 1
     _, _, feas = c.bounds(wl.S, T)
     assert not feas
+
+
+def _distant_layers(m, depth, rng):
+    """Random layers of disjoint pairs at distance 1 to 4 (some layers hold
+    only adjacent pairs, some only distant ones)."""
+    layers = []
+    for _ in range(depth):
+        free = list(range(m))
+        layer = []
+        for _ in range(m // 2):
+            a = int(rng.choice(free))
+            cand = [b for b in free if a < b <= a + 4]
+            if not cand:
+                continue
+            b = int(rng.choice(cand))
+            free.remove(a)
+            free.remove(b)
+            layer.append((a, b, float(rng.uniform(0, np.pi / 2)), float(rng.uniform(0, 2 * np.pi))))
+        layers.append(layer)
+    return layers
+
+
+@pytest.mark.parametrize("m", [3, 5, 8, 12])
+def test_distant_pairs_compile_to_the_same_unitary(m):
+    """A splitter on distant modes is compiled to adjacent splitters (a chain
+    of theta = pi/2 splitters bringing the lower mode next to the upper one
+    and back): the compiled circuit's unitary, composed by the oracle, equals
+    the given circuit's; adjacent pairs pass through unchanged."""
+    import oracle
+    rng = np.random.default_rng(100 + m)
+    layers = _distant_layers(m, 5, rng)
+    assert any(b > a + 1 for l in layers for a, b, _, _ in l)
+    c = lofp.Circuit(m, layers)
+    comp = c.compiled_layers()
+    assert all(b == a + 1 for l in comp for a, b, _, _ in l)
+    flat = [bs for l in layers for bs in l]
+    cflat = [bs for l in comp for bs in l]
+    assert np.abs(oracle.compose(m, flat) - oracle.compose(m, cflat)).max() < 1e-14
+    # one extra splitter per step of the chain, there and back
+    assert len(cflat) == len(flat) + sum(2 * (b - a - 1) for a, b, _, _ in flat)
+    adjacent = [[(0, 1, 0.3, 0.4)], [(1, 2, 0.5, 0.6)]]
+    assert lofp.Circuit(3, adjacent).compiled_layers() == adjacent
+
+
+def test_distant_pairs_refuse_host_layer_queries():
+    c = lofp.Circuit(4, [[(0, 3, 0.2, 0.1)]])
+    for call in (lambda: c.light_cone(0, 0), lambda: c.bounds([1, 0, 0, 0], [0, 0, 0, 1])):
+        with pytest.raises(lofp.LofpError) as e:
+            call()
+        assert e.value.status == lofp.ENOTSUP
