@@ -255,7 +255,7 @@ def traffic_for(kernel: str):
         return None
     if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha16"]:
         return None
-    return rec["bytes_per_launch"]
+    return rec.get("bytes_per_launch", rec.get("bytes_per_step"))
 
 
 def contract_roofline(kernel, ms_k, transitions):
@@ -281,8 +281,9 @@ def pathsum_roofline(s0, avg):
     byts = 32.0 * s0["bfs_states"]
     achieved = byts / (ms_fwd * 1e-3) / 1e9 if ms_fwd > 0 else 0.0
     return {"kernel": "k_gate (forward)", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_ms": ms_fwd,
-            "algorithmic": "32 B per frontier state (one 16 B write, one 16 B read)"}
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for("k_gate"), "avg_ms": ms_fwd,
+            "algorithmic": "32 B per frontier state (one 16 B write, one 16 B read); achieved and traffic are "
+                           "per step (all forward launches of one call)"}
 
 
 def measure(lofp, circ, wl, T, out, stream, method, fwd, bwd, steps, warmup):

@@ -630,6 +630,7 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
         // a workspace sized by the S-side bound (no read-back)
         HIPCHK(ensure(c.d_ws, (size_t)B * 2 * a.max_states * sizeof(double2)));
         a.ws = c.d_ws.as<double2>();
+        a.lds_states = contract_lds_room(a.nvars, a.m);   // patterns whose own state fits keep it in LDS
     } else if (max_states > (1 << 22) || contract_lds_bytes(a, true) > 64 * 1024) {
         int *d_max = reinterpret_cast<int32_t *>(ctr + 5);
         HIPCHK(launch_contract_sizes(a, d_max, s));
@@ -641,9 +642,11 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
         if (contract_lds_bytes(a, true) > 64 * 1024) {
             HIPCHK(ensure(c.d_ws, (size_t)B * 2 * a.max_states * sizeof(double2)));
             a.ws = c.d_ws.as<double2>();
+            a.lds_states = contract_lds_room(a.nvars, a.m);
         }
     }
     if (state_limit > 0 && a.max_states > state_limit) a.max_states = state_limit;
+    if (a.lds_states > a.max_states) a.lds_states = a.max_states;   // the limit holds in LDS too
     tm.mark();
     HIPCHK(launch_contract(a, s));
     tm.mark();
@@ -699,7 +702,7 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
     HIPCHK(ensure(c.d_kslot, (size_t)2 * B * sizeof(int)));
     HIPCHK(ensure(c.d_kof, kl.slot_key_bytes));
     HIPCHK(ensure(c.d_krep, (size_t)2 * kKeySubs * B * sizeof(int)));
-    HIPCHK(ensure(c.d_kcnt, (2 * kKeySubs + 4) * sizeof(int)));   // as the device-decided form lays it out
+    HIPCHK(ensure(c.d_kcnt, (2 * kKeySubs + 8) * sizeof(int)));   // as the device-decided form lays it out
     HIPCHK(ensure(c.d_khull, kl.hull_bytes));
     HIPCHK(ensure(c.d_klohi, (size_t)2 * 2 * B * span * sizeof(int16_t)));
     KeyArgs ka{};
@@ -909,7 +912,7 @@ lofp_status run_contract_split_dev(lofp_circuit_s &c, const int32_t *S, int n, i
     HIPCHK(ensure(c.d_kslot, (size_t)2 * B * sizeof(int)));
     HIPCHK(ensure(c.d_kof, kl.slot_key_bytes));
     HIPCHK(ensure(c.d_krep, (size_t)2 * kKeySubs * B * sizeof(int)));
-    HIPCHK(ensure(c.d_kcnt, (2 * kKeySubs + 4) * sizeof(int)));   // claim counts, then the decision words
+    HIPCHK(ensure(c.d_kcnt, (2 * kKeySubs + 8) * sizeof(int)));   // claim counts, then the decision words
     HIPCHK(ensure(c.d_khull, kl.hull_bytes));
     HIPCHK(ensure(c.d_klohi, (size_t)2 * 2 * B * span * sizeof(int16_t)));
     HIPCHK(ensure(c.d_korder, (size_t)2 * 2 * B * sizeof(int)));
@@ -966,22 +969,21 @@ lofp_status run_contract_split_dev(lofp_circuit_s &c, const int32_t *S, int n, i
     const int lds_states = (int)std::min<int64_t>(mx, room);
     const bool any_lds = lds_states > 0;
     const size_t lds_bytes = contract_job_lds_bytes(c.nvars, m, any_lds ? lds_states : 0, any_lds);
+    // a grid of the blocks that can be resident, taking the jobs, largest
+    // first, from a counter: no block waits for a job that does not exist,
+    // and each block keeps one workspace slice for the jobs whose state does
+    // not fit LDS
+    const int grid =
+        std::max(1, std::min(2 * B, contract_multi_resident_blocks(lds_bytes, any_lds ? lds_states : mx)));
     MultiOverride ov{mx, nullptr, nullptr, fin_cap, lds_states, ka.order};
     ov.njobs = ka.ctl + 1;
+    ov.next = ka.ctl + 4;
     if (lds_states < mx) {
-        // jobs whose state does not fit LDS share a pool of workspace slices,
-        // one per job that can be resident
-        const int R = contract_multi_resident_blocks(lds_bytes, any_lds ? lds_states : mx);
-        HIPCHK(ensure(c.d_ws, (size_t)R * 2 * mx * sizeof(double2)));
-        const size_t before = c.d_wspool.cap;
-        HIPCHK(ensure(c.d_wspool, (size_t)R * sizeof(int)));
-        if (c.d_wspool.cap != before) HIPCHK(launch_fill_i32(c.d_wspool.as<int32_t>(), c.d_wspool.cap / sizeof(int), 0, s));
+        HIPCHK(ensure(c.d_ws, (size_t)grid * 2 * mx * sizeof(double2)));
         ov.ws_base = c.d_ws.as<double2>();
-        ov.ws_pool = c.d_wspool.as<int>();
-        ov.ws_slots = R;
     }
     tm.mark();
-    HIPCHK(launch_contract_multi(2 * B, c.d_jobs.as<ContractJob>(), lds_bytes, any_lds ? lds_states : mx, any_lds,
+    HIPCHK(launch_contract_multi(grid, c.d_jobs.as<ContractJob>(), lds_bytes, any_lds ? lds_states : mx, any_lds,
                                  fp32 != 0, ctr + 3, reinterpret_cast<int32_t *>(ctr + 4), s, ov,
                                  st != nullptr && count_work));
     pa.S = c.d_S.as<int32_t>();
@@ -1002,6 +1004,7 @@ lofp_status run_contract_split_dev(lofp_circuit_s &c, const int32_t *S, int n, i
     if (!pp_lds) {
         HIPCHK(ensure(c.d_ws2, pp_ws));
         pa.ws = c.d_ws2.as<double2>();
+        pa.lds_states = std::min(contract_lds_room(pa.nvars, pa.m), pp_states);
     }
     HIPCHK(launch_contract(pa, s));
     tm.mark();
@@ -1538,7 +1541,7 @@ lofp_status lofp_circuit_destroy(lofp_circuit c)
                       &c->d_count, &c->d_slot_stage, &c->d_off, &c->d_coff, &c->d_fa, &c->d_fb, &c->d_ba, &c->d_bb,
                       &c->d_levels, &c->d_tab_mid, &c->d_counters, &c->d_T, &c->d_out, &c->d_ws,
                       &c->d_cfg, &c->d_rankb, &c->d_ktab, &c->d_kslot, &c->d_kof, &c->d_krep, &c->d_kcnt,
-                      &c->d_khull, &c->d_klohi, &c->d_kinf, &c->d_jobs, &c->d_kstate, &c->d_korder, &c->d_wspool, &c->d_ws2};
+                      &c->d_khull, &c->d_klohi, &c->d_kinf, &c->d_jobs, &c->d_kstate, &c->d_korder, &c->d_ws2};
     // pooled blocks are reused at once, so no work of this circuit may be left
     if (c->dev_ready || !c->blocks.empty()) (void)hipDeviceSynchronize();
     for (DevBuf *b : bufs) release(*b);

@@ -27,6 +27,7 @@
 // over the new state, each entry gathered in a fixed order; the final sum is
 // compensated and combined in a fixed order.  With unit weights the same
 // program counts the valid paths.
+#include <algorithm>
 #include <utility>
 
 #include "lofp_device.h"
@@ -392,13 +393,21 @@ __device__ __forceinline__ void step_entries(const StepDesc &d, const double2 *_
         for (int i1 = 0; i1 < srad1; ++i1) {
             const int gx = bx + cx1 * i1, gy = by + cy1 * i1, gn = bn + cn1 * i1;
             const int ob = base_old + i1 * sstr1;
+            // the splitter's photon numbers and the table offset of sector N,
+            // sum_{k<N} (k+1)^2 = N(N+1)(2N+1)/6, stepped along i0 (the
+            // polynomial is an integer for every N, so the recurrence
+            // off(N+1) = off(N) + (N+1)^2 also holds through negative N,
+            // where the visit reads the zero slot)
+            int N = gn, x1 = gx, y1 = gy;
+            int off = N * (N + 1) * (2 * N + 1) / 6;
 #pragma unroll 2
             for (int i0 = 0; i0 < srad0; ++i0) {
                 const double2 prev = bufA[ob + i0 * sstr0];
-                const int N = gn + cn0 * i0, x1 = gx + cx0 * i0, y1 = gy + cy0 * i0;
                 const bool ok = (x1 < y1 ? x1 : y1) >= 0 && (x1 > y1 ? x1 : y1) <= N;
-                const unsigned un = (unsigned)N;
-                visit(prev, ok, un * (un + 1u) * (2u * un + 1u) / 6u + (unsigned)x1 * (un + 1u) + (unsigned)y1);
+                visit(prev, ok, (unsigned)(off + x1 * (N + 1) + y1));
+                const int Nn = N + cn0;
+                off += cn0 > 0 ? Nn * Nn : (cn0 < 0 ? -(N * N) : 0);
+                N = Nn; x1 += cx0; y1 += cy0;
             }
         }
         bufB[e] = acc;
@@ -601,13 +610,10 @@ __device__ void contract_run(const ContractJob &g, unsigned char *smem, unsigned
     if (STATS) atomicAdd(stat_transitions, trans);
 }
 
-// Single circuit, one block per pattern.
+// The contraction of pattern p of a single-circuit launch.
 template <bool COUNT, bool F32, bool LDS_STATE, int BS, bool STATS>
-__global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
+__device__ void contract_pattern(const ContractArgs &g, int p, unsigned char *smem)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    if (g.skip && *g.skip) return;   // the batch went to the split contraction
-    const int p = blockIdx.x;
     const int nc = g.m - 1, span = (g.D + 1) * nc;
     ContractJob j;
     j.m = g.m; j.n = g.n; j.D = g.D; j.nvars = g.nvars; j.nsteps = g.nsteps;
@@ -623,29 +629,39 @@ __global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
     j.stats = g.stats;
     j.ovf = nullptr;
     if (!contract_setup<BS>(j, smem)) return;
+    if (!LDS_STATE && g.lds_states > 0) {
+        // this pattern's own largest state decides: LDS when it fits, else
+        // its workspace slice
+        if (job_max_state<BS>(j, smem) <= g.lds_states) {
+            j.max_states = g.lds_states;
+            contract_run<COUNT, F32, true, BS, STATS>(j, smem, g.stat_transitions, g.overflow);
+        } else {
+            contract_run<COUNT, F32, false, BS, STATS>(j, smem, g.stat_transitions, g.overflow);
+        }
+        return;
+    }
     contract_run<COUNT, F32, LDS_STATE, BS, STATS>(j, smem, g.stat_transitions, g.overflow);
 }
 
-// Many circuits, one block per job (in the order ov.order gives: the
-// largest jobs first, so that every CU starts one of them).
-// Waves per SIMD a multi-job block size is compiled for: 512-thread blocks
-// run three jobs (24 waves) per CU.
-template <int BS> constexpr int multi_waves_per_simd() { return BS >= 512 ? 6 : 1; }
-
-// ABS: the absolute form (sum over paths of the product of |Re W| + |Im W|),
-// which bounds the rounding error of the FP32-product form.
-template <bool F32, bool LDS_STATE, int BS, bool STATS, bool ABS>
-__global__ __launch_bounds__(BS, multi_waves_per_simd<BS>()) void k_contract_multi(const ContractJob *__restrict__ jobs,
-                                                       unsigned long long *stat_transitions, int32_t *overflow,
-                                                       MultiOverride ov)
+// Single circuit, one block per pattern.
+template <bool COUNT, bool F32, bool LDS_STATE, int BS, bool STATS>
+__global__ __launch_bounds__(BS) void k_contract(ContractArgs g)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    if (ov.njobs && (int)blockIdx.x >= *ov.njobs) return;   // launched for the worst case
-    const int jb = ov.order ? ov.order[blockIdx.x] : (int)blockIdx.x;
+    if (g.skip && *g.skip) return;   // the batch went to the split contraction
+    contract_pattern<COUNT, F32, LDS_STATE, BS, STATS>(g, (int)blockIdx.x, smem);
+}
+
+// One job of a multi-job launch (job jb; `slice` picks its workspace slice).
+template <bool F32, bool LDS_STATE, int BS, bool STATS, bool ABS>
+__device__ void multi_job(const ContractJob *__restrict__ jobs, int jb, int slice,
+                          unsigned long long *stat_transitions, int32_t *overflow, const MultiOverride &ov,
+                          unsigned char *smem)
+{
     ContractJob j = jobs[jb];
     if (ov.max_states > 0) {
         j.max_states = ov.max_states;
-        j.ws = ov.ws_base && !ov.ws_pool ? ov.ws_base + (int64_t)jb * 2 * ov.max_states : nullptr;
+        j.ws = ov.ws_base ? ov.ws_base + (int64_t)slice * 2 * ov.max_states : nullptr;
         if (ov.state_base) {
             j.state_out = ov.state_base + (int64_t)jb * ov.state_cap;
             j.state_cap = ov.state_cap;
@@ -661,34 +677,50 @@ __global__ __launch_bounds__(BS, multi_waves_per_simd<BS>()) void k_contract_mul
             // the LDS its state would have used stages the step programs
             unsigned char *stg = (size_t)ov.lds_states * 2 * sizeof(double2) >= kDescChunk * sizeof(ContractStep)
                                      ? smem + job_lds_head(j.nvars, j.m - 1) : nullptr;
-            // a workspace slice from the pool: at most ws_slots jobs are
-            // resident, so a free slice exists; the probe count is bounded
-            // all the same (a job left without one reports an overflow)
-            __shared__ int s_slot;
-            if (ov.ws_pool) {
-                if (threadIdx.x == 0) {
-                    int got = -1;
-                    for (int p = 0; p < 4 * ov.ws_slots && got < 0; ++p) {
-                        const int sl = (int)((blockIdx.x + (unsigned)p) % (unsigned)ov.ws_slots);
-                        if (atomicCAS(&ov.ws_pool[sl], 0, 1) == 0) got = sl;
-                    }
-                    s_slot = got;
-                }
-                __syncthreads();
-                j.ws = s_slot >= 0 ? ov.ws_base + (int64_t)s_slot * 2 * ov.max_states : nullptr;
-            }
             contract_run<ABS, F32 || ABS, false, BS, STATS>(j, smem, stat_transitions, overflow, stg);
-            if (ov.ws_pool) {
-                __syncthreads();   // every lane is done with the slice
-                if (threadIdx.x == 0 && s_slot >= 0) {
-                    __threadfence();
-                    atomicExch(&ov.ws_pool[s_slot], 0);
-                }
-            }
         }
         return;
     }
     contract_run<ABS, F32 || ABS, LDS_STATE, BS, STATS>(j, smem, stat_transitions, overflow);
+}
+
+// Many circuits, one block per job (in the order ov.order gives: the
+// largest jobs first, so that every CU starts one of them); or, with
+// ov.next set, a grid of the blocks that can be resident: block b takes job
+// b and then further jobs from that counter, in the same order, until
+// *ov.njobs are taken, each block using workspace slice blockIdx.x.
+// Waves per SIMD a multi-job block size is compiled for: 512-thread blocks
+// run three jobs (24 waves) per CU.
+template <int BS> constexpr int multi_waves_per_simd() { return BS >= 512 ? 6 : 1; }
+
+// ABS: the absolute form (sum over paths of the product of |Re W| + |Im W|),
+// which bounds the rounding error of the FP32-product form.
+template <bool F32, bool LDS_STATE, int BS, bool STATS, bool ABS>
+__global__ __launch_bounds__(BS, multi_waves_per_simd<BS>()) void k_contract_multi(const ContractJob *__restrict__ jobs,
+                                                       unsigned long long *stat_transitions, int32_t *overflow,
+                                                       MultiOverride ov)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (ov.next) {
+        // block b takes job b, then jobs gridDim.x, gridDim.x + 1, ... from
+        // the counter: no atomic for the first round, and a block past the
+        // job count returns at once
+        __shared__ int s_k;
+        const int nj = *ov.njobs;
+        int k = (int)blockIdx.x;
+        for (;;) {
+            if (k >= nj) return;   // every block ends here once the jobs are taken
+            multi_job<F32, LDS_STATE, BS, STATS, ABS>(jobs, ov.order ? ov.order[k] : k, (int)blockIdx.x,
+                                                      stat_transitions, overflow, ov, smem);
+            __syncthreads();   // the job is done with LDS and s_k
+            if (threadIdx.x == 0) s_k = (int)gridDim.x + atomicAdd(ov.next, 1);
+            __syncthreads();
+            k = s_k;
+        }
+    }
+    if (ov.njobs && (int)blockIdx.x >= *ov.njobs) return;
+    const int jb = ov.order ? ov.order[blockIdx.x] : (int)blockIdx.x;
+    multi_job<F32, LDS_STATE, BS, STATS, ABS>(jobs, jb, jb, stat_transitions, overflow, ov, smem);
 }
 
 // Largest state of each job's program under its intervals.
@@ -866,23 +898,24 @@ hipError_t launch_contract_sizes(const ContractArgs &a, int *max_size, hipStream
 
 int contract_multi_resident_blocks(size_t lds_bytes, int max_states)
 {
-    int dev = 0, cus = 0, per_cu = 0;
+    int dev = 0, cus = 0, lds_cu = 0, thr_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         cus = 256;
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        lds_cu <= 0)
+        lds_cu = 160 * 1024;
+    if (hipDeviceGetAttribute(&thr_cu, hipDeviceAttributeMaxThreadsPerMultiProcessor, dev) != hipSuccess ||
+        thr_cu <= 0)
+        thr_cu = 2048;
     const bool wide = contract_block_size(max_states) != 64;
     const int bs = wide ? 512 : 64;
-    // the instantiations that take the global-state path differ only in
-    // template flags, not in resources that bound residency; query one
-    hipError_t e = wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &per_cu, reinterpret_cast<const void *>(k_contract_multi<false, true, 512, false, false>), bs,
-                              lds_bytes)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &per_cu, reinterpret_cast<const void *>(k_contract_multi<false, true, 64, false, false>), bs,
-                              lds_bytes);
-    if (e != hipSuccess || per_cu <= 0) per_cu = 2048 / bs;   // waves per CU bound
-    // with a margin: variants compiled with other flags may use fewer registers
-    return cus * per_cu * 2;
+    // blocks per CU: by LDS, by waves (the launch bound of a 512-thread
+    // block allows six waves per SIMD, four SIMDs per CU), by threads
+    int per_cu = lds_bytes > 0 ? (int)((size_t)lds_cu / lds_bytes) : thr_cu / bs;
+    per_cu = std::min(per_cu, thr_cu / bs);
+    if (wide) per_cu = std::min(per_cu, 4 * multi_waves_per_simd<512>() / (512 / 64));
+    return cus * std::max(per_cu, 1);
 }
 
 __global__ void k_fill_i32(int32_t *p, size_t n, int32_t v)
@@ -921,7 +954,7 @@ size_t contract_lds_bytes(const ContractArgs &a, bool state_in_lds)
 template <bool COUNT, bool F32, bool LDS_STATE>
 static void launch_contract_t(const ContractArgs &a, size_t dyn, hipStream_t stream)
 {
-    const bool wide = contract_block_size(a.max_states) != 64;
+    const bool wide = a.block ? a.block != 64 : contract_block_size(a.max_states) != 64;
     if (a.stats) {
         if (wide) hipLaunchKernelGGL((k_contract<COUNT, F32, LDS_STATE, 256, true>), dim3(a.B), dim3(256), dyn, stream, a);
         else hipLaunchKernelGGL((k_contract<COUNT, F32, LDS_STATE, 64, true>), dim3(a.B), dim3(64), dyn, stream, a);
@@ -935,7 +968,9 @@ hipError_t launch_contract(const ContractArgs &a, hipStream_t stream)
 {
     if (a.B == 0) return hipSuccess;
     const bool in_lds = a.ws == nullptr;
-    const size_t dyn = contract_lds_bytes(a, in_lds);
+    size_t dyn = contract_lds_bytes(a, in_lds);
+    if (!in_lds && a.lds_states > 0)   // per-pattern choice: room for LDS states too
+        dyn = contract_job_lds_bytes(a.nvars, a.m, a.lds_states, true);
     if (dyn > 64 * 1024) return hipErrorInvalidValue;
     if (a.count_only) {
         if (in_lds) launch_contract_t<true, false, true>(a, dyn, stream);

@@ -183,7 +183,7 @@ struct lofp_circuit_s {
     DevBuf d_S, d_lo, d_hi, d_inf, d_C, d_E, d_count, d_slot_stage, d_off, d_coff, d_fa, d_fb, d_ba, d_bb;
     DevBuf d_levels, d_tab_mid, d_counters, d_T, d_out, d_ws, d_cfg, d_rankb;
     DevBuf d_ktab, d_kslot, d_kof, d_krep, d_kcnt, d_khull, d_klohi, d_kinf, d_jobs, d_kstate, d_korder;
-    DevBuf d_wspool, d_ws2;                // workspace pool flags; per-pattern workspace
+    DevBuf d_ws2;                          // per-pattern workspace of the device-decided split
     std::vector<std::shared_ptr<lofp::host::SharedBlock>> blocks;   // pooled set-up blocks in use
     int32_t *h_pin = nullptr;              // small pinned readback buffer
     lofp::KeyLayoutState klay;             // layout of the key table and hulls

@@ -225,6 +225,7 @@ __global__ __launch_bounds__(256) void k_key_jobs_dev(KeyArgs a, ContractJob top
         a.ctl[1] = split ? ntop + nbot : 0;
         a.ctl[2] = ntop;
         a.ctl[3] = nbot;
+        a.ctl[4] = 0;   // the contraction's job counter
     }
     if (w >= ntop + nbot) return;
     const int half = w >= ntop, k = half ? w - ntop : w;

@@ -209,6 +209,9 @@ struct ContractArgs {
     int32_t *overflow;
     int stats;                // count transitions into stat_transitions
     const int32_t *skip;      // if set and nonzero: do nothing (the batch was split)
+    int lds_states;           // > 0 with ws set: a pattern whose own largest state
+                              // fits this many entries keeps it in LDS, others in ws
+    int block;                // threads per block: 64 or 256 (0: by max_states)
 };
 hipError_t launch_contract(const ContractArgs &a, hipStream_t stream);
 
@@ -244,10 +247,10 @@ struct MultiOverride {
     int lds_states;              // > 0: a job whose own largest state fits this
                                  // many entries keeps it in LDS, others in ws
     const int *order;            // block b runs job order[b] (nullptr: job b)
-    const int *njobs;            // if set: blocks at or past *njobs do nothing
-    int *ws_pool;                // if set: a job needing ws claims one of
-    int ws_slots;                // ws_slots slices (flags 0 = free) instead of
-                                 // using slice `job`
+    const int *njobs;            // if set: *njobs jobs (blocks past it do nothing)
+    int *next;                   // if set: block b takes job b, then jobs
+                                 // grid + (this counter, zero at launch) until
+                                 // *njobs are taken; block b uses workspace slice b
 };
 struct BoundsJob {
     int m, D, n;
@@ -267,8 +270,8 @@ hipError_t launch_contract_multi(int count, const ContractJob *jobs, size_t lds_
                                  bool abs = false);
 // Largest state over the jobs (one thread per job), atomically maxed into *mx.
 hipError_t launch_multi_sizes(int count, const ContractJob *jobs, int *mx, hipStream_t stream);
-// Most blocks of the split contraction kernel that can be resident at once
-// on the current device (sizes a workspace pool claimed per resident job).
+// Blocks of the multi-job contraction kernel that can be resident at once on
+// the current device (the grid of its job-queue form).
 int contract_multi_resident_blocks(size_t lds_bytes, int max_states);
 // Fills n ints with v (a kernel, so that a captured call records no memset).
 hipError_t launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t stream);
@@ -298,7 +301,8 @@ struct KeyArgs {
     int *order;                    // [2B] jobs by decreasing cost bucket
     // decided on the device (launches sized for the worst case, no host
     // read-back): nullptr in the host-sized form
-    int *ctl;                      // [4] split?, jobs, top keys, bottom keys
+    int *ctl;                      // [8] split?, jobs, top keys, bottom keys,
+                                   // next job to take (zeroed with the jobs)
     int small_min, small_max;      // batch sizes split without shared halves
 };
 // Insert every pattern's two half-rows; keys are numbered as their slots are
@@ -343,6 +347,13 @@ struct JoinArgs {
 };
 hipError_t launch_join(const JoinArgs &a, hipStream_t stream);
 size_t contract_job_lds_bytes(int nvars, int m, int max_states, bool state_in_lds);
+// State entries per buffer that fit in 64 KiB of LDS beside a job's fixed
+// LDS (the per-pattern choice of LDS or workspace uses it).
+inline int contract_lds_room(int nvars, int m)
+{
+    const size_t fixed = contract_job_lds_bytes(nvars, m, 0, true), cap = 64 * 1024;
+    return fixed < cap ? (int)((cap - fixed) / (2 * sizeof(double2))) : 0;
+}
 // LDS a block may allocate on the current device (64 KiB if the query fails)
 size_t max_lds_per_block();
 // Threads per contraction block for a largest state of max_states entries:

@@ -11,6 +11,7 @@
 // overlap on a device race.  The circuit's tables and step program must
 // already be on the device (set up by an earlier call of the ordinary
 // entry points for at least this photon number).
+#include <algorithm>
 #include <mutex>
 #include <string>
 
@@ -133,6 +134,7 @@ extern "C" lofp_status lofp_amplitudes_device_noalloc(lofp_circuit c, const int3
     a.hi = hi;
     a.infeasible = inf;
     a.ws = in_lds ? nullptr : reinterpret_cast<double2 *>(base + off_ws);
+    a.lds_states = in_lds ? 0 : std::min(contract_lds_room(a.nvars, a.m), a.max_states);
     a.stat_transitions = ctr + 3;
     a.overflow = reinterpret_cast<int32_t *>(ctr + 4);
     SVals sv{};
