@@ -1336,7 +1336,8 @@ lofp_status run_pathsum(lofp_circuit_s &c, const int32_t *S, int n, int B, const
             if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
                 ncu = prop.multiProcessorCount;
         }
-        const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / std::max<size_t>(lds, 1)));
+        const int occ = dfs_blocks_per_cu(a);
+        const int per_cu = occ > 0 ? occ : (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / std::max<size_t>(lds, 1)));
         const int64_t grid = std::min<int64_t>((int64_t)ncu * per_cu, std::max(gridp(sf), 1));
         tm.mark();  // 4
         HIPCHK(launch_dfs(a, (int)std::max<int64_t>(grid, 1), s));

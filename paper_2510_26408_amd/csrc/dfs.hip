@@ -314,9 +314,45 @@ __global__ __launch_bounds__(kDfsBlock) void k_dfs(DfsArgs g)
     atomicAdd(g.stat_edges, edges + leaves);
 }
 
+// Resident blocks per CU of the k_dfs instantiation a launch would use, with
+// `lds` bytes of dynamic LDS (0 when the runtime cannot say).
+template <bool FP32, bool TAB_LDS>
+static int dfs_occupancy_t(const DfsArgs &a, size_t lds)
+{
+    const int nc = a.m - 1;
+    int nb = 0;
+    hipError_t e;
+    if (nc <= 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_dfs<2, FP32, TAB_LDS>, kDfsBlock, lds);
+    else if (nc <= 16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_dfs<4, FP32, TAB_LDS>, kDfsBlock, lds);
+    else if (nc <= 24) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_dfs<6, FP32, TAB_LDS>, kDfsBlock, lds);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_dfs<8, FP32, TAB_LDS>, kDfsBlock, lds);
+    return e == hipSuccess ? nb : 0;
+}
+
+static int dfs_occupancy(const DfsArgs &a, bool tab_lds, size_t lds)
+{
+    if (a.fp32_products) return tab_lds ? dfs_occupancy_t<true, true>(a, lds) : dfs_occupancy_t<true, false>(a, lds);
+    return tab_lds ? dfs_occupancy_t<false, true>(a, lds) : dfs_occupancy_t<false, false>(a, lds);
+}
+
+// The middle gates' tables go to LDS only when that costs no resident
+// blocks: the walk is bound by the latency of its reads, and more waves per
+// CU hide more of it than the faster LDS table read saves (tables read
+// through the vector caches with 7 blocks per CU ran the c2 middle 1.57x
+// faster than LDS tables with 4).
 static bool dfs_tables_in_lds(const DfsArgs &a)
 {
-    return dfs_layout(a.tab_len, a.levels, (a.m - 1) * table_cols(a.n)).total <= 64 * 1024;
+    const int tsz = (a.m - 1) * table_cols(a.n);
+    const size_t with = dfs_layout(a.tab_len, a.levels, tsz).total;
+    if (with > 64 * 1024) return false;
+    const size_t without = dfs_layout(0, a.levels, tsz).total;
+    return dfs_occupancy(a, true, with) >= dfs_occupancy(a, false, without);
+}
+
+int dfs_blocks_per_cu(const DfsArgs &a)
+{
+    const bool tl = dfs_tables_in_lds(a);
+    return dfs_occupancy(a, tl, dfs_layout(tl ? a.tab_len : 0, a.levels, (a.m - 1) * table_cols(a.n)).total);
 }
 
 size_t dfs_lds_bytes(const DfsArgs &a)

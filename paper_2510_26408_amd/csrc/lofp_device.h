@@ -146,6 +146,7 @@ constexpr int kMaxDfsGates = 16;   // splitters enumerated depth-first (LDS stac
 constexpr int kDfsBlock = 128;
 hipError_t launch_dfs(const DfsArgs &a, int grid, hipStream_t stream);
 size_t dfs_lds_bytes(const DfsArgs &a);
+int dfs_blocks_per_cu(const DfsArgs &a);   // resident k_dfs blocks per CU (0: unknown)
 
 // a3/a4: per frontier entry, its packed cut values (cfg_words words of four
 // 8-bit cut values) and its rank in the backward stage's state space.
