@@ -113,10 +113,13 @@ __host__ __device__ inline DfsLds dfs_layout(int tab_len, int levels, int tsz)
 {
     DfsLds L;
     size_t o = 0;
+    // the stacks hold levels 0 .. levels-2: the last level's outputs are
+    // leaves, summed in place, never pushed
+    const size_t depth = levels > 1 ? (size_t)(levels - 1) : 0;
     L.tab = o; o += (size_t)tab_len * 16;
-    L.stP = o; o += (size_t)levels * kDfsBlock * 16;
+    L.stP = o; o += depth * kDfsBlock * 16;
     L.lev = o; o += (size_t)levels * 16;
-    L.stM = o; o += (size_t)levels * kDfsBlock * 8;
+    L.stM = o; o += depth * kDfsBlock * 8;
     L.LH = o; o += (size_t)levels * 8;
     L.E = o; o += (size_t)tsz * 4;
     L.total = (o + 15) & ~(size_t)15;
