@@ -138,7 +138,7 @@ def main():
     res["config"]["method_used"] = "contract" if used == lofp.METHOD_CONTRACT else "pathsum"
     if used == lofp.METHOD_CONTRACT:
         kname = "k_contract_multi" if s0["split_top_keys"] > 0 else "k_contract"
-        res["roofline"] = contract_roofline(kname, avg("ms_contract"), s0["transitions"])
+        res["roofline"] = contract_roofline(kname, avg("ms_contract"), s0["transitions"], args.config)
         res["split_keys"] = [s0["split_top_keys"], s0["split_bottom_keys"]]
         res["max_state"] = s0["max_state"]
         # evaluated work beside the represented paths: transitions per second
@@ -146,7 +146,7 @@ def main():
         res["transitions_per_step"] = s0["transitions"]
         res["transitions_per_s"] = s0["transitions"] / (ms * 1e-3)
     else:
-        res["roofline"] = pathsum_roofline(s0, avg)
+        res["roofline"] = pathsum_roofline(s0, avg, args.config)
         res["leaves_per_s"] = leaves / (ms * 1e-3)
         res["edges_per_s"] = edges / (ms * 1e-3)
     if args.calib_copy_mib > 0:
@@ -243,9 +243,11 @@ def measure_graph(lofp, circ, wl, T, out, stream, steps, warmup):
             "produced": produced}
 
 
-def traffic_for(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the kernel's source changed since the counters were taken."""
+def traffic_for(kernel: str, key: str):
+    """HBM bytes per launch (or per step, where the record says so) from the
+    committed rocprofv3 counter summary of `kernel` on workload `key`, or None
+    when there is no record for that workload or the kernel's source changed
+    since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -253,38 +255,37 @@ def traffic_for(kernel: str):
         src = open(os.path.join(ROOT, rec["source"]), "rb").read()
     except (OSError, KeyError, ValueError):
         return None
-    if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha16"]:
+    if rec.get("key") != key or hashlib.sha256(src).hexdigest()[:16] != rec["source_sha16"]:
         return None
     return rec.get("bytes_per_launch", rec.get("bytes_per_step"))
 
 
-def contract_roofline(kernel, ms_k, transitions):
+def contract_roofline(kernel, ms_k, transitions, key):
     # one complex FP64 multiply-add (8 flops) per state transition
     flops = 8.0 * transitions
     achieved = flops / (ms_k * 1e-3) / 1e12 if ms_k > 0 else 0.0
     return {"kernel": kernel, "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic_for(kernel),
+            "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic_for(kernel, key),
             "avg_ms": ms_k, "algorithmic": "8 FP64 flops (complex multiply-add) per contraction transition "
                                            "with a nonzero source"}
 
 
-def pathsum_roofline(s0, avg):
+def pathsum_roofline(s0, avg, name):
     ms_dfs, ms_fwd = avg("ms_dfs"), avg("ms_forward")
+    key = f"{name}/pathsum/{s0['fwd_layer']}-{s0['bwd_layer']}"
     if ms_dfs >= ms_fwd and ms_dfs > 0:
         flops = 6.0 * s0["dfs_edges"] + 8.0 * s0["dfs_leaves"]
         achieved = flops / (ms_dfs * 1e-3) / 1e12
-        # the committed counters were taken with the frontiers at layers 5 and 6
-        split = (s0.get("fwd_layer"), s0.get("bwd_layer")) == (5, 6)
         return {"kernel": "k_dfs", "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                "traffic": traffic_for("k_dfs") if split else None, "avg_ms": ms_dfs,
+                "traffic": traffic_for("k_dfs", key), "avg_ms": ms_dfs,
                 "algorithmic": "6 FP64 flops per tree edge (complex product) + 8 per leaf"}
     # forward frontier: per produced state one 16 B write plus one 16 B read of
     # each predecessor (counted once: 32 B per state)
     byts = 32.0 * s0["bfs_states"]
     achieved = byts / (ms_fwd * 1e-3) / 1e9 if ms_fwd > 0 else 0.0
     return {"kernel": "k_gate (forward)", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for("k_gate"), "avg_ms": ms_fwd,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for("k_gate", key), "avg_ms": ms_fwd,
             "algorithmic": "32 B per frontier state (one 16 B write, one 16 B read); achieved and traffic are "
                            "per step (all forward launches of one call)"}
 
@@ -338,14 +339,14 @@ def run_variant(lofp, workloads, torch, dev, stream, name, method, steps=5, fwd=
         out["transitions"] = s0["transitions"]
         out["transitions_per_s"] = s0["transitions"] / (ms * 1e-3)
         kname = "k_contract_multi" if s0["split_top_keys"] > 0 else "k_contract"
-        out["roofline"] = contract_roofline(kname, avg("ms_contract"), s0["transitions"])
+        out["roofline"] = contract_roofline(kname, avg("ms_contract"), s0["transitions"], name)
     else:
         out.update({k: s0[k] for k in ("fwd_layer", "bwd_layer", "dfs_levels", "frontier_states",
                                         "backward_states", "bfs_states", "dfs_leaves", "dfs_edges")})
         out["leaves_per_s"] = s0["dfs_leaves"] / (ms * 1e-3)
         out["edges_per_s"] = s0["dfs_edges"] / (ms * 1e-3)
         out["bfs_states_per_s"] = s0["bfs_states"] / (ms * 1e-3)
-        out["roofline"] = pathsum_roofline(s0, avg)
+        out["roofline"] = pathsum_roofline(s0, avg, name)
     return out
 
 
@@ -388,7 +389,8 @@ def c5_multi_variant(lofp, workloads, torch, R=64, steps=5):
             c.amplitudes(w.S, w.Ts[i:i + 32], lofp.make_opts(method=lofp.METHOD_CONTRACT, count_work=True), st)
             trans += st.transitions
     trans_all = trans * R / 8.0   # counted on 8 of the R circuits, scaled
-    rl = contract_roofline("k_contract_multi (multi-circuit)", ms_k, trans_all)
+    rl = contract_roofline("k_contract_multi", ms_k, trans_all, "c5x64")
+    rl["kernel"] = "k_contract_multi (multi-circuit)"
     return {"circuits": R, "patterns_per_circuit": wls[0].batch, "jobs": len(items), "device_ms": ms_k,
             "amplitudes_per_s": len(items) / (ms_k * 1e-3), "transitions_est": trans_all,
             "transitions_counted_on_circuits": 8, "roofline": rl}
