@@ -1,9 +1,12 @@
 // pool.cpp -- device memory pool for circuit set-up.
 //
 // Blocks of up to 16 MiB are rounded up to a power of two (at least 4 KiB)
-// and carved from 64 MiB slabs; freed blocks go to a per-class free list and
-// are reused.  Larger blocks are plain hipMalloc allocations.  One pool per
-// device; thread-safe.
+// and carved from slabs; freed blocks go to a per-class free list and are
+// reused.  Slabs start at 64 MiB and double up to 2 GiB, so a serving run
+// that sets up thousands of fresh circuits calls hipMalloc a handful of
+// times rather than once per 64 MiB (each such call stalls the thread that
+// makes it, and with it the requests that thread is launching).  Larger
+// blocks are plain hipMalloc allocations.  One pool per device; thread-safe.
 #include <hip/hip_runtime.h>
 
 #include <map>
@@ -16,14 +19,17 @@ namespace lofp {
 namespace host {
 namespace {
 
-constexpr size_t kSlab = size_t(64) << 20;
+constexpr size_t kSlabMin = size_t(64) << 20;
+constexpr size_t kSlabMax = size_t(2) << 30;
 constexpr size_t kMinBlock = size_t(4) << 10;
 constexpr size_t kMaxPooled = size_t(16) << 20;
 
 struct Pool {
     std::map<size_t, std::vector<void *>> free_lists;   // class size -> blocks
     char *slab = nullptr;
-    size_t used = kSlab;
+    size_t cap = 0;            // bytes of the current slab
+    size_t used = 0;
+    size_t next = kSlabMin;    // bytes of the next slab
 };
 
 std::mutex g_mu;
@@ -53,11 +59,17 @@ void *pool_alloc(size_t bytes, int device)
         fl.pop_back();
         return p;
     }
-    if (pl.used + c > kSlab) {
+    if (pl.used + c > pl.cap) {
         void *s = nullptr;
-        if (hipMalloc(&s, kSlab) != hipSuccess) return nullptr;
+        if (hipMalloc(&s, pl.next) != hipSuccess) {
+            // the doubled slab does not fit: fall back to the smallest
+            if (pl.next == kSlabMin || hipMalloc(&s, kSlabMin) != hipSuccess) return nullptr;
+            pl.next = kSlabMin;
+        }
         pl.slab = static_cast<char *>(s);
+        pl.cap = pl.next;
         pl.used = 0;
+        pl.next = pl.next < kSlabMax ? pl.next * 2 : kSlabMax;
     }
     void *p = pl.slab + pl.used;
     pl.used += c;
