@@ -6,40 +6,25 @@
 // sequence of beam-splitter outputs that leads from it to a configuration of
 // stage s_b, one tree edge per loop iteration (push, leaf or pop), so that
 // lanes of a wave advance independently and stay busy whatever the shape of
-// their subtrees.  Per edge: one transition-table read from LDS and one complex
-// FP64 product; at a leaf the backward-frontier amplitude of the reached
+// their subtrees.  Per edge: one transition-table read (from LDS, or through
+// the vector caches where LDS tables would cost resident blocks) and one
+// complex FP64 product; at a leaf the backward-frontier amplitude of the reached
 // configuration is found by its dense rank, which is kept up to date with two
 // table lookups per changed cut.  Ranges come from the per-pattern cut bounds,
 // so every edge taken leads to at least one valid leaf.
 //
 // The per-lane stack (prefix product, choice, range end, previous cut value,
-// prefix rank) lives in LDS as [level][lane]; cut values live in registers as
-// packed bytes.  A lane's leaves are accumulated with a compensated (TwoSum)
-// complex sum, multiplied by the frontier amplitude and written back in place
-// of it; the per-pattern total is formed by the reduction kernel in a fixed
-// order, so results do not depend on which lane took which entry.
+// prefix rank) lives in LDS as [level][lane], and so do the lane's cut values
+// as bytes, [cut][lane]: a cut is read or written by one LDS access at the
+// lane's own address (held as packed words in registers, each access was a
+// chain of selects over the words, several per edge).  A lane's leaves are
+// accumulated with a compensated (TwoSum) complex sum, multiplied by the
+// frontier amplitude and written back in place of it; the per-pattern total
+// is formed by the reduction kernel in a fixed order, so results do not
+// depend on which lane took which entry.
 #include "lofp_device.h"
 
 namespace lofp {
-
-template <int NW>
-struct PackedCuts {
-    uint32_t w[NW];
-    __device__ __forceinline__ int get(int idx) const
-    {
-        uint32_t s = w[0];
-#pragma unroll
-        for (int q = 1; q < NW; ++q) s = ((idx >> 2) == q) ? w[q] : s;
-        return (int)((s >> ((idx & 3) * 8)) & 0xffu);
-    }
-    __device__ __forceinline__ void set(int idx, int val)
-    {
-        const int sh = (idx & 3) * 8;
-#pragma unroll
-        for (int q = 0; q < NW; ++q)
-            if ((idx >> 2) == q) w[q] = (w[q] & ~(0xffu << sh)) | ((uint32_t)val << sh);
-    }
-};
 
 constexpr int kTabMax = kMaxCuts * (kMaxPhotons + 2);
 
@@ -107,9 +92,9 @@ constexpr int kMaxLevels = 128;
 
 // Dynamic LDS layout of k_dfs.
 struct DfsLds {
-    size_t tab, lev, stP, stM, E, LH, total;
+    size_t tab, lev, stP, stM, E, LH, cut, total;
 };
-__host__ __device__ inline DfsLds dfs_layout(int tab_len, int levels, int tsz)
+__host__ __device__ inline DfsLds dfs_layout(int tab_len, int levels, int tsz, int nc)
 {
     DfsLds L;
     size_t o = 0;
@@ -122,6 +107,7 @@ __host__ __device__ inline DfsLds dfs_layout(int tab_len, int levels, int tsz)
     L.stM = o; o += depth * kDfsBlock * 8;
     L.LH = o; o += (size_t)levels * 8;
     L.E = o; o += (size_t)tsz * 4;
+    L.cut = o; o += (size_t)nc * kDfsBlock;
     L.total = (o + 15) & ~(size_t)15;
     return L;
 }
@@ -135,7 +121,7 @@ __global__ __launch_bounds__(kDfsBlock) void k_dfs(DfsArgs g)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nc = g.m - 1, W = table_cols(g.n), span = (g.D + 1) * nc, tsz = nc * W;
-    const DfsLds Ly = dfs_layout(TAB_LDS ? g.tab_len : 0, g.levels, tsz);
+    const DfsLds Ly = dfs_layout(TAB_LDS ? g.tab_len : 0, g.levels, tsz, nc);
     double2 *tab_s = reinterpret_cast<double2 *>(smem + Ly.tab);
     const double2 *tab = TAB_LDS ? tab_s : g.tab;
     int4 *lev = reinterpret_cast<int4 *>(smem + Ly.lev);
@@ -143,6 +129,7 @@ __global__ __launch_bounds__(kDfsBlock) void k_dfs(DfsArgs g)
     int2 *stM = reinterpret_cast<int2 *>(smem + Ly.stM);
     int32_t *sE = reinterpret_cast<int32_t *>(smem + Ly.E);
     int2 *sLH = reinterpret_cast<int2 *>(smem + Ly.LH);
+    unsigned char *cut8 = smem + Ly.cut + threadIdx.x;   // cut r of this lane at cut8[r * kDfsBlock]
     __shared__ int s_p, s_cnt, s_beg, s_end;
     const int tid = threadIdx.x, bd = kDfsBlock;
 
@@ -205,7 +192,6 @@ __global__ __launch_bounds__(kDfsBlock) void k_dfs(DfsArgs g)
         const int64_t kbase = g.off_front[p];
         const double2 *Bp = g.back + g.off_back[p];
 
-        PackedCuts<NW> A;
         int64_t k = 0;
         int d = 0, v = 0, vhi = -1, old = 0, prev = 0, N = 0, x1 = 0, a = 0, tb = 0, rank = 0;
         double2 P = make_double2(1.0, 0.0);
@@ -217,9 +203,9 @@ __global__ __launch_bounds__(kDfsBlock) void k_dfs(DfsArgs g)
             const int4 L = lev[d];
             a = L.x;
             tb = L.z;
-            prev = a > 0 ? A.get(a - 1) : 0;
-            const int next = a + 1 < nc ? A.get(a + 1) : g.n;
-            old = A.get(a);
+            prev = a > 0 ? cut8[(a - 1) * kDfsBlock] : 0;
+            const int next = a + 1 < nc ? cut8[(a + 1) * kDfsBlock] : g.n;
+            old = cut8[a * kDfsBlock];
             x1 = old - prev;
             N = next - prev;
             const int2 LH = sLH[d];
@@ -233,7 +219,12 @@ __global__ __launch_bounds__(kDfsBlock) void k_dfs(DfsArgs g)
                 if (e >= end) break;
                 k = kbase + e;
 #pragma unroll
-                for (int q = 0; q < NW; ++q) A.w[q] = g.cfg[k * g.cfg_words + q];
+                for (int q = 0; q < NW; ++q) {
+                    const uint32_t wq = g.cfg[k * g.cfg_words + q];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        if (4 * q + b < nc) cut8[(4 * q + b) * kDfsBlock] = (unsigned char)(wq >> (8 * b));
+                }
                 rank = g.rank_back[k];
                 d = 0;
                 P = make_double2(1.0, 0.0);
@@ -251,7 +242,7 @@ __global__ __launch_bounds__(kDfsBlock) void k_dfs(DfsArgs g)
                     need = true;
                     continue;
                 }
-                A.set(a, old);
+                cut8[a * kDfsBlock] = (unsigned char)old;
                 --d;
                 const int2 M = stM[d * bd + tid];
                 if (FP32) {
@@ -267,8 +258,8 @@ __global__ __launch_bounds__(kDfsBlock) void k_dfs(DfsArgs g)
                 const int4 L = lev[d];
                 a = L.x;
                 tb = L.z;
-                prev = a > 0 ? A.get(a - 1) : 0;
-                const int next = a + 1 < nc ? A.get(a + 1) : g.n;
+                prev = a > 0 ? cut8[(a - 1) * kDfsBlock] : 0;
+                const int next = a + 1 < nc ? cut8[(a + 1) * kDfsBlock] : g.n;
                 x1 = old - prev;
                 N = next - prev;
                 continue;
@@ -306,7 +297,7 @@ __global__ __launch_bounds__(kDfsBlock) void k_dfs(DfsArgs g)
                 stP[d * bd + tid] = P;
                 P = cmul(P, w);
             }
-            A.set(a, v);
+            cut8[a * kDfsBlock] = (unsigned char)v;
             ++d;
             rank = rn;
             init_level();
@@ -346,21 +337,21 @@ static int dfs_occupancy(const DfsArgs &a, bool tab_lds, size_t lds)
 static bool dfs_tables_in_lds(const DfsArgs &a)
 {
     const int tsz = (a.m - 1) * table_cols(a.n);
-    const size_t with = dfs_layout(a.tab_len, a.levels, tsz).total;
+    const size_t with = dfs_layout(a.tab_len, a.levels, tsz, a.m - 1).total;
     if (with > 64 * 1024) return false;
-    const size_t without = dfs_layout(0, a.levels, tsz).total;
+    const size_t without = dfs_layout(0, a.levels, tsz, a.m - 1).total;
     return dfs_occupancy(a, true, with) >= dfs_occupancy(a, false, without);
 }
 
 int dfs_blocks_per_cu(const DfsArgs &a)
 {
     const bool tl = dfs_tables_in_lds(a);
-    return dfs_occupancy(a, tl, dfs_layout(tl ? a.tab_len : 0, a.levels, (a.m - 1) * table_cols(a.n)).total);
+    return dfs_occupancy(a, tl, dfs_layout(tl ? a.tab_len : 0, a.levels, (a.m - 1) * table_cols(a.n), a.m - 1).total);
 }
 
 size_t dfs_lds_bytes(const DfsArgs &a)
 {
-    return dfs_layout(dfs_tables_in_lds(a) ? a.tab_len : 0, a.levels, (a.m - 1) * table_cols(a.n)).total;
+    return dfs_layout(dfs_tables_in_lds(a) ? a.tab_len : 0, a.levels, (a.m - 1) * table_cols(a.n), a.m - 1).total;
 }
 
 template <bool FP32, bool TAB_LDS>
