@@ -76,6 +76,20 @@ enum {
     LOFP_PREC_FP32 = 1        /* path products in FP32; tables and sums FP64 */
 };
 
+/* How the contraction treats a batch sharing S (Sec. II.C contracted from
+ * both ends): each distinct top and bottom half of T contracted once and
+ * joined per pattern, or one contraction per pattern.  The results agree to
+ * rounding (the sums run in another order). */
+enum {
+    LOFP_SPLIT_AUTO = 0,      /* split when halves are shared, for batches of
+                                 256 to 1024 patterns, and for smaller
+                                 batches of circuits with at least 40
+                                 splitters (two half-length chains in
+                                 parallel beat one long chain)             */
+    LOFP_SPLIT_NEVER = 1,     /* one contraction per pattern                 */
+    LOFP_SPLIT_ALWAYS = 2     /* halves contracted and joined for any batch  */
+};
+
 typedef struct {
     int32_t method;        /* LOFP_METHOD_*                                    */
     int32_t precision;     /* LOFP_PREC_*                                      */
@@ -102,7 +116,7 @@ typedef struct {
     double fp32_rtol;         /* multi-circuit FP32 form: a result whose
                                  rounding bound exceeds fp32_rtol * |amp| is
                                  recomputed in FP64 (0 = 1e-6)               */
-    int32_t autotune;         /* contraction of a batch of >= 64 patterns: 1 =
+    int32_t autotune;         /* contraction with split = LOFP_SPLIT_AUTO: 1 =
                                  on the first call for this circuit, S and
                                  batch size, time the candidate ways to
                                  contract it (split cut, LDS per job, split
@@ -110,7 +124,7 @@ typedef struct {
                                  keep the fastest for later calls with
                                  autotune = 1 (that first call synchronises
                                  the stream); 0 = the default way          */
-    int32_t reserved;
+    int32_t split;            /* contraction: LOFP_SPLIT_* (EINVAL otherwise) */
 } lofp_opts;
 
 /* Per-call statistics (filled when a non-null pointer is passed). */

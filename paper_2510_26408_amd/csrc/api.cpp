@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <limits>
 #include <array>
 #include <cstdio>
 #include <cstring>
@@ -558,11 +559,20 @@ lofp_status run_contract_split(lofp_circuit_s &c, const int32_t *S, int n, int B
                                int state_limit, const SplitCfg &cfg, Timer &tm, bool &used, bool &bounds_done);
 
 // The default split: the middle cut, 52 KiB of LDS per job (three jobs per
-// CU), batches of 256 to 1024 patterns split without shared halves.
+// CU), batches of 256 to 1024 patterns split without shared halves.  A
+// circuit of at least kSplitChainGates splitters also splits batches below
+// 256: a job's time is its chain of one-splitter steps (1.5-2 us each,
+// nearly whatever the state size), so two half-length jobs in parallel and a
+// join finish sooner than one job per pattern (one c2 pattern: 0.18 ->
+// 0.13 ms).  Shorter circuits keep one job per pattern: there the grouping
+// and join kernels cost more than the shorter chain saves.
+constexpr int kSplitChainGates = 40;
+
 SplitCfg default_split_cfg(const lofp_circuit_s &c)
 {
     SplitCfg k;
     k.rs = (c.nc - 1) / 2;
+    if (c.G >= kSplitChainGates) k.small_min = 1;
     return k;
 }
 
@@ -583,7 +593,7 @@ lofp_status run_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, cons
     if (rc != LOFP_OK) return rc;
     bool bounds_done = false;
     const SplitCfg cfg = cfg_in ? *cfg_in : default_split_cfg(c);
-    if (!count_only && allow_split && B >= 64 && cfg.mode != SplitCfg::kPerPattern) {
+    if (!count_only && allow_split && B >= std::min(64, cfg.small_min) && cfg.mode != SplitCfg::kPerPattern) {
         bool used = false;
         if (cfg.mode == SplitCfg::kDevice) {
             rc = run_contract_split_dev(c, S, n, B, T_dev, out_dev, fp32, s, st, count_work, state_limit, cfg, tm, used);
@@ -1063,6 +1073,15 @@ lofp_status tune_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, con
             k.lds_kb = kb;
             if (k.rs >= 0 && k.rs <= c.nc - 2) cand.push_back(k);
         }
+    if (B < d.small_max && B < 256) {
+        // a small batch: split or not, whatever the circuit's default
+        for (int drs : {0, -1, 1}) {
+            SplitCfg k = d;
+            k.rs = d.rs + drs;
+            k.small_min = d.small_min == 1 ? 256 : 1;
+            if (k.rs >= 0 && k.rs <= c.nc - 2) cand.push_back(k);
+        }
+    }
     SplitCfg pp = d;
     pp.mode = SplitCfg::kPerPattern;
     cand.push_back(pp);
@@ -1712,6 +1731,7 @@ lofp_status lofp_amplitudes_device(lofp_circuit c, const int32_t *S, int32_t bat
     if (opts) o = *opts;
     if (o.precision != LOFP_PREC_FP64 && o.precision != LOFP_PREC_FP32) return fail(LOFP_EINVAL, "bad precision");
     if (o.method < 0 || o.method > LOFP_METHOD_CONTRACT) return fail(LOFP_EINVAL, "bad method");
+    if (o.split < LOFP_SPLIT_AUTO || o.split > LOFP_SPLIT_ALWAYS) return fail(LOFP_EINVAL, "bad split mode");
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
         stats->batch = batch;
@@ -1751,7 +1771,15 @@ lofp_status lofp_amplitudes_device(lofp_circuit c, const int32_t *S, int32_t bat
         inner.s = s;
         const int fp32 = o.precision == LOFP_PREC_FP32;
         const SplitCfg *cfg = nullptr;
-        if (o.autotune && batch >= 64) {
+        SplitCfg fixed = default_split_cfg(*c);
+        if (o.split == LOFP_SPLIT_NEVER) {
+            fixed.mode = SplitCfg::kPerPattern;
+            cfg = &fixed;
+        } else if (o.split == LOFP_SPLIT_ALWAYS) {
+            fixed.small_min = 1;
+            fixed.small_max = std::numeric_limits<int>::max();
+            cfg = &fixed;
+        } else if (o.autotune) {
             // the tuned way for this S, batch size, precision and state limit
             const lofp_circuit_s::TuneKey key{Sv, {batch, fp32, o.state_limit}};
             auto it = c->tuned.find(key);

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "liblofp.so")
 OK, EINVAL, ENOMEM, ENOTSUP, EDEVICE = 0, 1, 2, 3, 4
 METHOD_AUTO, METHOD_PATHSUM, METHOD_CONTRACT = 0, 1, 2
 PREC_FP64, PREC_FP32 = 0, 1
+SPLIT_AUTO, SPLIT_NEVER, SPLIT_ALWAYS = 0, 1, 2
 
 EXPORTED = (
     "lofp_last_error", "lofp_version", "lofp_circuit_create", "lofp_circuit_destroy", "lofp_light_cone",
@@ -47,7 +48,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("precision", ctypes.c_int32), ("fwd_layer", ctypes.c_int32),
                 ("bwd_layer", ctypes.c_int32), ("record_timing", ctypes.c_int32),
                 ("frontier_budget_kb", ctypes.c_int32), ("count_work", ctypes.c_int32), ("state_limit", ctypes.c_int32),
-                ("fp32_rtol", ctypes.c_double), ("autotune", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fp32_rtol", ctypes.c_double), ("autotune", ctypes.c_int32), ("split", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -151,7 +152,7 @@ def _ip(a: np.ndarray):
 
 def make_opts(method: int = METHOD_AUTO, precision: int = PREC_FP64, fwd_layer: int = -1, bwd_layer: int = -1,
               record_timing: bool = False, frontier_budget_kb: int = 0, count_work: bool = False,
-              fp32_rtol: float = 0.0, state_limit: int = 0, autotune: bool = False) -> Opts:
+              fp32_rtol: float = 0.0, state_limit: int = 0, autotune: bool = False, split: int = 0) -> Opts:
     o = Opts()
     o.method, o.precision, o.fwd_layer, o.bwd_layer = method, precision, fwd_layer, bwd_layer
     o.record_timing = 1 if record_timing else 0
@@ -160,6 +161,7 @@ def make_opts(method: int = METHOD_AUTO, precision: int = PREC_FP64, fwd_layer: 
     o.fp32_rtol = fp32_rtol
     o.state_limit = state_limit
     o.autotune = 1 if autotune else 0
+    o.split = split
     return o
 
 

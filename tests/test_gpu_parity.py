@@ -20,6 +20,8 @@ pytestmark = pytest.mark.gpu
 ATOL = 1e-12
 RTOL = 1e-9          # relative agreement where the oracle resolves the amplitude
 EB_FACTOR = 1e3      # slack in units of the oracle's own rounding bound
+# one contraction per pattern: the reference the split contraction is checked against
+NEVER_SPLIT = lofp.make_opts(method=lofp.METHOD_CONTRACT, split=lofp.SPLIT_NEVER)
 
 
 def _need_gpu():
@@ -248,14 +250,22 @@ def test_leaf_count_matches_path_count_when_frontiers_are_endpoints():
 
 # ------------------------------------------------------------- determinism
 def test_deterministic_and_independent_of_batch():
+    """Repeated calls give the same bits.  One contraction per pattern gives
+    each pattern the same bits alone and in any batch; the split form (the
+    default for this circuit) agrees with it to rounding: its half states
+    span the hull of the batch's intervals, so their sums take other terms
+    in another order."""
     wl = workloads.make("c2", seed=5, batch=64)
     c = lofp.Circuit(wl.m, wl.layers)
     a = c.amplitudes(wl.S, wl.Ts)
     b = c.amplitudes(wl.S, wl.Ts)
     assert np.array_equal(a, b)
+    pp = c.amplitudes(wl.S, wl.Ts, NEVER_SPLIT)
+    check(a, pp, 1e-14)
     for p in (0, 17, 63):
-        alone = c.amplitudes(wl.S, wl.Ts[p:p + 1])
-        assert alone[0] == a[p]
+        alone = c.amplitudes(wl.S, wl.Ts[p:p + 1], NEVER_SPLIT)
+        assert alone[0] == pp[p]
+        check(c.amplitudes(wl.S, wl.Ts[p:p + 1]), pp[p:p + 1], 1e-14)
 
 
 # ------------------------------------------------------------ FP32 products
@@ -318,7 +328,7 @@ def test_multi_circuit_batch_matches_oracle_and_single_calls():
     for i, (c, r) in enumerate(items):
         want = oracle.amplitude(r.m, r.S, r.T, flat(r.layers))
         assert abs(got[i] - want) <= ATOL
-        alone = c.amplitudes(r.S, r.T[None, :], lofp.make_opts(method=lofp.METHOD_CONTRACT))[0]
+        alone = c.amplitudes(r.S, r.T[None, :], NEVER_SPLIT)[0]
         assert alone == got[i]
 
 
@@ -404,8 +414,8 @@ def test_server_results_same_alone_and_in_mix():
 def test_split_contraction_full_c2_batch():
     """The 4096-pattern batch shares S: the contraction runs once per distinct
     top and bottom half of T and joins per pattern.  Checked against the
-    oracle on a sample and against the unsplit contraction (batches below the
-    split threshold) on every pattern."""
+    oracle on a sample and against one contraction per pattern on every
+    pattern."""
     wl = workloads.make("c2", seed=0)
     c = lofp.Circuit(wl.m, wl.layers)
     st = lofp.Stats()
@@ -413,8 +423,7 @@ def test_split_contraction_full_c2_batch():
     assert st.split_top_keys > 0 and st.split_bottom_keys > 0
     idx = np.random.default_rng(2).choice(wl.batch, 64, replace=False)
     check(got[idx], oracle_amps(wl.m, wl.S, wl.Ts[idx], wl.layers))
-    ref = np.concatenate([c.amplitudes(wl.S, wl.Ts[i:i + 32], lofp.make_opts(method=lofp.METHOD_CONTRACT))
-                          for i in range(0, wl.batch, 32)])
+    ref = np.concatenate([c.amplitudes(wl.S, wl.Ts[i:i + 32], NEVER_SPLIT) for i in range(0, wl.batch, 32)])
     check(got, ref, 1e-14)
 
 
@@ -446,7 +455,7 @@ def test_split_contraction_invalid_rows_and_no_sharing():
     got4 = c4.amplitudes(wl4.S, wl4.Ts, lofp.make_opts(method=lofp.METHOD_CONTRACT), st4)
     assert st4.split_top_keys > 0
     check(got4[:64], oracle_amps(wl4.m, wl4.S, wl4.Ts[:64], wl4.layers))
-    unsplit = np.concatenate([c4.amplitudes(wl4.S, wl4.Ts[i:i + 32], lofp.make_opts(method=lofp.METHOD_CONTRACT))
+    unsplit = np.concatenate([c4.amplitudes(wl4.S, wl4.Ts[i:i + 32], NEVER_SPLIT)
                               for i in range(0, 64, 32)])
     check(got4[:64], unsplit, 1e-14)
 
@@ -636,7 +645,7 @@ def test_split_contraction_shrinking_batches_on_one_circuit():
     wl = workloads.make("c2", seed=6)
     c = lofp.Circuit(wl.m, wl.layers)
     opts = lofp.make_opts(method=lofp.METHOD_CONTRACT)
-    unsplit = np.concatenate([c.amplitudes(wl.S, wl.Ts[i:i + 32], opts) for i in range(0, 1024, 32)])
+    unsplit = np.concatenate([c.amplitudes(wl.S, wl.Ts[i:i + 32], NEVER_SPLIT) for i in range(0, 1024, 32)])
     for lo_, hi_ in ((0, 4096), (100, 1004), (0, 1000), (700, 1000)):
         st = lofp.Stats()
         got = c.amplitudes(wl.S, wl.Ts[lo_:hi_], opts, st)
@@ -693,6 +702,41 @@ def test_contraction_overflow_is_nan_without_stats_and_enomem_with(batch):
     check(c.amplitudes(wl.S, wl.Ts, lofp.make_opts(method=lofp.METHOD_CONTRACT)), want)
 
 
+def test_small_batches_split_for_latency():
+    """A circuit of 40 or more splitters splits even one pattern into its two
+    halves (two half-length chains in parallel, then the join); a short one
+    keeps one contraction per pattern unless asked.  Every form agrees with
+    one contraction per pattern and with the oracle."""
+    wl = workloads.make("c2", seed=9)
+    c = lofp.Circuit(wl.m, wl.layers)
+    for B in (1, 8, 40):
+        Ts = wl.Ts[:B]
+        ref = c.amplitudes(wl.S, Ts, NEVER_SPLIT)
+        st = lofp.Stats()
+        got = c.amplitudes(wl.S, Ts, lofp.make_opts(method=lofp.METHOD_CONTRACT), st)
+        assert st.split_top_keys > 0 and st.split_bottom_keys > 0, B
+        check(got, ref, 1e-14)
+        st = lofp.Stats()
+        got = c.amplitudes(wl.S, Ts, lofp.make_opts(method=lofp.METHOD_CONTRACT, split=lofp.SPLIT_ALWAYS), st)
+        assert st.split_top_keys > 0
+        check(got, ref, 1e-14)
+        check(ref, oracle_amps(wl.m, wl.S, Ts, wl.layers))
+    w1 = workloads.make("c1", seed=0)
+    c1 = lofp.Circuit(w1.m, w1.layers)
+    ref = c1.amplitudes(w1.S, w1.Ts[:1], NEVER_SPLIT)
+    st = lofp.Stats()
+    got = c1.amplitudes(w1.S, w1.Ts[:1], lofp.make_opts(method=lofp.METHOD_CONTRACT), st)
+    assert st.split_top_keys == 0
+    check(got, ref, 1e-14)
+    st = lofp.Stats()
+    got = c1.amplitudes(w1.S, w1.Ts[:1], lofp.make_opts(method=lofp.METHOD_CONTRACT, split=lofp.SPLIT_ALWAYS), st)
+    assert st.split_top_keys > 0
+    check(got, ref, 1e-14)
+    check(ref, oracle_amps(w1.m, w1.S, w1.Ts[:1], w1.layers))
+    with pytest.raises(lofp.LofpError):
+        c1.amplitudes(w1.S, w1.Ts[:1], lofp.make_opts(method=lofp.METHOD_CONTRACT, split=3))
+
+
 def test_c5_full_batch_split_for_parallelism():
     """The 32-mode, depth-6 workload at its full 512 patterns, in the launch
     the benchmark times (the batch split into top and bottom halves for
@@ -706,8 +750,7 @@ def test_c5_full_batch_split_for_parallelism():
     assert st.method_used == lofp.METHOD_CONTRACT and st.split_top_keys > 0
     idx = np.random.default_rng(14).choice(wl.batch, 64, replace=False)
     check(got[idx], oracle_amps(wl.m, wl.S, wl.Ts[idx], wl.layers))
-    ref = np.concatenate([c.amplitudes(wl.S, wl.Ts[i:i + 32], lofp.make_opts(method=lofp.METHOD_CONTRACT))
-                          for i in range(0, wl.batch, 32)])
+    ref = np.concatenate([c.amplitudes(wl.S, wl.Ts[i:i + 32], NEVER_SPLIT) for i in range(0, wl.batch, 32)])
     check(got, ref, 1e-14)
 
 
@@ -877,9 +920,9 @@ def test_graph_replay_equals_eager_tuned_call():
 
 @pytest.mark.parametrize("name,batch", [("c2", 1), ("c5", 512), ("c3", 300)])
 def test_graph_small_and_other_workloads(name, batch):
-    """Captured calls for a single pattern (one contraction per pattern), the
-    32-mode batch and a bunched batch, each replayed twice against the eager
-    call."""
+    """Captured calls for a single pattern (split into its halves: the
+    circuit is long), the 32-mode batch and a bunched batch, each replayed
+    twice against the eager call."""
     import torch
     wl = workloads.make(name, seed=5, batch=batch)
     c = lofp.Circuit(wl.m, wl.layers)

@@ -30,10 +30,13 @@ def test_noalloc_matches_device_entry_point(name, sizes):
     c = lofp.Circuit(wl.m, wl.layers)
     T = torch.from_numpy(np.ascontiguousarray(wl.Ts)).cuda()
     opts = lofp.make_opts(method=lofp.METHOD_CONTRACT)
+    # the ordinary call with one contraction per pattern, the form the
+    # allocation-free call runs
+    ref_opts = lofp.make_opts(method=lofp.METHOD_CONTRACT, split=lofp.SPLIT_NEVER)
     want = oracle.amplitudes(wl.m, wl.S, wl.Ts, _flat(wl.layers), nthreads=8)[0]
     # the ordinary call sets the circuit up on the device (it may allocate)
     ref = torch.zeros(wl.batch, dtype=torch.complex128, device="cuda")
-    c.amplitudes_device(wl.S, T, ref, opts)
+    c.amplitudes_device(wl.S, T, ref, ref_opts)
     torch.cuda.synchronize()
     ref = ref.cpu().numpy()
     for b in sizes:
@@ -41,10 +44,9 @@ def test_noalloc_matches_device_entry_point(name, sizes):
         c.amplitudes_device_noalloc(wl.S, T[:b], out, opts)
         torch.cuda.synchronize()
         got = out.cpu().numpy()
-        # below 64 patterns the ordinary call runs the same per-pattern
-        # kernel (its state size may come from the device instead of the
-        # S-side bound, which can change the block size and so the order of
-        # the final sum)
+        # the same per-pattern kernel (the ordinary call's state size may
+        # come from the device instead of the S-side bound, which can change
+        # the block size and so the order of the final sum)
         assert np.abs(got - ref[:b]).max() <= 1e-14, name
         assert np.abs(got - want[:b]).max() <= ATOL
 
