@@ -4,9 +4,10 @@
 //
 // Each lane owns one forward-frontier configuration at a time and walks every
 // sequence of beam-splitter outputs that leads from it to a configuration of
-// stage s_b, one tree edge per loop iteration (push, leaf or pop), so that
-// lanes of a wave advance independently and stay busy whatever the shape of
-// their subtrees.  Per edge: one transition-table read (from LDS, or through
+// stage s_b, so that lanes of a wave advance independently and stay busy
+// whatever the shape of their subtrees.  One loop pass takes every leaf of a
+// last-level range, climbs out of the levels it has used up and steps down
+// one edge, so the lanes of a wave run the same bodies in step.  Per edge: one transition-table read (from LDS, or through
 // the vector caches where LDS tables would cost resident blocks) and one
 // complex FP64 product; at a leaf the backward-frontier amplitude of the reached
 // configuration is found by its dense rank, which is kept up to date with two
@@ -197,7 +198,6 @@ __global__ __launch_bounds__(kDfsBlock) void k_dfs(DfsArgs g)
         double2 P = make_double2(1.0, 0.0);
         float2 Pf = make_float2(1.f, 0.f);
         CSum sr{0.0, 0.0}, si{0.0, 0.0};
-        bool need = true;
 
         auto init_level = [&]() {
             const int4 L = lev[d];
@@ -212,36 +212,57 @@ __global__ __launch_bounds__(kDfsBlock) void k_dfs(DfsArgs g)
             v = LH.x > prev ? LH.x : prev;
             vhi = LH.y < next ? LH.y : next;
         };
-
-        while (true) {
-            if (need) {
-                const int e = beg + atomicAdd(&s_cnt, 1);
-                if (e >= end) break;
-                k = kbase + e;
+        // the lane's next entry of the chunk (false once the chunk is used up)
+        auto fetch = [&]() -> bool {
+            const int e = beg + atomicAdd(&s_cnt, 1);
+            if (e >= end) return false;
+            k = kbase + e;
 #pragma unroll
-                for (int q = 0; q < NW; ++q) {
-                    const uint32_t wq = g.cfg[k * g.cfg_words + q];
+            for (int q = 0; q < NW; ++q) {
+                const uint32_t wq = g.cfg[k * g.cfg_words + q];
 #pragma unroll
-                    for (int b = 0; b < 4; ++b)
-                        if (4 * q + b < nc) cut8[(4 * q + b) * kDfsBlock] = (unsigned char)(wq >> (8 * b));
-                }
-                rank = g.rank_back[k];
-                d = 0;
-                P = make_double2(1.0, 0.0);
-                Pf = make_float2(1.f, 0.f);
-                sr = CSum{0.0, 0.0};
-                si = CSum{0.0, 0.0};
-                init_level();
-                need = false;
+                for (int b = 0; b < 4; ++b)
+                    if (4 * q + b < nc) cut8[(4 * q + b) * kDfsBlock] = (unsigned char)(wq >> (8 * b));
             }
-            if (v > vhi) {
-                if (d == 0) {
-                    const double2 f = g.front[k];
-                    const double2 s = make_double2(sr.s + sr.c, si.s + si.c);
-                    g.front[k] = cmul(f, s);
-                    need = true;
-                    continue;
+            rank = g.rank_back[k];
+            d = 0;
+            P = make_double2(1.0, 0.0);
+            Pf = make_float2(1.f, 0.f);
+            sr = CSum{0.0, 0.0};
+            si = CSum{0.0, 0.0};
+            init_level();
+            return true;
+        };
+
+        // One pass: every leaf of a last-level range, then the climb out of
+        // the exhausted levels, then one step down.  A wave runs each of the
+        // three bodies once per pass with its lanes in step, where a pass of
+        // one body per lane ran the three one after another for the wave's
+        // lanes in different phases.
+        bool live = fetch();
+        while (live) {
+            if (d == last && v <= vhi) {
+                // the whole leaf range: independent loads
+                const int wrow = tb + sector_offset(N) + x1 * (N + 1) - prev;
+                const int32_t *Ea = sE + a * W;
+                const int rbase = rank - Ea[old];
+                for (; v <= vhi; ++v) {
+                    const double2 w = tab[wrow + v];
+                    const double2 b = Bp[rbase + Ea[v]];
+                    double2 c2;
+                    if (FP32) {
+                        const float2 Pn = make_float2(Pf.x * (float)w.x - Pf.y * (float)w.y,
+                                                      Pf.x * (float)w.y + Pf.y * (float)w.x);
+                        c2 = cmul(make_double2((double)Pn.x, (double)Pn.y), b);
+                    } else {
+                        c2 = cmul(cmul(P, w), b);
+                    }
+                    csum_add(sr, c2.x);
+                    csum_add(si, c2.y);
+                    ++leaves;
                 }
+            }
+            while (v > vhi && d > 0) {
                 cut8[a * kDfsBlock] = (unsigned char)old;
                 --d;
                 const int2 M = stM[d * bd + tid];
@@ -262,30 +283,19 @@ __global__ __launch_bounds__(kDfsBlock) void k_dfs(DfsArgs g)
                 const int next = a + 1 < nc ? cut8[(a + 1) * kDfsBlock] : g.n;
                 x1 = old - prev;
                 N = next - prev;
+            }
+            if (v > vhi) {
+                // level 0 used up: the entry is done
+                const double2 f = g.front[k];
+                const double2 sm = make_double2(sr.s + sr.c, si.s + si.c);
+                g.front[k] = cmul(f, sm);
+                live = fetch();
                 continue;
             }
+            // one step down (d < last here: a last-level range is used up above)
             const int wrow = tb + sector_offset(N) + x1 * (N + 1) - prev;
             const int32_t *Ea = sE + a * W;
             const int rbase = rank - Ea[old];
-            if (d == last) {
-                // the whole leaf level in one iteration: independent loads
-                for (; v <= vhi; ++v) {
-                    const double2 w = tab[wrow + v];
-                    const double2 b = Bp[rbase + Ea[v]];
-                    double2 c2;
-                    if (FP32) {
-                        const float2 Pn = make_float2(Pf.x * (float)w.x - Pf.y * (float)w.y,
-                                                      Pf.x * (float)w.y + Pf.y * (float)w.x);
-                        c2 = cmul(make_double2((double)Pn.x, (double)Pn.y), b);
-                    } else {
-                        c2 = cmul(cmul(P, w), b);
-                    }
-                    csum_add(sr, c2.x);
-                    csum_add(si, c2.y);
-                    ++leaves;
-                }
-                continue;
-            }
             const double2 w = tab[wrow + v];
             const int rn = rbase + Ea[v];
             ++edges;
