@@ -270,16 +270,21 @@ def contract_roofline(kernel, ms_k, transitions, key):
                                            "with a nonzero source"}
 
 
+def dfs_roofline(s0, avg, key):
+    ms_dfs = avg("ms_dfs")
+    flops = 6.0 * s0["dfs_edges"] + 8.0 * s0["dfs_leaves"]
+    achieved = flops / (ms_dfs * 1e-3) / 1e12 if ms_dfs > 0 else 0.0
+    return {"kernel": "k_dfs", "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+            "traffic": traffic_for("k_dfs", key), "avg_ms": ms_dfs,
+            "algorithmic": "6 FP64 flops per tree edge (complex product) + 8 per leaf"}
+
+
 def pathsum_roofline(s0, avg, name):
     ms_dfs, ms_fwd = avg("ms_dfs"), avg("ms_forward")
     key = f"{name}/pathsum/{s0['fwd_layer']}-{s0['bwd_layer']}"
     if ms_dfs >= ms_fwd and ms_dfs > 0:
-        flops = 6.0 * s0["dfs_edges"] + 8.0 * s0["dfs_leaves"]
-        achieved = flops / (ms_dfs * 1e-3) / 1e12
-        return {"kernel": "k_dfs", "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                "traffic": traffic_for("k_dfs", key), "avg_ms": ms_dfs,
-                "algorithmic": "6 FP64 flops per tree edge (complex product) + 8 per leaf"}
+        return dfs_roofline(s0, avg, key)
     # forward frontier: per produced state one 16 B write plus one 16 B read of
     # each predecessor (counted once: 32 B per state)
     byts = 32.0 * s0["bfs_states"]
@@ -347,6 +352,9 @@ def run_variant(lofp, workloads, torch, dev, stream, name, method, steps=5, fwd=
         out["edges_per_s"] = s0["dfs_edges"] / (ms * 1e-3)
         out["bfs_states_per_s"] = s0["bfs_states"] / (ms * 1e-3)
         out["roofline"] = pathsum_roofline(s0, avg, name)
+        if s0["dfs_levels"] > 0:
+            # the depth-first kernel beside the dominant one
+            out["roofline_dfs"] = dfs_roofline(s0, avg, f"{name}/pathsum/{s0['fwd_layer']}-{s0['bwd_layer']}")
     return out
 
 
