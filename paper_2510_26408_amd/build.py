@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "liblofp.so")
-SOURCES = ["tables.hip", "plan.hip", "frontier.hip", "dfs.hip", "reduce.hip", "contract.hip", "keys.hip", "pool.cpp", "api.cpp", "serve.cpp", "graph.cpp", "noalloc.hip"]
+SOURCES = ["tables.hip", "plan.hip", "frontier.hip", "dfs.hip", "reduce.hip", "contract.hip", "join.hip", "keys.hip", "pool.cpp", "api.cpp", "serve.cpp", "graph.cpp", "noalloc.hip"]
 
 
 def hipcc() -> str:

@@ -34,27 +34,6 @@
 
 namespace lofp {
 
-// exact small-integer quotient via the float reciprocal (values < 2^22)
-__device__ __forceinline__ int qdiv(int a, int d, float inv)
-{
-    int q = __float2int_rz(__int2float_rn(a) * inv);
-    int r = a - q * d;
-    if (r < 0) { --q; r += d; }
-    if (r >= d) { ++q; }
-    return q;
-}
-
-// a table in global memory, read as pairs of doubles (lets the compiler use
-// global loads with a 32-bit offset rather than flat ones)
-typedef const double __attribute__((address_space(1))) gdouble;
-
-// A result that could not be computed (a state larger than its buffers):
-// NaN in both parts, so no caller takes it for an amplitude.
-__device__ __forceinline__ double2 nan2()
-{
-    return make_double2(__builtin_nan(""), __builtin_nan(""));
-}
-
 // A job whose state does not fit its buffers stops (whole block, uniform
 // condition): the launch's overflow flag, the job's own flag and a NaN in
 // its amplitude record it.
@@ -750,121 +729,6 @@ hipError_t launch_multi_sizes(int count, const ContractJob *jobs, int *mx, hipSt
 {
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(k_multi_sizes, dim3((count + 63) / 64), dim3(64), 0, stream, count, jobs, mx);
-    return hipGetLastError();
-}
-
-// Join of a split contraction, one block per pattern: the sum over the
-// pattern's own box of crossing versions of TOP(versions) * BOT(versions),
-// each state addressed by value through its key's interval layout.  Both
-// states list the crossing versions in the same order, so neighbouring lanes
-// read neighbouring entries of both.
-// NS: the number of crossing versions (a compile-time count, so the set-up
-// loads are all issued together and the digit loop has no branches).  Two
-// waves per pattern: the kernel's time is the longest box's gather chain.
-constexpr int kJoinBlock = 128;
-template <int NS>
-__global__ __launch_bounds__(kJoinBlock) void k_join(JoinArgs g)
-{
-    if (g.split_flag && !*g.split_flag) return;   // contracted per pattern instead
-    const int p = blockIdx.x;
-    const int nc = g.m - 1, span = (g.D + 1) * nc;
-    if (g.infeasible[p]) {
-        if (threadIdx.x == 0) g.out[p] = make_double2(0.0, 0.0);
-        return;
-    }
-    const int tk = g.slot_key[key_slot_index(0, g.stride, g.slot[p])];
-    const int bk = g.slot_key[key_slot_index(1, g.stride, g.slot[g.B + p])];
-    const int16_t *plo = g.lo + (int64_t)p * span, *phi = g.hi + (int64_t)p * span;
-    const int16_t *tlo = g.tlo + (int64_t)tk * span, *thi = g.thi + (int64_t)tk * span;
-    const int16_t *blo = g.blo + (int64_t)bk * span, *bhi = g.bhi + (int64_t)bk * span;
-    // per crossing variable (both states in the top order): pattern box,
-    // top stride/offset, bottom stride/offset
-    int pl[NS > 0 ? NS : 1], ph[NS > 0 ? NS : 1], tl[NS > 0 ? NS : 1], th[NS > 0 ? NS : 1];
-    int bl[NS > 0 ? NS : 1], bh[NS > 0 ? NS : 1];
-#pragma unroll
-    for (int q = 0; q < NS; ++q) {
-        const int i = g.cidx[q];
-        pl[q] = plo[i]; ph[q] = phi[i]; tl[q] = tlo[i]; th[q] = thi[i]; bl[q] = blo[i]; bh[q] = bhi[i];
-    }
-    int pstr[NS > 0 ? NS : 1], toff[NS > 0 ? NS : 1], tstr[NS > 0 ? NS : 1], boff[NS > 0 ? NS : 1];
-    int bstr[NS > 0 ? NS : 1];
-    float pinv[NS > 0 ? NS : 1];
-    int box = 1;
-    int64_t ts = 1, bs = 1;
-    bool fits = !g.top_ovf[tk] && !g.bot_ovf[bk];
-#pragma unroll
-    for (int q = 0; q < NS; ++q) {
-        pstr[q] = box;
-        pinv[q] = 1.0f / (float)box;
-        toff[q] = pl[q] - tl[q];          // state digit = pattern digit + offset
-        boff[q] = pl[q] - bl[q];
-        tstr[q] = (int)ts;
-        bstr[q] = (int)bs;
-        ts *= th[q] >= tl[q] ? th[q] - tl[q] + 1 : 0;
-        bs *= bh[q] >= bl[q] ? bh[q] - bl[q] + 1 : 0;
-        ts = ts < (1LL << 40) ? ts : (1LL << 40);
-        bs = bs < (1LL << 40) ? bs : (1LL << 40);
-        box *= ph[q] >= pl[q] ? ph[q] - pl[q] + 1 : 0;
-        box = box < (1 << 30) ? box : (1 << 30);
-        // a feasible pattern's box lies inside both keys' boxes (each key's
-        // box is the hull of its members' boxes)
-        fits = fits && (ph[q] < pl[q] || (pl[q] >= tl[q] && ph[q] <= th[q] && pl[q] >= bl[q] && ph[q] <= bh[q]));
-    }
-    // both states must be as large as their keys' boxes say
-    fits = fits && ts <= g.state_cap && bs <= g.state_cap;
-    if (!fits) {
-        if (threadIdx.x == 0) g.out[p] = nan2();
-        return;
-    }
-    const gdouble *TS = (const gdouble *)(g.top_state + (int64_t)tk * g.state_cap);
-    const gdouble *BS_ = (const gdouble *)(g.bot_state + (int64_t)bk * g.state_cap);
-    CSum sr{0.0, 0.0}, si{0.0, 0.0};
-#pragma unroll 4
-    for (int e = threadIdx.x; e < box; e += kJoinBlock) {
-        int rem = e, ti = 0, bi = 0;
-#pragma unroll
-        for (int q = NS - 1; q >= 0; --q) {
-            const int d = q > 0 ? qdiv(rem, pstr[q], pinv[q]) : rem;
-            rem -= d * pstr[q];
-            ti += (d + toff[q]) * tstr[q];
-            bi += (d + boff[q]) * bstr[q];
-        }
-        const double2 c = cmul(make_double2(TS[2 * ti], TS[2 * ti + 1]), make_double2(BS_[2 * bi], BS_[2 * bi + 1]));
-        csum_add(sr, c.x);
-        csum_add(si, c.y);
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        CSum b{__shfl_xor(sr.s, off, 64), __shfl_xor(sr.c, off, 64)};
-        CSum c{__shfl_xor(si.s, off, 64), __shfl_xor(si.c, off, 64)};
-        if (threadIdx.x & off) { CSum t = sr; sr = b; b = t; t = si; si = c; c = t; }
-        csum_merge(sr, b);
-        csum_merge(si, c);
-    }
-    // the waves' partial sums, merged in wave order
-    __shared__ CSum part[2][kJoinBlock / 64];
-    if ((threadIdx.x & 63) == 0) { part[0][threadIdx.x >> 6] = sr; part[1][threadIdx.x >> 6] = si; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        CSum a = part[0][0], b = part[1][0];
-        for (int w = 1; w < kJoinBlock / 64; ++w) { csum_merge(a, part[0][w]); csum_merge(b, part[1][w]); }
-        g.out[p] = make_double2(a.s + a.c, b.s + b.c);
-    }
-}
-
-template <int... N>
-static void launch_join_ns(const JoinArgs &a, hipStream_t stream, std::integer_sequence<int, N...>)
-{
-    using K = void (*)(JoinArgs);
-    static const K table[] = {k_join<N>...};
-    hipLaunchKernelGGL(table[a.nshared], dim3(a.B), dim3(kJoinBlock), 0, stream, a);
-}
-
-hipError_t launch_join(const JoinArgs &a, hipStream_t stream)
-{
-    if (a.B == 0) return hipSuccess;
-    if (a.nshared < 0 || a.nshared > kMaxActive) return hipErrorInvalidValue;
-    launch_join_ns(a, stream, std::make_integer_sequence<int, kMaxActive + 1>{});
     return hipGetLastError();
 }
 

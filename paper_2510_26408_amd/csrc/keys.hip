@@ -23,6 +23,30 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
+// The hull entries a half's keys use: every time of the cuts its program
+// reads, its own cuts and the two crossing ones (top: cuts 0..rs+1, bottom:
+// cuts rs..m-2).  Entries outside stay empty in every slot.
+struct HullRegion {
+    int r0, w, n;
+    float winv;
+};
+__device__ __forceinline__ HullRegion hull_region(const KeyArgs &a, int half)
+{
+    const int nc = a.m - 1;
+    HullRegion h;
+    h.r0 = half ? a.rs : 0;
+    h.w = half ? nc - a.rs : a.rs + 2;
+    h.n = (a.span / nc) * h.w;
+    h.winv = 1.0f / (float)h.w;
+    return h;
+}
+// Entry j (0 <= j < n) of the region as an index into a hull row.
+__device__ __forceinline__ int hull_at(const HullRegion &h, int nc, int j)
+{
+    const int t = qdiv(j, h.w, h.winv);
+    return t * nc + h.r0 + (j - t * h.w);
+}
+
 // One wave per (pattern, half); lane i holds row entry i (m <= 32).  The
 // hash is the XOR of per-entry mixes (order-free, so the same on every run).
 // A slot holds the row's 32-bit hash above p (right photon number) or p + B
@@ -83,7 +107,9 @@ __global__ __launch_bounds__(256) void k_key_insert(KeyArgs a)
     if (a.infeasible[p]) return;
     // the slot's hull of its feasible members' intervals
     const int64_t row = key_hull_row(half, a.stride, j, a.span);
-    for (int i = lane; i < a.span; i += 64) {
+    const HullRegion hr = hull_region(a, half);
+    for (int e = lane; e < hr.n; e += 64) {
+        const int i = hull_at(hr, a.m - 1, e);
         atomicMin(&a.hlo[row + i], (int)a.lo[(int64_t)p * a.span + i]);
         atomicMax(&a.hhi[row + i], (int)a.hi[(int64_t)p * a.span + i]);
     }
@@ -154,9 +180,13 @@ __global__ __launch_bounds__(256) void k_key_jobs(KeyArgs a, int ntop, int nbot,
     // (the reduction consumes every lane's loads before the hull is reset)
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) work += __shfl_xor(work, o, 64);
-    for (int i = lane; i < a.span; i += 64) {
-        a.hlo[srow + i] = kHullEmptyLo;
-        a.hhi[srow + i] = kHullEmptyHi;
+    {
+        const HullRegion hr = hull_region(a, half);
+        for (int e = lane; e < hr.n; e += 64) {
+            const int i = hull_at(hr, a.m - 1, e);
+            a.hlo[srow + i] = kHullEmptyLo;
+            a.hhi[srow + i] = kHullEmptyHi;
+        }
     }
     if (lane != 0) return;
     unsigned long long *tab = a.table + key_slot_index(half, a.stride, 0);
@@ -187,9 +217,13 @@ __global__ __launch_bounds__(256) void k_key_reset(KeyArgs a, int ntop, int nbot
     const int half = w >= ntop, k = half ? w - ntop : w;
     const int sl = key_slot_of(a, half, k);
     const int64_t srow = key_hull_row(half, a.stride, sl, a.span);
-    for (int i = lane; i < a.span; i += 64) {
-        a.hlo[srow + i] = kHullEmptyLo;
-        a.hhi[srow + i] = kHullEmptyHi;
+    {
+        const HullRegion hr = hull_region(a, half);
+        for (int e = lane; e < hr.n; e += 64) {
+            const int i = hull_at(hr, a.m - 1, e);
+            a.hlo[srow + i] = kHullEmptyLo;
+            a.hhi[srow + i] = kHullEmptyHi;
+        }
     }
     if (lane == 0) a.table[key_slot_index(half, a.stride, sl)] = kKeyEmpty;
 }
@@ -233,7 +267,9 @@ __global__ __launch_bounds__(256) void k_key_jobs_dev(KeyArgs a, ContractJob top
     const int64_t srow = key_hull_row(half, a.stride, sl, a.span);
     if (!split) {
         // one contraction per pattern: only empty the slot
-        for (int i = lane; i < a.span; i += 64) {
+        const HullRegion hr = hull_region(a, half);
+        for (int e = lane; e < hr.n; e += 64) {
+            const int i = hull_at(hr, a.m - 1, e);
             a.hlo[srow + i] = kHullEmptyLo;
             a.hhi[srow + i] = kHullEmptyHi;
         }
@@ -268,9 +304,13 @@ __global__ __launch_bounds__(256) void k_key_jobs_dev(KeyArgs a, ContractJob top
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) work += __shfl_xor(work, o, 64);
-    for (int i = lane; i < a.span; i += 64) {
-        a.hlo[srow + i] = kHullEmptyLo;
-        a.hhi[srow + i] = kHullEmptyHi;
+    {
+        const HullRegion hr = hull_region(a, half);
+        for (int e = lane; e < hr.n; e += 64) {
+            const int i = hull_at(hr, a.m - 1, e);
+            a.hlo[srow + i] = kHullEmptyLo;
+            a.hhi[srow + i] = kHullEmptyHi;
+        }
     }
     if (lane != 0) return;
     unsigned long long *tab = a.table + key_slot_index(half, a.stride, 0);

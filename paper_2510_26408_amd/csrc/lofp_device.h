@@ -37,6 +37,27 @@ __device__ __forceinline__ void csum_merge(CSum &a, const CSum &b)
     a.c += b.c;
 }
 
+// exact small-integer quotient via the float reciprocal (values < 2^22)
+__device__ __forceinline__ int qdiv(int a, int d, float inv)
+{
+    int q = __float2int_rz(__int2float_rn(a) * inv);
+    int r = a - q * d;
+    if (r < 0) { --q; r += d; }
+    if (r >= d) { ++q; }
+    return q;
+}
+
+// a table in global memory, read as pairs of doubles (lets the compiler use
+// global loads with a 32-bit offset rather than flat ones)
+typedef const double __attribute__((address_space(1))) gdouble;
+
+// A result that could not be computed (a state larger than its buffers):
+// NaN in both parts, so no caller takes it for an amplitude.
+__device__ __forceinline__ double2 nan2()
+{
+    return make_double2(__builtin_nan(""), __builtin_nan(""));
+}
+
 // Find the pattern owning flattened index k: largest p with off[p] <= k.
 __device__ __forceinline__ int find_pattern(const int64_t *off, int B, int64_t k)
 {

@@ -16,7 +16,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2510_26408_amd", "csrc")
 SOURCES = ["api.cpp", "serve.cpp", "pool.cpp", "graph.cpp", "noalloc.hip", "tables.hip", "plan.hip", "frontier.hip",
-           "dfs.hip", "reduce.hip", "contract.hip", "keys.hip"]
+           "dfs.hip", "reduce.hip", "contract.hip", "join.hip", "keys.hip"]
 
 pytestmark = pytest.mark.slow
 
