@@ -737,6 +737,25 @@ def test_small_batches_split_for_latency():
         c1.amplitudes(w1.S, w1.Ts[:1], lofp.make_opts(method=lofp.METHOD_CONTRACT, split=3))
 
 
+@pytest.mark.parametrize("m,D,seed", [(6, 2, 21), (7, 5, 22), (9, 4, 23), (12, 7, 24), (14, 6, 25), (20, 3, 26)])
+def test_forced_split_join_many_shapes(m, D, seed):
+    """The split contraction forced on brickwork circuits of several widths
+    and depths: the join sums over one to six crossing versions and boxes
+    from a single entry to several passes of a wave.  Every pattern agrees
+    with one contraction per pattern, a sample with the oracle."""
+    rng = np.random.default_rng(seed)
+    layers = workloads.random_brickwork(m, D, rng)
+    S = workloads.photons_even_modes(m)
+    Ts = np.stack([workloads.sample_collision_free(rng, S, D) for _ in range(48)])
+    c = lofp.Circuit(m, layers)
+    st = lofp.Stats()
+    got = c.amplitudes(S, Ts, lofp.make_opts(method=lofp.METHOD_CONTRACT, split=lofp.SPLIT_ALWAYS), st)
+    assert st.split_top_keys > 0 and st.split_bottom_keys > 0
+    ref = c.amplitudes(S, Ts, NEVER_SPLIT)
+    check(got, ref, 1e-14)
+    check(got[:8], oracle_amps(m, S, Ts[:8], layers))
+
+
 def test_c5_full_batch_split_for_parallelism():
     """The 32-mode, depth-6 workload at its full 512 patterns, in the launch
     the benchmark times (the batch split into top and bottom halves for
