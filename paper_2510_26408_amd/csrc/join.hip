@@ -12,9 +12,10 @@ namespace lofp {
 // each state addressed by value through its key's interval layout.  Both
 // states list the crossing versions in the same order, so neighbouring lanes
 // read neighbouring entries of both.  Boxes hold hundreds to a few thousand
-// entries (c2: 580 on average); the reads of the two states, written by other
-// XCDs in the contraction kernel, mostly miss L2 and bound the kernel, so the
-// per-entry index work is kept small (see the loop).
+// entries (580 on average for 16 modes, 8 photons, depth 8); the reads of
+// the two states, written by other XCDs in the contraction kernel, mostly
+// miss L2 and bound the kernel, so the per-entry index work is kept small
+// (see the loop).
 // NS: the number of crossing versions (a compile-time count, so the set-up
 // loads are all issued together and the digit loops have no branches).
 constexpr int kJoinWaves = 4;
