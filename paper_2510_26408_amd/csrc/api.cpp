@@ -898,13 +898,16 @@ lofp_status run_contract_split_dev(lofp_circuit_s &c, const int32_t *S, int n, i
         fin_cap = std::min(fin_cap, state_limit);
         pp_states = std::min(pp_states, state_limit);
     }
-    // the per-pattern contraction (runs only if the device does not split)
+    // the per-pattern contraction (runs only if the device does not split;
+    // a configuration that splits every batch never runs it, so it is not
+    // launched: its B blocks would only return)
+    const bool always_split = cfg.small_min <= 1 && cfg.small_max == std::numeric_limits<int>::max();
     ContractArgs pa{};
     pa.B = B; pa.m = m; pa.n = n; pa.D = c.D;
     pa.nvars = c.nvars;
     pa.max_states = pp_states;
     const bool pp_lds = contract_lds_bytes(pa, true) <= 64 * 1024;
-    const size_t pp_ws = pp_lds ? 0 : (size_t)B * 2 * pp_states * sizeof(double2);
+    const size_t pp_ws = pp_lds || always_split ? 0 : (size_t)B * 2 * pp_states * sizeof(double2);
     if (pp_ws > ((size_t)1 << 30)) return LOFP_OK;
     used = true;
     if (!sp->on_device) {
@@ -1011,12 +1014,14 @@ lofp_status run_contract_split_dev(lofp_circuit_s &c, const int32_t *S, int n, i
     pa.overflow = reinterpret_cast<int32_t *>(ctr + 4);
     pa.stats = st != nullptr && count_work;
     pa.skip = ka.ctl;
-    if (!pp_lds) {
-        HIPCHK(ensure(c.d_ws2, pp_ws));
-        pa.ws = c.d_ws2.as<double2>();
-        pa.lds_states = std::min(contract_lds_room(pa.nvars, pa.m), pp_states);
+    if (!always_split) {
+        if (!pp_lds) {
+            HIPCHK(ensure(c.d_ws2, pp_ws));
+            pa.ws = c.d_ws2.as<double2>();
+            pa.lds_states = std::min(contract_lds_room(pa.nvars, pa.m), pp_states);
+        }
+        HIPCHK(launch_contract(pa, s));
     }
-    HIPCHK(launch_contract(pa, s));
     tm.mark();
     JoinArgs ja{};
     ja.B = B; ja.m = m; ja.n = n; ja.D = c.D;
@@ -1071,7 +1076,12 @@ lofp_status tune_contract(lofp_circuit_s &c, const int32_t *S, int n, int B, con
             SplitCfg k = d;
             k.rs = d.rs + drs;
             k.lds_kb = kb;
-            if (k.rs >= 0 && k.rs <= c.nc - 2) cand.push_back(k);
+            if (k.rs < 0 || k.rs > c.nc - 2) continue;
+            cand.push_back(k);
+            // the same, split whatever the sharing: no per-pattern launch
+            k.small_min = 1;
+            k.small_max = std::numeric_limits<int>::max();
+            cand.push_back(k);
         }
     if (B < d.small_max && B < 256) {
         // a small batch: split or not, whatever the circuit's default
